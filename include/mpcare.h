@@ -1,0 +1,252 @@
+/*
+ * mpcare.h - C ABI of the MI355X (gfx950) mixed-precision Newton refinement
+ * library for large sparse continuous-time algebraic Riccati equations
+ *
+ *      A^T X + X A - X B B^T X + C^T C = 0,     X ~ Z Z^T          (eq. (1.1))
+ *
+ * with A sparse (n x n, CSR), B dense n x m, C dense p x n, m, p << n
+ * (problem statement, Sec. 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * All array arguments are DEVICE pointers (memory of the device the
+ *    context was created on) unless the comment says "host".  The caller owns
+ *    every input and output buffer; the library never frees or keeps them.
+ *    The library owns only its internal workspace (allocated lazily, cached in
+ *    the context, released by care_ctx_destroy).
+ *  * Dense matrices are column-major FP64 with a leading dimension >= n.
+ *    C is passed as stored by the problem statement, p x n ROW-major, which is
+ *    the same bytes as C^T column-major n x p with leading dimension n.
+ *  * Work is ordered on the context's HIP stream (given at creation).  Every
+ *    call returns after its device work has completed, because the method
+ *    takes host-side decisions (convergence checks, eigenvalue splits).
+ *  * Every function returns care_status: 0 = OK, > 0 = warning (outputs are
+ *    valid), < 0 = error.  On an error the outputs are unspecified, except for
+ *    CARE_ERR_CAPACITY, where *r_out (or *rp/*rm) holds the number of columns
+ *    that would have been needed.  Argument checks happen before any device
+ *    work.  care_last_error() returns a message for the calling thread.
+ *  * No C++ exception crosses this interface.
+ */
+#ifndef MPCARE_H
+#define MPCARE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t care_status;
+
+enum {
+  CARE_OK = 0,
+  CARE_WARN_STAGNATED = 1,      /* refinement stopped on the stagnation test (Sec. 5) */
+  CARE_WARN_MAXIT = 2,          /* k_max / j_max / Krylov iteration cap reached      */
+  CARE_ERR_ARG = -1,            /* invalid argument (message via care_last_error)    */
+  CARE_ERR_CAPACITY = -2,       /* output too small; required size reported         */
+  CARE_ERR_UNSTABLE = -3,       /* iteration diverged (A or A_k not stable)         */
+  CARE_ERR_BREAKDOWN = -4,      /* Krylov breakdown that could not be recovered      */
+  CARE_ERR_NONFINITE = -5,      /* NaN/Inf met in inputs or iterates                 */
+  CARE_ERR_DEVICE = -6,         /* HIP / rocBLAS / rocSOLVER runtime error           */
+  CARE_ERR_NOMEM = -7,          /* device allocation failed                          */
+  CARE_ERR_NOT_IMPLEMENTED = -8
+};
+
+/* Inner precision u_s of the initial solve and of the inner Lyapunov
+ * solves (Sec. 2, precision levels; hierarchy u_s >= u >= u_r, u_c).
+ * Residual evaluation, storage and update are always FP64 (u = u_r = u_c,
+ * as in the experiments of Sec. 5). */
+enum {
+  CARE_FP64 = 0,                /* u_s = FP64 (the all-double baseline)             */
+  CARE_FP32 = 1,                /* u_s = FP32                                       */
+  CARE_BF16_SPMM = 2            /* FP32 inner solves whose sparse products read the
+                                   off-diagonal values of A in bfloat16            */
+};
+
+/* CSR of A itself (NOT of A^T); 0-based int32 indices, column indices sorted
+ * within each row, no duplicates.  row_ptr has n+1 entries.  Device memory. */
+typedef struct {
+  int64_t n, nnz;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const double* val;
+} care_csr;
+
+/* ADI shift p = re + i im.  Re p < 0.  Complex shifts are given as adjacent
+ * conjugate pairs (p, conj p) with Im p > 0 first.  Shift arrays are HOST
+ * memory; shifts are cycled when more ADI steps than shifts are needed. */
+typedef struct {
+  double re, im;
+} care_shift;
+
+typedef struct care_ctx care_ctx;
+
+/* Solver options; care_opts_default fills the values used in Sec. 5. */
+typedef struct {
+  int32_t inner_prec;     /* CARE_FP64 | CARE_FP32 | CARE_BF16_SPMM                     */
+  int32_t k_max;          /* refinement steps of Framework 1 (20)                     */
+  int32_t k0_max;         /* Newton steps of the initial NLR-ADI solve (20)           */
+  int32_t j_max;          /* ADI steps per Lyapunov solve (50)                        */
+  double eta_r_rel;       /* Alg. 1 threshold, relative to max|lambda(H)| (1e-4)      */
+  double eta_s_rel;       /* Alg. 2 threshold, relative to max|lambda(P)| (10 u_fp64)  */
+  double tau_L;           /* inner LR-ADI stop ||W^T W||_F <= tau_L ||W0^T W0||_F;
+                             <= 0 selects 1e-12 (FP64) / 1e-5 (FP32) / 1e-2 (BF16)    */
+  double tau_0;           /* initial NLR-ADI stop on the relative Riccati residual;
+                             <= 0 selects max(tol, 10 tau_L)                          */
+  double stagnation;      /* stop when ||R_{k+1}|| / ||R_k|| > stagnation (0.999)     */
+  int32_t krylov_maxit;   /* BiCGStab iteration cap per shifted solve (4000)          */
+  double krylov_tol;      /* per-column relative residual; <= 0 selects 1e-5 for
+                             FP32/BF16 and 1e-10 for FP64                             */
+  int32_t check_every;    /* host convergence poll period of the Krylov loop (8)      */
+  int32_t penzl_l0;       /* auto shifts: number of shifts (16)                       */
+  int32_t penzl_kp;       /* auto shifts: Arnoldi steps on A^T (20)                   */
+  int32_t penzl_km;       /* auto shifts: Arnoldi steps on A^-T (10)                  */
+  int32_t profile;        /* 1: time every sparse-product launch with HIP events      */
+  const double* Z_init;   /* optional FP64 start factor Z_1 (device, n x r_init);
+                             skips the initial NLR-ADI solve (resume)               */
+  int64_t ldz_init;
+  int32_t r_init;
+} care_opts;
+
+/* Statistics written by the solvers (host struct). */
+typedef struct {
+  int32_t iter0_outer, iter0_inner;   /* initial solve "outer(inner)" (Sec. 5 tables)  */
+  int32_t iter_outer, iter_inner;     /* refinement "outer(inner)"                     */
+  int32_t rank;                       /* columns of the returned factor               */
+  int32_t stagnated;
+  double res_rel;                     /* ||R(Z)||_F / ||C^T C||_F of the result (FP64)  */
+  double res_paper;                   /* the paper's normalised residual "Res" (Sec. 5) */
+  double eta_n;                       /* ||P-||_F / ||P||_F of the last Alg. 2 (Lemma 1) */
+  double t_total, t_stage0, t_refine, t_setup;   /* seconds, host wall clock          */
+  int64_t spmm_calls;                 /* sparse product launches                       */
+  double spmm_bytes;                  /* algorithmic bytes of those launches           */
+  double t_spmm;                      /* summed kernel time (profile = 1), seconds      */
+  int64_t krylov_iters;               /* BiCGStab iterations summed over columns' solves */
+  int32_t hist_len;                   /* entries of res_hist used                      */
+  double res_hist[48];                /* relative residual after each outer step      */
+} care_stats;
+
+/* ---------------------------------------------------------------------- */
+/* Context                                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Create a context on `device` that orders all work on `stream` (a
+ * hipStream_t passed as void*; NULL = the default stream).  *ctx receives a
+ * handle owned by the caller, released with care_ctx_destroy. */
+care_status care_ctx_create(care_ctx** ctx, int32_t device, void* stream);
+void care_ctx_destroy(care_ctx* ctx);
+
+/* Default options for inner precision `inner_prec` (values of Sec. 5:
+ * eta_r = 1e-4 max|lambda(H)|, eta_s = 10 u max|lambda(P)|, tau_L = 1e-12 /
+ * 1e-5, k_max = 20, j_max = 50). */
+void care_opts_default(care_opts* opts, int32_t inner_prec);
+
+/* Message describing the last error of the calling thread ("" if none). */
+const char* care_last_error(void);
+
+/* Library version string (static storage). */
+const char* care_version(void);
+
+/* ---------------------------------------------------------------------- */
+/* Building blocks of the LR-ADI inner loop (Sec. 4)                        */
+/* ---------------------------------------------------------------------- */
+
+/* Shifted sparse product Y = (A^T + p I) X in precision `prec` (the
+ * operator M_alpha of the SMW formula, Sec. 4).  X: n x k column-major FP64
+ * (ldx >= n); Y: n x k (ldy >= n).  For a complex shift, X and Y hold k
+ * complex columns as [Re(X) | Im(X)] (2k real columns).  X is rounded to
+ * the working precision first and Y is returned in FP64.  k = 0 is a no-op. */
+care_status care_spmm(care_ctx* ctx, const care_csr* A, int32_t prec, care_shift p,
+                      const double* X, int64_t ldx, int32_t k, double* Y, int64_t ldy);
+
+/* Shifted block solve (A_k^T + p I) V = W with A_k = A - B K^T, by the
+ * Sherman-Morrison-Woodbury formula of Sec. 4: solve (A^T + p I)[Vh, S] = [W, K]
+ * with column-batched BiCGStab in precision `prec`, then
+ * V = Vh + S (I_m - B^T S)^{-1} B^T Vh.  B, K: n x m column-major (ldb, ldk
+ * >= n; K = NULL or m = 0 means A_k = A).  W, V: n x w (complex shifts: [Re|Im]
+ * layout as in care_spmm for V; W is real).  tol <= 0 / maxit <= 0 select the
+ * precision's defaults.  *iters (host, may be NULL) receives the largest
+ * per-column iteration count.  Returns CARE_WARN_MAXIT if a column did not
+ * reach tol. */
+care_status care_shifted_solve(care_ctx* ctx, const care_csr* A, const double* B, int64_t ldb,
+                               const double* K, int64_t ldk, int32_t m, care_shift p,
+                               const double* W, int64_t ldw, int32_t w, int32_t prec,
+                               double tol, int32_t maxit, double* V, int64_t ldv, int32_t* iters);
+
+/* Gram product C = X^T Y of tall-skinny FP64 panels (FP64 matrix cores),
+ * the Gram step of the thin QR of F in Algorithm 1 and of G in Algorithm 2.
+ * X: n x a (ldx >= n), Y: n x b (ldy >= n), C: a x b (ldc >= a).  Summation
+ * over row blocks runs in a fixed order (run-to-run reproducible). */
+care_status care_gram(care_ctx* ctx, int64_t n, const double* X, int64_t ldx, int32_t a, const double* Y,
+                      int64_t ldy, int32_t b, double* C, int64_t ldc);
+
+/* Tall-skinny product Y = alpha X S + beta Y (FP64 matrix cores): X n x q
+ * (ldx >= n), S q x k (lds >= q), Y n x k (ldy >= n); beta = 0 does not read
+ * Y.  Forms U = F T^{-1}, C+- = U Q+- |Lambda+-|^(1/2) and Z = V Theta+
+ * Sigma+^(1/2) in Algorithms 1 and 2. */
+care_status care_tsgemm(care_ctx* ctx, int64_t n, const double* X, int64_t ldx, int32_t q, const double* S,
+                        int64_t lds, int32_t k, double alpha, double beta, double* Y, int64_t ldy);
+
+/* ---------------------------------------------------------------------- */
+/* The four solver entry points                                             */
+/* ---------------------------------------------------------------------- */
+
+/* LR-ADI for the Lyapunov equation  A_k^T X + X A_k + W W^T = 0,
+ * A_k = A - B K^T (B, K: n x m; B = K = NULL or m = 0 means A_k = A), the
+ * inner solver of Sec. 4 (residual-based LR-ADI; real shifts and
+ * complex-conjugate pairs).  W: n x w.  Runs in opts->inner_prec until
+ * ||W_j^T W_j||_F <= tol ||W^T W||_F (tol <= 0 selects opts' tau_L) or
+ * opts->j_max steps.  Output Z: n x (*r_out) FP64, ldz >= n, capacity rmax
+ * columns; block j of w columns keeps the column order of W (a complex pair
+ * gives two blocks).  stats may be NULL. */
+care_status lyap_lradi(care_ctx* ctx, const care_csr* A, const double* B, const double* K, int32_t m,
+                       const double* W, int64_t ldw, int32_t w, const care_shift* shifts,
+                       int32_t nshifts, double tol, const care_opts* opts, double* Z, int64_t ldz,
+                       int32_t rmax, int32_t* r_out, care_stats* stats);
+
+/* Algorithm 1 (Residual Factor Decomposition) in FP64:
+ * R(Z Z^T) = C+ C+^T - C- C-^T with thresholds +-eta_r, eta_r = eta_r_rel
+ * max|lambda(H)| (eta_r_rel = 0: no truncation).  Z: n x r (ldz >= n).
+ * Cp: n x (*rp), Cm: n x (*rm), leading dimension ldc >= n, each with
+ * capacity `cap` columns.  *res_fro (host) = ||R(Z Z^T)||_F = ||H||_F,
+ * taken from the eigenvalues of H before truncation. */
+care_status care_residual_factor(care_ctx* ctx, const care_csr* A, const double* B, int32_t m,
+                                 const double* C, int32_t p, const double* Z, int64_t ldz, int32_t r,
+                                 double eta_r_rel, double* Cp, int32_t* rp, double* Cm, int32_t* rm,
+                                 int64_t ldc, int32_t cap, double* res_fro);
+
+/* Algorithm 2 (Solution Factor Decomposition) for a general signature:
+ * given G (n x s, ldg >= n) and host sign[s] in {+1, -1} (N = diag(sign)),
+ * returns Z (n x *r_out, ldz >= n, capacity cap) with Z Z^T the positive
+ * spectral part of G N G^T above eta_s = eta_s_rel max|lambda(P)|.
+ * sign = all +1 gives plain column compression.  *eta_n (host, may be
+ * NULL) receives ||P-||_F / ||P||_F. */
+care_status lowrank_truncate(care_ctx* ctx, int64_t n, const double* G, int64_t ldg, int32_t s, const int8_t* sign,
+                             double eta_s_rel, double* Z, int64_t ldz, int32_t cap, int32_t* r_out,
+                             double* eta_n);
+
+/* Framework 1 (Factorization-based Mixed Precision Newton Iterative
+ * Refinement): initial NLR-ADI solve in opts->inner_prec (Sec. 4), then
+ * FP64 Algorithm 1, inner LR-ADI corrections on [C+, C-] in inner_prec and
+ * FP64 Algorithm 2, until ||R||_F <= tol ||C^T C||_F.  B: n x m, C: p x n
+ * row-major.  shifts: host array of nshifts shifts; nshifts = 0 computes
+ * them with the Penzl heuristic (Ritz values of A^T and A^-T).  Z: n x *r_out
+ * FP64 (ldz >= n, capacity rmax).  Warnings: CARE_WARN_STAGNATED,
+ * CARE_WARN_MAXIT (Z holds the best factor so far). */
+care_status care_solve(care_ctx* ctx, const care_csr* A, const double* B, int32_t m, const double* C,
+                       int32_t p, double tol, const care_shift* shifts, int32_t nshifts,
+                       const care_opts* opts, double* Z, int64_t ldz, int32_t rmax, int32_t* r_out,
+                       care_stats* stats);
+
+/* Penzl-type heuristic shifts (the "shifts from Krylov subspaces" of Sec. 5):
+ * Ritz values of kp Arnoldi steps with A^T and km steps with A^-T (FP64),
+ * then the greedy min-max choice of l0 shifts.  shifts_out: HOST array with
+ * room for l0 + 1 entries (a conjugate pair is never split); *count receives
+ * the number written. */
+care_status care_penzl_shifts(care_ctx* ctx, const care_csr* A, int32_t l0, int32_t kp, int32_t km,
+                              care_shift* shifts_out, int32_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPCARE_H */

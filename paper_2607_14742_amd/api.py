@@ -1,0 +1,262 @@
+"""Python binding of libmpcare (argument marshalling only).
+
+Dense matrices are torch float64 CUDA tensors of shape (rows, cols) in
+COLUMN-major storage (stride (1, ld)); `colmajor()` converts.  Sparse A is a
+`DeviceCSR` (CSR of A itself, int32 indices, float64 values).  Every call goes
+through the C ABI of include/mpcare.h; nothing here computes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import (CARE_BF16_SPMM, CARE_FP32, CARE_FP64, care_csr, care_opts, care_shift,  # noqa: F401
+                   care_stats)
+
+PREC = {"fp64": CARE_FP64, "fp32": CARE_FP32, "bf16": CARE_BF16_SPMM,
+        CARE_FP64: CARE_FP64, CARE_FP32: CARE_FP32, CARE_BF16_SPMM: CARE_BF16_SPMM}
+
+
+class CareError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+        self.name = L.STATUS_NAMES.get(status, str(status))
+
+
+def _lib():
+    return L.load()
+
+
+def _check(st):
+    if st < 0:
+        raise CareError(st, _lib().care_last_error().decode())
+    return st
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def colmajor(t: torch.Tensor) -> torch.Tensor:
+    """Same values, column-major storage (stride (1, rows))."""
+    if t.dim() == 1:
+        t = t.reshape(-1, 1)
+    if t.stride(0) == 1 and t.stride(1) >= max(t.shape[0], 1):
+        return t
+    return t.t().contiguous().t()
+
+
+def tight(t: torch.Tensor) -> torch.Tensor:
+    """Column-major copy with leading dimension exactly rows."""
+    if t.dim() == 1:
+        t = t.reshape(-1, 1)
+    return t.t().contiguous().t()
+
+
+def empty_colmajor(rows, cols, device, dtype=torch.float64):
+    return torch.empty((max(cols, 1), rows), device=device, dtype=dtype).t()[:, :cols]
+
+
+def _ld(t):
+    return max(t.stride(1), t.shape[0], 1) if t.dim() == 2 else max(t.shape[0], 1)
+
+
+class DeviceCSR:
+    """CSR of A on the GPU (the caller's buffers, passed to the ABI as-is)."""
+
+    def __init__(self, row_ptr, col_idx, val, n):
+        self.row_ptr, self.col_idx, self.val, self.n = row_ptr, col_idx, val, int(n)
+        self.nnz = int(col_idx.numel())
+        self._c = care_csr(self.n, self.nnz, row_ptr.data_ptr(), col_idx.data_ptr(), val.data_ptr())
+
+    @classmethod
+    def from_scipy(cls, A, device="cuda"):
+        A = A.tocsr()
+        A.sort_indices()
+        return cls(torch.as_tensor(A.indptr.astype(np.int32), device=device),
+                   torch.as_tensor(A.indices.astype(np.int32), device=device),
+                   torch.as_tensor(A.data.astype(np.float64), device=device), A.shape[0])
+
+    @property
+    def c(self):
+        return C.byref(self._c)
+
+
+class Context:
+    """A library context bound to one device and one HIP stream (torch's
+    current stream by default)."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.device = device
+        self.stream = stream or torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        _check(_lib().care_ctx_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib().care_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def default_opts(prec="fp64", **kw) -> care_opts:
+    o = care_opts()
+    _lib().care_opts_default(C.byref(o), PREC[prec])
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _shift(p) -> care_shift:
+    p = complex(p)
+    return care_shift(p.real, p.imag)
+
+
+def _shift_array(shifts):
+    s = list(shifts)
+    arr = (care_shift * max(len(s), 1))()
+    for i, p in enumerate(s):
+        arr[i] = _shift(p)
+    return arr, len(s)
+
+
+def version():
+    return _lib().care_version().decode()
+
+
+def spmm(ctx: Context, A: DeviceCSR, X: torch.Tensor, shift=0.0, prec="fp64") -> torch.Tensor:
+    """Y = (A^T + p I) X (complex p: X, Y hold [Re | Im] blocks)."""
+    X = colmajor(X)
+    k = X.shape[1] // 2 if complex(shift).imag != 0 else X.shape[1]
+    Y = empty_colmajor(A.n, X.shape[1], X.device)
+    _check(_lib().care_spmm(ctx.h, A.c, PREC[prec], _shift(shift), _ptr(X), _ld(X), k, _ptr(Y), _ld(Y)))
+    return Y
+
+
+def gram(ctx, X, Y):
+    """C = X^T Y (FP64 matrix cores)."""
+    X, Y = colmajor(X), colmajor(Y)
+    C_ = empty_colmajor(X.shape[1], Y.shape[1], X.device)
+    _check(_lib().care_gram(ctx.h, X.shape[0], _ptr(X), _ld(X), X.shape[1], _ptr(Y), _ld(Y), Y.shape[1], _ptr(C_),
+                            _ld(C_)))
+    return C_
+
+
+def tsgemm(ctx, X, S, alpha=1.0, beta=0.0, Y=None):
+    """Y = alpha X S + beta Y (FP64 matrix cores)."""
+    X, S = colmajor(X), colmajor(S)
+    if Y is None:
+        Y = empty_colmajor(X.shape[0], S.shape[1], X.device)
+    else:
+        Y = colmajor(Y)
+    _check(_lib().care_tsgemm(ctx.h, X.shape[0], _ptr(X), _ld(X), X.shape[1], _ptr(S), _ld(S), S.shape[1], alpha,
+                              beta, _ptr(Y), _ld(Y)))
+    return Y
+
+
+def shifted_solve(ctx, A, W, shift, B=None, K=None, prec="fp64", tol=0.0, maxit=0):
+    """V = (A_k^T + p I)^{-1} W with A_k = A - B K^T (SMW); complex p returns [Re | Im]."""
+    W = colmajor(W)
+    w = W.shape[1]
+    m = 0 if K is None else K.shape[1]
+    B = colmajor(B) if B is not None else None
+    K = colmajor(K) if K is not None else None
+    vc = 2 * w if complex(shift).imag != 0 else w
+    V = empty_colmajor(A.n, vc, W.device)
+    it = C.c_int32(0)
+    st = _check(_lib().care_shifted_solve(ctx.h, A.c, _ptr(B), _ld(B) if B is not None else A.n, _ptr(K),
+                                          _ld(K) if K is not None else A.n, m, _shift(shift), _ptr(W), _ld(W), w,
+                                          PREC[prec], tol, maxit, _ptr(V), _ld(V), C.byref(it)))
+    return V, dict(status=st, iters=it.value)
+
+
+def lyap_lradi(ctx, A, W, shifts, B=None, K=None, tol=0.0, opts=None, rmax=None):
+    """LR-ADI for A_k^T X + X A_k + W W^T = 0; returns (Z, stats, status)."""
+    W = colmajor(W)
+    n, w = W.shape
+    m = 0 if K is None else K.shape[1]
+    Bc = tight(B) if B is not None else None            # the ABI takes B, K with ld = n
+    Kc = tight(K) if K is not None else None
+    opts = opts or default_opts()
+    rmax = rmax or w * (opts.j_max + 2)
+    Z = empty_colmajor(n, rmax, W.device)
+    r = C.c_int32(0)
+    stats = care_stats()
+    arr, ns = _shift_array(shifts)
+    st = _check(_lib().lyap_lradi(ctx.h, A.c, _ptr(Bc), _ptr(Kc), m, _ptr(W), _ld(W), w, arr, ns, tol,
+                                  C.byref(opts), _ptr(Z), _ld(Z), rmax, C.byref(r), C.byref(stats)))
+    return Z[:, :r.value], stats.to_dict(), st
+
+
+def residual_factor(ctx, A, B, C_, Z, eta_r_rel=1e-4, cap=None):
+    """Algorithm 1: returns (C+, C-, ||R||_F)."""
+    n = A.n
+    Bc = tight(B) if B is not None and B.shape[1] else None
+    Cr = C_.contiguous()                                    # p x n row-major
+    Z = colmajor(Z)
+    r = Z.shape[1]
+    p = Cr.shape[0]
+    m = 0 if Bc is None else Bc.shape[1]
+    cap = cap or (2 * r + m + p)
+    Cp = empty_colmajor(n, cap, Z.device)
+    Cm = empty_colmajor(n, cap, Z.device)
+    rp, rm, res = C.c_int32(0), C.c_int32(0), C.c_double(0)
+    _check(_lib().care_residual_factor(ctx.h, A.c, _ptr(Bc), m, _ptr(Cr), p, _ptr(Z) if r else None, _ld(Z), r,
+                                       eta_r_rel, _ptr(Cp), C.byref(rp), _ptr(Cm), C.byref(rm), _ld(Cp), cap,
+                                       C.byref(res)))
+    return Cp[:, :rp.value], Cm[:, :rm.value], res.value
+
+
+def lowrank_truncate(ctx, G, sign, eta_s_rel=1.1102230246251565e-15, cap=None):
+    """Algorithm 2 with signature diag(sign): returns (Z, eta_n)."""
+    G = colmajor(G)
+    n, s = G.shape
+    sg = (C.c_int8 * max(s, 1))(*[int(v) for v in sign])
+    cap = cap or max(s, 1)
+    Z = empty_colmajor(n, cap, G.device)
+    r, eta_n = C.c_int32(0), C.c_double(0)
+    _check(_lib().lowrank_truncate(ctx.h, n, _ptr(G), _ld(G), s, sg, eta_s_rel, _ptr(Z), _ld(Z), cap, C.byref(r),
+                                   C.byref(eta_n)))
+    return Z[:, :r.value], eta_n.value
+
+
+def care_solve(ctx, A, B, C_, tol=1e-10, shifts=None, prec="fp32", opts=None, rmax=None, **kw):
+    """Framework 1.  B: n x m, C_: p x n.  Returns (Z, stats dict, status)."""
+    B = tight(B)
+    Cr = C_.contiguous()
+    n, m = B.shape
+    p = Cr.shape[0]
+    opts = opts or default_opts(prec, **kw)
+    rmax = rmax or min(n, 4096)
+    Z = empty_colmajor(n, rmax, B.device)
+    r = C.c_int32(0)
+    stats = care_stats()
+    arr, ns = _shift_array(shifts if shifts is not None else [])
+    st = _check(_lib().care_solve(ctx.h, A.c, _ptr(B), m, _ptr(Cr), p, tol, arr, ns, C.byref(opts), _ptr(Z),
+                                  _ld(Z), rmax, C.byref(r), C.byref(stats)))
+    return Z[:, :r.value], stats.to_dict(), st
+
+
+def penzl_shifts(ctx, A, l0=16, kp=20, km=10):
+    out = (care_shift * (l0 + 1))()
+    cnt = C.c_int32(0)
+    _check(_lib().care_penzl_shifts(ctx.h, A.c, l0, kp, km, out, C.byref(cnt)))
+    return np.array([complex(out[i].re, out[i].im) for i in range(cnt.value)])

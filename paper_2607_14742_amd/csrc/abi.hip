@@ -1,0 +1,393 @@
+// extern "C" entry points: argument checks, context handling, conversion of
+// internal errors to status codes.  No exception crosses this boundary.
+#include <cstring>
+
+#include "care.hpp"
+
+using namespace mpcare;
+
+struct care_ctx {
+  Ctx c;
+};
+
+namespace {
+
+template <typename F>
+care_status guarded(F&& f) {
+  try {
+    set_last_error("");
+    return f();
+  } catch (const CareError& e) {
+    set_last_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return CARE_ERR_NOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return CARE_ERR_DEVICE;
+  } catch (...) {
+    set_last_error("unknown internal error");
+    return CARE_ERR_DEVICE;
+  }
+}
+
+Ctx* unwrap(care_ctx* c) {
+  if (!c) fail(CARE_ERR_ARG, "context is NULL");
+  HIP_CHECK(hipSetDevice(c->c.device));
+  return &c->c;
+}
+
+void check_csr_shape(const care_csr* A) {
+  if (!A) fail(CARE_ERR_ARG, "A is NULL");
+  if (A->n < 1) fail(CARE_ERR_ARG, "A must have n >= 1");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* care_version(void) { return "mpcare 0.1 (gfx950)"; }
+
+const char* care_last_error(void) { return last_error_cstr(); }
+
+void care_opts_default(care_opts* o, int32_t inner_prec) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->inner_prec = inner_prec;
+  o->k_max = 20;
+  o->k0_max = 20;
+  o->j_max = 50;
+  o->eta_r_rel = 1e-4;
+  o->eta_s_rel = 10.0 * 1.1102230246251565e-16;
+  o->tau_L = 0.0;          // precision default
+  o->tau_0 = 0.0;
+  o->stagnation = 0.999;
+  o->krylov_maxit = 4000;
+  o->krylov_tol = 0.0;     // precision default
+  o->check_every = 8;
+  o->penzl_l0 = 16;
+  o->penzl_kp = 20;
+  o->penzl_km = 10;
+  o->profile = 0;
+  o->Z_init = nullptr;
+  o->ldz_init = 0;
+  o->r_init = 0;
+}
+
+care_status care_ctx_create(care_ctx** out, int32_t device, void* stream) {
+  return guarded([&]() -> care_status {
+    if (!out) fail(CARE_ERR_ARG, "ctx output pointer is NULL");
+    *out = nullptr;
+    int count = 0;
+    HIP_CHECK(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) fail(CARE_ERR_ARG, "device index out of range");
+    HIP_CHECK(hipSetDevice(device));
+    care_ctx* c = new care_ctx();
+    c->c.device = device;
+    c->c.stream = (hipStream_t)stream;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+      c->c.num_cu = prop.multiProcessorCount;
+    c->c.arena = new Arena(c->c.stream);
+    if (rocblas_create_handle(&c->c.blas) != rocblas_status_success) {
+      delete c->c.arena;
+      delete c;
+      fail(CARE_ERR_DEVICE, "rocblas_create_handle failed");
+    }
+    rocblas_set_stream(c->c.blas, c->c.stream);
+    *out = c;
+    return CARE_OK;
+  });
+}
+
+void care_ctx_destroy(care_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->c.device);
+  (void)hipStreamSynchronize(c->c.stream);
+  for (auto& e : c->c.event_pool) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (auto& e : c->c.pending_events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  if (c->c.blas) rocblas_destroy_handle(c->c.blas);
+  delete c->c.arena;
+  if (c->c.pinned) (void)hipHostFree(c->c.pinned);
+  delete c;
+}
+
+care_status care_spmm(care_ctx* cx, const care_csr* A, int32_t prec, care_shift p, const double* X, int64_t ldx,
+                      int32_t k, double* Y, int64_t ldy) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    check_csr_shape(A);
+    const Prec pr = prec_from_abi(prec);
+    if (k < 0) fail(CARE_ERR_ARG, "k must be >= 0");
+    if (k == 0) return CARE_OK;
+    if (!X || !Y || ldx < A->n || ldy < A->n) fail(CARE_ERR_ARG, "invalid X / Y");
+    if (!std::isfinite(p.re) || !std::isfinite(p.im)) fail(CARE_ERR_ARG, "shift not finite");
+    SellOp op;
+    build_sell(ctx, A, pr, op);
+    const int64_t n = A->n, ld = pad_ld(n);
+    const bool cp = p.im != 0.0;
+    const int kr = cp ? 2 * k : k;
+    std::vector<int> map(kr);
+    for (int c = 0; c < kr; ++c) map[c] = cp ? ((c % 2) ? k + c / 2 : c / 2) : c;
+    std::vector<int> inv(kr);
+    for (int c = 0; c < kr; ++c) inv[map[c]] = c;
+    if (pr == Prec::F64) {
+      DBuf<double> xi(ctx, (size_t)ld * kr), yi(ctx, (size_t)ld * kr);
+      copy_cols<double, double>(ctx, n, kr, X, ldx, xi.get(), ld, map.data());
+      spmm_plain(ctx, op, p.re, p.im, xi.get(), ld, kr, yi.get(), ld);
+      copy_cols<double, double>(ctx, n, kr, yi.get(), ld, Y, ldy, inv.data());
+    } else {
+      DBuf<float> xi(ctx, (size_t)ld * kr), yi(ctx, (size_t)ld * kr);
+      copy_cols<double, float>(ctx, n, kr, X, ldx, xi.get(), ld, map.data());
+      spmm_plain(ctx, op, p.re, p.im, xi.get(), ld, kr, yi.get(), ld);
+      copy_cols<float, double>(ctx, n, kr, yi.get(), ld, Y, ldy, inv.data());
+    }
+    ctx->sync();
+    return CARE_OK;
+  });
+}
+
+care_status care_shifted_solve(care_ctx* cx, const care_csr* A, const double* B, int64_t ldb, const double* K,
+                               int64_t ldk, int32_t m, care_shift p, const double* W, int64_t ldw, int32_t w,
+                               int32_t prec, double tol, int32_t maxit, double* V, int64_t ldv, int32_t* iters) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    check_csr_shape(A);
+    const Prec pr = prec_from_abi(prec);
+    const int64_t n = A->n, ld = pad_ld(n);
+    if (w < 0 || m < 0) fail(CARE_ERR_ARG, "w and m must be >= 0");
+    if (w == 0) return CARE_OK;
+    if (!W || !V || ldw < n || ldv < n) fail(CARE_ERR_ARG, "invalid W / V");
+    const bool smw = K != nullptr && m > 0;
+    if (smw && (!B || ldb < n || ldk < n)) fail(CARE_ERR_ARG, "invalid B / K");
+    if (!(p.re < 0) || !std::isfinite(p.re) || !std::isfinite(p.im)) fail(CARE_ERR_ARG, "shift needs Re p < 0");
+    SellOp op;
+    build_sell(ctx, A, pr, op);
+    care_opts d;
+    care_opts_default(&d, prec);
+    d.krylov_tol = tol;
+    d.krylov_maxit = maxit;
+    Resolved r = resolve_opts(&d, 1e-10);
+    LradiParams lp;
+    lp.ktol = r.ktol;
+    lp.kmaxit = r.kmaxit;
+    lp.check_every = r.check_every;
+    const bool cp = p.im != 0.0;
+    const int vc = cp ? 2 * w : w;
+    std::vector<int> inv(vc);
+    for (int c = 0; c < vc; ++c) inv[c] = cp ? ((c < w) ? 2 * c : 2 * (c - w) + 1) : c;
+    KrylovResult kr;
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      DBuf<T> Bs(ctx, (size_t)ld * std::max(m, 1)), Ks(ctx, (size_t)ld * std::max(m, 1)), Ws(ctx, (size_t)ld * w),
+          Vs(ctx, (size_t)ld * vc);
+      if (smw) {
+        copy_cols<double, T>(ctx, n, m, B, ldb, Bs.get(), ld);
+        copy_cols<double, T>(ctx, n, m, K, ldk, Ks.get(), ld);
+      }
+      copy_cols<double, T>(ctx, n, w, W, ldw, Ws.get(), ld);
+      kr = shifted_solve<T>(ctx, op, Bs.get(), smw ? Ks.get() : nullptr, smw ? m : 0, Ws.get(), w, Shift{p.re, p.im},
+                            lp, Vs.get());
+      copy_cols<T, double>(ctx, n, vc, Vs.get(), ld, V, ldv, inv.data());
+    };
+    if (pr == Prec::F64) run(double{});
+    else run(float{});
+    ctx->sync();
+    if (iters) *iters = kr.max_iters;
+    return kr.unconverged ? CARE_WARN_MAXIT : CARE_OK;
+  });
+}
+
+care_status care_gram(care_ctx* cx, int64_t n, const double* X, int64_t ldx, int32_t a, const double* Y, int64_t ldy,
+                      int32_t b, double* Cm, int64_t ldc) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    if (n < 0 || a < 0 || b < 0) fail(CARE_ERR_ARG, "negative size");
+    if (a == 0 || b == 0) return CARE_OK;
+    if (!X || !Y || !Cm || ldx < std::max<int64_t>(n, 1) || ldy < std::max<int64_t>(n, 1) || ldc < a)
+      fail(CARE_ERR_ARG, "invalid pointers or leading dimensions");
+    gram<double, double>(ctx, n, X, ldx, a, Y, ldy, b, Cm, ldc);
+    ctx->sync();
+    return CARE_OK;
+  });
+}
+
+care_status care_tsgemm(care_ctx* cx, int64_t n, const double* X, int64_t ldx, int32_t q, const double* S,
+                        int64_t lds, int32_t k, double alpha, double beta, double* Y, int64_t ldy) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    if (n < 0 || q < 0 || k < 0) fail(CARE_ERR_ARG, "negative size");
+    if (n == 0 || k == 0) return CARE_OK;
+    if (!Y || ldy < n || (q > 0 && (!X || !S || ldx < n || lds < q)))
+      fail(CARE_ERR_ARG, "invalid pointers or leading dimensions");
+    tsgemm<double, double>(ctx, n, X, ldx, q, S, lds, k, alpha, beta, Y, ldy);
+    ctx->sync();
+    return CARE_OK;
+  });
+}
+
+care_status lyap_lradi(care_ctx* cx, const care_csr* A, const double* B, const double* K, int32_t m,
+                       const double* W, int64_t ldw, int32_t w, const care_shift* shifts, int32_t nshifts,
+                       double tol, const care_opts* opts, double* Z, int64_t ldz, int32_t rmax, int32_t* r_out,
+                       care_stats* stats) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    check_csr_shape(A);
+    const int64_t n = A->n, ld = pad_ld(n);
+    if (w < 0 || m < 0) fail(CARE_ERR_ARG, "w and m must be >= 0");
+    if (!r_out) fail(CARE_ERR_ARG, "r_out is NULL");
+    if (w > 0 && (!W || ldw < n)) fail(CARE_ERR_ARG, "invalid W");
+    if (!Z || ldz < n || rmax < 0) fail(CARE_ERR_ARG, "invalid Z");
+    const bool smw = K != nullptr && m > 0;
+    if (smw && !B) fail(CARE_ERR_ARG, "B is NULL while K is given");
+    std::vector<Shift> sh = check_shifts(shifts, nshifts);
+    care_opts d;
+    care_opts_default(&d, CARE_FP64);
+    const care_opts* o = opts ? opts : &d;
+    Resolved r = resolve_opts(o, 1e-10);
+    LradiParams lp;
+    lp.tol = tol > 0 ? tol : r.tau_L;
+    lp.jmax = r.j_max;
+    lp.ktol = r.ktol;
+    lp.kmaxit = r.kmaxit;
+    lp.check_every = r.check_every;
+    ctx->reset_counters();
+    ctx->profile = o->profile;
+    const double t0 = now_s();
+    SellOp op;
+    build_sell(ctx, A, r.prec, op);
+    LradiOut lo;
+    const int zcap = lradi_capacity(w, lp.jmax);
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      DBuf<T> Bs(ctx, (size_t)ld * std::max(m, 1)), Ks(ctx, (size_t)ld * std::max(m, 1)),
+          Ws(ctx, (size_t)ld * std::max(w, 1)), Zs(ctx, (size_t)ld * std::max(zcap, 1));
+      if (smw) {
+        copy_cols<double, T>(ctx, n, m, B, n, Bs.get(), ld);
+        copy_cols<double, T>(ctx, n, m, K, n, Ks.get(), ld);
+      }
+      copy_cols<double, T>(ctx, n, w, W, ldw, Ws.get(), ld);
+      lo = lradi_run<T>(ctx, op, Bs.get(), smw ? Ks.get() : nullptr, smw ? m : 0, Ws.get(), w, sh, lp, Zs.get(),
+                        zcap);
+      *r_out = lo.zcols;
+      if (lo.zcols > rmax) fail(CARE_ERR_CAPACITY, "Z needs " + std::to_string(lo.zcols) + " columns");
+      copy_cols<T, double>(ctx, n, lo.zcols, Zs.get(), ld, Z, ldz);
+    };
+    if (w > 0) {
+      if (r.prec == Prec::F64) run(double{});
+      else run(float{});
+    } else {
+      *r_out = 0;
+    }
+    ctx->sync();
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->iter_outer = 1;
+      stats->iter_inner = lo.steps;
+      stats->rank = lo.zcols;
+      stats->res_rel = lo.res_rel;
+      stats->t_total = now_s() - t0;
+      stats->spmm_calls = ctx->spmm_calls;
+      stats->spmm_bytes = ctx->spmm_bytes;
+      stats->t_spmm = ctx->t_spmm;
+      stats->krylov_iters = ctx->krylov_iters;
+      stats->hist_len = 1;
+      stats->res_hist[0] = lo.res_rel;
+    }
+    if (w > 0 && lo.res_rel > lp.tol) return CARE_WARN_MAXIT;
+    return lo.krylov_unconverged ? CARE_WARN_MAXIT : CARE_OK;
+  });
+}
+
+care_status care_residual_factor(care_ctx* cx, const care_csr* A, const double* B, int32_t m, const double* C,
+                                 int32_t p, const double* Z, int64_t ldz, int32_t r, double eta_r_rel, double* Cp,
+                                 int32_t* rp, double* Cm, int32_t* rm, int64_t ldc, int32_t cap, double* res_fro) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    check_csr_shape(A);
+    const int64_t n = A->n, ld = pad_ld(n);
+    if (m < 0 || p < 0 || r < 0) fail(CARE_ERR_ARG, "m, p, r must be >= 0");
+    if ((m > 0 && !B) || (p > 0 && !C) || (r > 0 && (!Z || ldz < n))) fail(CARE_ERR_ARG, "invalid B / C / Z");
+    if (!rp || !rm || !res_fro || cap < 0 || ldc < n || (cap > 0 && (!Cp || !Cm)))
+      fail(CARE_ERR_ARG, "invalid outputs");
+    if (!(eta_r_rel >= 0)) fail(CARE_ERR_ARG, "eta_r_rel must be >= 0");
+    SellOp op;
+    build_sell(ctx, A, Prec::F64, op);
+    DBuf<double> B64(ctx, (size_t)ld * std::max(m, 1)), Ct(ctx, (size_t)ld * std::max(p, 1));
+    if (m > 0) copy_cols<double, double>(ctx, n, m, B, n, B64.get(), ld);
+    if (p > 0) copy_cols<double, double>(ctx, n, p, C, n, Ct.get(), ld);
+    ResidualFactor rf;
+    residual_factor(ctx, op, B64.get(), m, Ct.get(), p, Z, ldz, r, eta_r_rel, rf);
+    *rp = rf.rp;
+    *rm = rf.rm;
+    *res_fro = rf.res_fro;
+    if (rf.rp > cap || rf.rm > cap)
+      fail(CARE_ERR_CAPACITY, "residual factors need " + std::to_string(std::max(rf.rp, rf.rm)) + " columns");
+    if (rf.rp) copy_cols<double, double>(ctx, n, rf.rp, rf.Cp.get(), ld, Cp, ldc);
+    if (rf.rm) copy_cols<double, double>(ctx, n, rf.rm, rf.Cm.get(), ld, Cm, ldc);
+    ctx->sync();
+    return CARE_OK;
+  });
+}
+
+care_status lowrank_truncate(care_ctx* cx, int64_t n, const double* G, int64_t ldg, int32_t s, const int8_t* sign,
+                             double eta_s_rel, double* Z, int64_t ldz, int32_t cap, int32_t* r_out, double* eta_n) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    if (s < 0 || !r_out || cap < 0) fail(CARE_ERR_ARG, "invalid sizes");
+    if (s > 0 && (!G || !sign)) fail(CARE_ERR_ARG, "G or sign is NULL");
+    if (!(eta_s_rel >= 0)) fail(CARE_ERR_ARG, "eta_s_rel must be >= 0");
+    if (n < 1 || ldg < n || ldz < n) fail(CARE_ERR_ARG, "need n >= 1, ldg >= n, ldz >= n");
+    std::vector<double> sg(s);
+    for (int i = 0; i < s; ++i) {
+      if (sign[i] != 1 && sign[i] != -1) fail(CARE_ERR_ARG, "sign entries must be +1 or -1");
+      sg[i] = sign[i];
+    }
+    TruncResult tr;
+    signed_truncate(ctx, n, G, ldg, s, sg, eta_s_rel, tr);
+    *r_out = tr.r;
+    if (eta_n) *eta_n = tr.eta_n;
+    if (tr.r > cap) fail(CARE_ERR_CAPACITY, "Z needs " + std::to_string(tr.r) + " columns");
+    if (tr.r) copy_cols<double, double>(ctx, n, tr.r, tr.Z.get(), pad_ld(n), Z, ldz);
+    ctx->sync();
+    return CARE_OK;
+  });
+}
+
+care_status care_solve(care_ctx* cx, const care_csr* A, const double* B, int32_t m, const double* C, int32_t p,
+                       double tol, const care_shift* shifts, int32_t nshifts, const care_opts* opts, double* Z,
+                       int64_t ldz, int32_t rmax, int32_t* r_out, care_stats* stats) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    check_csr_shape(A);
+    care_stats local;
+    care_status warn = CARE_OK;
+    care_solve_impl(ctx, A, B, m, C, p, tol, shifts, nshifts, opts, Z, ldz, rmax, r_out, stats ? stats : &local,
+                    &warn);
+    return warn;
+  });
+}
+
+care_status care_penzl_shifts(care_ctx* cx, const care_csr* A, int32_t l0, int32_t kp, int32_t km,
+                              care_shift* out, int32_t* count) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    check_csr_shape(A);
+    if (!out || !count || l0 < 1 || kp < 1 || km < 0) fail(CARE_ERR_ARG, "invalid Penzl arguments");
+    SellOp op;
+    build_sell(ctx, A, Prec::F64, op);
+    std::vector<Shift> s = penzl_shifts(ctx, op, l0, kp, km);
+    *count = (int)s.size();
+    for (size_t i = 0; i < s.size(); ++i) out[i] = care_shift{s[i].re, s[i].im};
+    return CARE_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,295 @@
+// LR-ADI driver and its fused update kernel.
+#include "adi.hpp"
+
+#include <cmath>
+
+#include "dense.hpp"
+
+namespace mpcare {
+
+using cplx = std::complex<double>;
+
+std::vector<Shift> check_shifts(const care_shift* s, int count) {
+  if (count <= 0 || !s) fail(CARE_ERR_ARG, "empty shift set");
+  std::vector<Shift> out;
+  for (int i = 0; i < count; ++i) {
+    const double re = s[i].re, im = s[i].im;
+    if (!(re < 0.0) || !std::isfinite(re) || !std::isfinite(im))
+      fail(CARE_ERR_ARG, "shift " + std::to_string(i) + " must have a finite negative real part");
+    if (im != 0.0) {
+      if (im < 0.0 || i + 1 >= count || s[i + 1].re != re || s[i + 1].im != -im)
+        fail(CARE_ERR_ARG, "complex shift " + std::to_string(i) +
+                               " must be followed by its conjugate (positive imaginary part first)");
+      out.push_back({re, im});
+      out.push_back({re, -im});
+      ++i;
+    } else {
+      out.push_back({re, 0.0});
+    }
+  }
+  return out;
+}
+
+// Gauss-Jordan inverse of a small complex matrix (column-major), partial pivoting
+static bool cinv(int m, std::vector<cplx>& A) {
+  std::vector<cplx> I((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) I[(size_t)i * m + i] = 1.0;
+  for (int c = 0; c < m; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < m; ++r)
+      if (std::abs(A[(size_t)c * m + r]) > std::abs(A[(size_t)c * m + piv])) piv = r;
+    if (std::abs(A[(size_t)c * m + piv]) == 0.0) return false;
+    if (piv != c)
+      for (int j = 0; j < m; ++j) {
+        std::swap(A[(size_t)j * m + c], A[(size_t)j * m + piv]);
+        std::swap(I[(size_t)j * m + c], I[(size_t)j * m + piv]);
+      }
+    const cplx d = A[(size_t)c * m + c];
+    for (int j = 0; j < m; ++j) {
+      A[(size_t)j * m + c] /= d;
+      I[(size_t)j * m + c] /= d;
+    }
+    for (int r = 0; r < m; ++r) {
+      if (r == c) continue;
+      const cplx f = A[(size_t)c * m + r];
+      if (f == 0.0) continue;
+      for (int j = 0; j < m; ++j) {
+        A[(size_t)j * m + r] -= f * A[(size_t)j * m + c];
+        I[(size_t)j * m + r] -= f * I[(size_t)j * m + c];
+      }
+    }
+  }
+  A.swap(I);
+  return true;
+}
+
+// V = Vh + S Y (SMW correction, S: n x m, Y: m x w), then the ADI update.
+// Real:    W -= 2 p V;  Z(:, c) = sqrt(-2p) V(:, c)
+// Complex: Vh, S interleaved (re, im) column pairs, Y = Yr + i Yi;
+//          Vr_hat = Re V + delta Im V;  W -= 4 Re(p) Vr_hat;
+//          Z(:, c) = z1 Vr_hat,  Z(:, w + c) = z2 Im V
+template <typename T, bool CPLX>
+__global__ void __launch_bounds__(256) k_adi_update(int64_t n, int w, int m, int64_t ld, const T* __restrict__ Vh,
+                                                    const T* __restrict__ S, const double* __restrict__ Yr,
+                                                    const double* __restrict__ Yi, T* __restrict__ W,
+                                                    T* __restrict__ Z, double c_w, double z1, double z2,
+                                                    double delta) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n || c >= w) return;
+  if (!CPLX) {
+    double v = (double)Vh[(int64_t)c * ld + i];
+    for (int l = 0; l < m; ++l) v += (double)S[(int64_t)l * ld + i] * Yr[(int64_t)c * m + l];
+    const int64_t o = (int64_t)c * ld + i;
+    W[o] = (T)((double)W[o] - c_w * v);
+    Z[o] = (T)(z1 * v);
+  } else {
+    double vr = (double)Vh[(int64_t)(2 * c) * ld + i];
+    double vi = (double)Vh[(int64_t)(2 * c + 1) * ld + i];
+    for (int l = 0; l < m; ++l) {
+      const double sr = (double)S[(int64_t)(2 * l) * ld + i], si = (double)S[(int64_t)(2 * l + 1) * ld + i];
+      const double yr = Yr[(int64_t)c * m + l], yi = Yi[(int64_t)c * m + l];
+      vr += sr * yr - si * yi;
+      vi += sr * yi + si * yr;
+    }
+    const double vhat = vr + delta * vi;
+    const int64_t o = (int64_t)c * ld + i;
+    W[o] = (T)((double)W[o] - c_w * vhat);
+    Z[o] = (T)(z1 * vhat);
+    Z[(int64_t)(w + c) * ld + i] = (T)(z2 * vi);
+  }
+}
+
+template <typename T>
+static double fro_gram(Ctx* ctx, int64_t n, const T* W, int64_t ld, int w) {
+  DBuf<double> G(ctx, (size_t)w * w);
+  gram(ctx, n, W, ld, w, W, ld, w, G.get(), w);
+  std::vector<double> h((size_t)w * w);
+  d2h(ctx, h.data(), G.get(), h.size() * sizeof(double));
+  double s = 0;
+  for (double v : h) s += v * v;
+  return std::sqrt(s);
+}
+
+struct ShiftCache {
+  bool ready = false;
+  DBuf<uint8_t> S;              // M^{-1} K (T, ld x m, complex: 2m interleaved)
+  std::vector<cplx> Tinv;       // (I - B^T S)^{-1}, m x m
+};
+
+// One SMW shifted solve: M [Vh, S] = [W, K] (S only when not cached for this
+// shift), then Y = T^{-1} (B^T Vh) returned as (yr, yi), m x w column-major.
+// rhs / sol: scratch panels of ld x 2 (w + m) entries; Vh is left in sol.
+template <typename T>
+static KrylovResult smw_step(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, const T* W, int w, Shift p,
+                             ShiftCache& sc, const LradiParams& prm, T* rhs, T* sol, std::vector<double>& yr,
+                             std::vector<double>& yi) {
+  const int64_t n = op.n, ld = pad_ld(n);
+  const bool smw = K != nullptr && m > 0;
+  const bool cp = p.im != 0.0;
+  const bool need_s = smw && !sc.ready;
+  const int nrhs = w + (need_s ? m : 0);
+  if (!cp) {
+    copy_cols<T, T>(ctx, n, w, W, ld, rhs, ld);
+    if (need_s) copy_cols<T, T>(ctx, n, m, K, ld, rhs + (int64_t)w * ld, ld);
+  } else {
+    std::vector<int> map(2 * std::max(w, m));
+    for (int c = 0; c < std::max(w, m); ++c) {
+      map[2 * c] = c;
+      map[2 * c + 1] = -1;
+    }
+    copy_cols<T, T>(ctx, n, 2 * w, W, ld, rhs, ld, map.data());
+    if (need_s) copy_cols<T, T>(ctx, n, 2 * m, K, ld, rhs + (int64_t)2 * w * ld, ld, map.data());
+  }
+  KrylovResult kr = bicgstab<T>(ctx, op, p.re, p.im, (cp ? 2 : 1) * nrhs, rhs, ld, sol, ld, prm.ktol, prm.kmaxit,
+                                prm.check_every);
+  yr.assign((size_t)std::max(m, 1) * w, 0.0);
+  yi.assign((size_t)std::max(m, 1) * w, 0.0);
+  if (!smw) return kr;
+  if (need_s) {
+    const int sc_cols = (cp ? 2 : 1) * m;
+    sc.S.resize(ctx, (size_t)ld * sc_cols * sizeof(T));
+    d2d(ctx, sc.S.get(), sol + (int64_t)(cp ? 2 : 1) * w * ld, (size_t)ld * sc_cols * sizeof(T));
+    DBuf<double> G(ctx, (size_t)m * sc_cols);
+    gram(ctx, n, B, ld, m, (const T*)sc.S.get(), ld, sc_cols, G.get(), m);
+    std::vector<double> h((size_t)m * sc_cols);
+    d2h(ctx, h.data(), G.get(), h.size() * sizeof(double));
+    std::vector<cplx> Tm((size_t)m * m);
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i) {
+        const cplx bs = cp ? cplx(h[(size_t)(2 * j) * m + i], h[(size_t)(2 * j + 1) * m + i])
+                           : cplx(h[(size_t)j * m + i], 0.0);
+        Tm[(size_t)j * m + i] = (i == j ? 1.0 : 0.0) - bs;
+      }
+    if (!cinv(m, Tm)) fail(CARE_ERR_BREAKDOWN, "singular SMW capacitance matrix I - B^T (A^T + pI)^{-1} K");
+    sc.Tinv = Tm;
+    sc.ready = true;
+  }
+  const int vcols = (cp ? 2 : 1) * w;
+  DBuf<double> Gbv(ctx, (size_t)m * vcols);
+  gram(ctx, n, B, ld, m, sol, ld, vcols, Gbv.get(), m);
+  std::vector<double> h((size_t)m * vcols);
+  d2h(ctx, h.data(), Gbv.get(), h.size() * sizeof(double));
+  for (int c = 0; c < w; ++c)
+    for (int i = 0; i < m; ++i) {
+      cplx acc = 0.0;
+      for (int l = 0; l < m; ++l) {
+        const cplx g = cp ? cplx(h[(size_t)(2 * c) * m + l], h[(size_t)(2 * c + 1) * m + l])
+                          : cplx(h[(size_t)c * m + l], 0.0);
+        acc += sc.Tinv[(size_t)l * m + i] * g;
+      }
+      yr[(size_t)c * m + i] = acc.real();
+      yi[(size_t)c * m + i] = acc.imag();
+    }
+  return kr;
+}
+
+template <typename T>
+LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T* W, int w,
+                   const std::vector<Shift>& shifts, const LradiParams& prm, T* Z, int zcap) {
+  LradiOut out;
+  const int64_t n = op.n;
+  const int64_t ld = pad_ld(n);
+  if (w <= 0) return out;
+  if (shifts.empty()) fail(CARE_ERR_ARG, "empty shift set");
+  const bool smw = K != nullptr && m > 0;
+  out.res0 = fro_gram(ctx, n, W, ld, w);
+  if (!std::isfinite(out.res0)) fail(CARE_ERR_NONFINITE, "non-finite right-hand side factor");
+  if (out.res0 == 0.0) return out;
+
+  const int maxcols = smw ? w + m : w;
+  DBuf<T> rhs(ctx, (size_t)ld * 2 * maxcols), sol(ctx, (size_t)ld * 2 * maxcols);
+  std::vector<ShiftCache> cache(shifts.size());
+  DBuf<double> dYr(ctx, (size_t)std::max(m, 1) * w), dYi(ctx, (size_t)std::max(m, 1) * w);
+  std::vector<double> yr, yi;
+
+  size_t idx = 0;
+  while (out.steps < prm.jmax) {
+    const Shift p = shifts[idx % shifts.size()];
+    ShiftCache& sc = cache[idx % shifts.size()];
+    const bool cp = p.im != 0.0;
+    const int width = (cp ? 2 : 1) * w;
+    if (out.zcols + width > zcap) fail(CARE_ERR_CAPACITY, "LR-ADI factor buffer too small");
+    KrylovResult kr = smw_step<T>(ctx, op, B, K, m, W, w, p, sc, prm, rhs.get(), sol.get(), yr, yi);
+    out.krylov_unconverged += kr.unconverged;
+    out.krylov_max_iters = std::max(out.krylov_max_iters, kr.max_iters);
+    if (smw) {
+      h2d(ctx, dYr.get(), yr.data(), (size_t)m * w * sizeof(double));
+      if (cp) h2d(ctx, dYi.get(), yi.data(), (size_t)m * w * sizeof(double));
+    }
+    T* Zb = Z + (int64_t)out.zcols * ld;
+    dim3 g(ceil_div(n, 256), w);
+    const T* Sp = smw ? (const T*)sc.S.get() : nullptr;
+    if (!cp) {
+      const double z1 = std::sqrt(-2.0 * p.re);
+      hipLaunchKernelGGL((k_adi_update<T, false>), g, dim3(256), 0, ctx->stream, n, w, smw ? m : 0, ld,
+                         (const T*)sol.get(), Sp, dYr.get(), dYi.get(), W, Zb, 2.0 * p.re, z1, 0.0, 0.0);
+      out.steps += 1;
+      idx += 1;
+    } else {
+      const double delta = p.re / p.im;
+      const double gam = std::sqrt(-2.0 * p.re);
+      const double z1 = std::sqrt(2.0) * gam, z2 = std::sqrt(2.0) * gam * std::sqrt(delta * delta + 1.0);
+      hipLaunchKernelGGL((k_adi_update<T, true>), g, dim3(256), 0, ctx->stream, n, w, smw ? m : 0, ld,
+                         (const T*)sol.get(), Sp, dYr.get(), dYi.get(), W, Zb, 4.0 * p.re, z1, z2, delta);
+      out.steps += 2;
+      idx += 2;
+    }
+    KERNEL_CHECK();
+    out.zcols += width;
+    const double res = fro_gram(ctx, n, W, ld, w);
+    if (!std::isfinite(res)) fail(CARE_ERR_NONFINITE, "LR-ADI residual became non-finite");
+    out.res_rel = res / out.res0;
+    if (out.res_rel > 1e8) fail(CARE_ERR_UNSTABLE, "LR-ADI diverged (is A - B K^T stable?)");
+    if (out.res_rel <= prm.tol) break;
+  }
+  return out;
+}
+
+template <typename T>
+KrylovResult shifted_solve(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, const T* W, int w, Shift p,
+                           const LradiParams& prm, T* V) {
+  const int64_t n = op.n, ld = pad_ld(n);
+  const bool cp = p.im != 0.0;
+  const int maxcols = w + m;
+  DBuf<T> rhs(ctx, (size_t)ld * 2 * maxcols), sol(ctx, (size_t)ld * 2 * maxcols);
+  ShiftCache sc;
+  std::vector<double> yr, yi;
+  KrylovResult kr = smw_step<T>(ctx, op, B, K, m, W, w, p, sc, prm, rhs.get(), sol.get(), yr, yi);
+  const int vcols = (cp ? 2 : 1) * w;
+  d2d(ctx, V, sol.get(), (size_t)ld * vcols * sizeof(T));
+  if (K != nullptr && m > 0) {
+    // V += S Yhat, Yhat the real form of the complex m x w matrix Y
+    const int sr = (cp ? 2 : 1) * m;
+    std::vector<double> Yh((size_t)sr * vcols, 0.0);
+    for (int c = 0; c < w; ++c)
+      for (int l = 0; l < m; ++l) {
+        const double a = yr[(size_t)c * m + l], b = yi[(size_t)c * m + l];
+        if (!cp) {
+          Yh[(size_t)c * sr + l] = a;
+        } else {
+          Yh[(size_t)(2 * c) * sr + 2 * l] = a;
+          Yh[(size_t)(2 * c + 1) * sr + 2 * l] = b;
+          Yh[(size_t)(2 * c) * sr + 2 * l + 1] = -b;
+          Yh[(size_t)(2 * c + 1) * sr + 2 * l + 1] = a;
+        }
+      }
+    DBuf<double> dY(ctx, Yh.size());
+    h2d(ctx, dY.get(), Yh.data(), Yh.size() * sizeof(double));
+    tsgemm<T, T>(ctx, n, (const T*)sc.S.get(), ld, sr, dY.get(), sr, vcols, 1.0, 1.0, V, ld);
+  }
+  ctx->sync();
+  return kr;
+}
+
+template KrylovResult shifted_solve<double>(Ctx*, const SellOp&, const double*, const double*, int, const double*,
+                                            int, Shift, const LradiParams&, double*);
+template KrylovResult shifted_solve<float>(Ctx*, const SellOp&, const float*, const float*, int, const float*, int,
+                                           Shift, const LradiParams&, float*);
+
+template LradiOut lradi_run<double>(Ctx*, const SellOp&, const double*, const double*, int, double*, int,
+                                    const std::vector<Shift>&, const LradiParams&, double*, int);
+template LradiOut lradi_run<float>(Ctx*, const SellOp&, const float*, const float*, int, float*, int,
+                                   const std::vector<Shift>&, const LradiParams&, float*, int);
+
+}  // namespace mpcare

@@ -1,0 +1,62 @@
+// Residual-based LR-ADI with SMW shifted solves (the inner solver of Sec. 4).
+//
+// For  A_k^T X + X A_k + W0 W0^T = 0,  A_k = A - B K^T,  F = A_k^T:
+//   real p:        V = (F + p I)^{-1} W,  W <- W - 2 p V,  Z <- [Z, sqrt(-2p) V]
+//   pair (p, p*):  V = (F + p I)^{-1} W (complex), delta = Re p / Im p,
+//                  Vh = Re V + delta Im V,  W <- W - 4 Re(p) Vh,
+//                  Z <- [Z, sqrt(2) g Vh, sqrt(2) g sqrt(delta^2 + 1) Im V],
+//                  g = sqrt(-2 Re p)
+// and ||residual||_F = ||W^T W||_F after every step.  (F + p I)^{-1} is applied
+// through the Sherman-Morrison-Woodbury formula of Sec. 4 with M = A^T + p I:
+//   M [Vh, S] = [W, K],  T = I_m - B^T S,  V = Vh + S T^{-1} B^T Vh,
+// where S = M^{-1} K and T^{-1} are cached per shift for the whole solve.
+#pragma once
+
+#include <complex>
+
+#include "krylov.hpp"
+
+namespace mpcare {
+
+struct Shift {
+  double re, im;
+};
+
+struct LradiParams {
+  double tol = 1e-12;        // ||W^T W||_F <= tol ||W0^T W0||_F
+  int jmax = 50;
+  double ktol = 1e-10;       // Krylov relative residual per column
+  int kmaxit = 4000;
+  int check_every = 8;
+};
+
+struct LradiOut {
+  int steps = 0;             // ADI steps (a complex pair counts 2)
+  int zcols = 0;             // columns written to Z
+  double res_rel = 0.0;      // final ||W^T W||_F / ||W0^T W0||_F
+  double res0 = 0.0;         // ||W0^T W0||_F
+  int krylov_unconverged = 0;
+  int krylov_max_iters = 0;
+};
+
+// shift list checks: Re < 0, complex shifts as (p, conj p) with Im p > 0 first
+std::vector<Shift> check_shifts(const care_shift* s, int count);
+
+// Run LR-ADI in vector precision T (double or float) on the prepared
+// operator.  B, K: n x m (K may be NULL), W: n x w, all with leading
+// dimension pad_ld(n); W is overwritten by the final residual factor.  Z
+// (ld pad_ld(n), capacity zcap columns) receives the factor blocks.
+template <typename T>
+LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T* W, int w,
+                   const std::vector<Shift>& shifts, const LradiParams& prm, T* Z, int zcap);
+
+// One SMW shifted solve (A_k^T + p I) V = W (the building block of
+// lradi_run), V explicit: n x w real, or n x 2w interleaved for complex p.
+template <typename T>
+KrylovResult shifted_solve(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, const T* W, int w, Shift p,
+                           const LradiParams& prm, T* V);
+
+// largest number of factor columns lradi_run can write for jmax steps
+inline int lradi_capacity(int w, int jmax) { return w * (jmax + 2); }
+
+}  // namespace mpcare

@@ -1,0 +1,339 @@
+// Framework 1 (Factorization-based Mixed Precision Newton Iterative
+// Refinement) with the NLR-ADI initial solve of Sec. 4.
+#include "care.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace mpcare {
+
+static const double U64 = 1.1102230246251565e-16;   // FP64 unit roundoff (Table 1)
+static const double U32 = 5.9604644775390625e-08;   // FP32 unit roundoff (Table 1)
+static const double UBF = 3.90625e-03;              // bfloat16 unit roundoff (Table 1)
+
+Resolved resolve_opts(const care_opts* o, double tol) {
+  Resolved r;
+  care_opts d;
+  care_opts_default(&d, o ? o->inner_prec : CARE_FP64);
+  if (!o) o = &d;
+  r.prec = prec_from_abi(o->inner_prec);
+  const double tl_def = r.prec == Prec::F64 ? 1e-12 : (r.prec == Prec::F32 ? 1e-5 : 1e-3);
+  const double kt_def = r.prec == Prec::F64 ? 1e-10 : (r.prec == Prec::F32 ? 1e-5 : 1e-3);
+  r.tau_L = o->tau_L > 0 ? o->tau_L : tl_def;
+  r.ktol = o->krylov_tol > 0 ? o->krylov_tol : kt_def;
+  r.tau_0 = o->tau_0 > 0 ? o->tau_0 : std::max(tol, 10.0 * r.tau_L);
+  r.eta_r_rel = o->eta_r_rel;
+  r.eta_s_rel = o->eta_s_rel;
+  r.stagnation = o->stagnation > 0 ? o->stagnation : 0.999;
+  r.k_max = o->k_max;
+  r.k0_max = o->k0_max;
+  r.j_max = o->j_max;
+  r.kmaxit = o->krylov_maxit > 0 ? o->krylov_maxit : 4000;
+  r.check_every = o->check_every > 0 ? o->check_every : 8;
+  if (r.k_max < 1 || r.k0_max < 1 || r.j_max < 1) fail(CARE_ERR_ARG, "k_max, k0_max and j_max must be >= 1");
+  if (r.eta_r_rel < 0 || r.eta_s_rel < 0) fail(CARE_ERR_ARG, "truncation thresholds must be >= 0");
+  return r;
+}
+
+static double unit_roundoff(Prec p) { return p == Prec::F64 ? U64 : (p == Prec::F32 ? U32 : UBF); }
+
+// ||F M F^T||_F for F = [W, dK], M = diag(I, -I): from the Gram G = F^T F,
+// ||F M F^T||_F^2 = sum_ij s_i s_j G_ij^2.
+template <typename T>
+static double kleinman_residual(Ctx* ctx, int64_t n, const T* W, int w, const T* dK, int m) {
+  const int64_t ld = pad_ld(n);
+  const int q = w + m;
+  DBuf<T> F(ctx, (size_t)ld * q);
+  d2d(ctx, F.get(), W, (size_t)ld * w * sizeof(T));
+  d2d(ctx, F.get() + (int64_t)w * ld, dK, (size_t)ld * m * sizeof(T));
+  DBuf<double> G(ctx, (size_t)q * q);
+  gram(ctx, n, F.get(), ld, q, F.get(), ld, q, G.get(), q);
+  std::vector<double> h((size_t)q * q);
+  d2h(ctx, h.data(), G.get(), h.size() * sizeof(double));
+  double s = 0.0;
+  for (int j = 0; j < q; ++j)
+    for (int i = 0; i < q; ++i) {
+      const double sg = ((i < w) == (j < w)) ? 1.0 : -1.0;
+      const double g = h[(size_t)j * q + i];
+      s += sg * g * g;
+    }
+  return std::sqrt(std::max(s, 0.0));
+}
+
+struct SolveState {
+  const SellOp* A64 = nullptr;
+  const SellOp* As = nullptr;      // operator in the inner precision
+  DBuf<double> B64, Ct64;          // ld = pad_ld(n)
+  int64_t n = 0, ld = 0;
+  int m = 0, p = 0;
+  double nrm_ctc = 0.0;            // ||C^T C||_F
+  std::vector<Shift> shifts;
+  Resolved prm;
+};
+
+template <typename T>
+static void cast_in(Ctx* ctx, int64_t n, int cols, const double* src, int64_t lds, DBuf<T>& dst) {
+  const int64_t ld = pad_ld(n);
+  dst.resize(ctx, (size_t)ld * std::max(cols, 1));
+  copy_cols<double, T>(ctx, n, cols, src, lds, dst.get(), ld);
+}
+
+// Stage 0: NLR-ADI (Newton-Kleinman, K_0 = 0) in precision T.
+template <typename T>
+static void stage0(Ctx* ctx, SolveState& S, TruncResult& Zout, care_stats* st, std::vector<double>& hist) {
+  const int64_t n = S.n, ld = S.ld;
+  const int m = S.m, p = S.p;
+  DBuf<T> Bs, Cts;
+  cast_in<T>(ctx, n, m, S.B64.get(), ld, Bs);
+  cast_in<T>(ctx, n, p, S.Ct64.get(), ld, Cts);
+  const int wmax = p + m;
+  const int zcap = lradi_capacity(wmax, S.prm.j_max);
+  DBuf<T> K(ctx, (size_t)ld * std::max(m, 1)), Kn(ctx, (size_t)ld * std::max(m, 1)),
+      dK(ctx, (size_t)ld * std::max(m, 1));
+  DBuf<T> W(ctx, (size_t)ld * wmax), Zb(ctx, (size_t)ld * zcap);
+  DBuf<double> Y(ctx, (size_t)zcap * std::max(m, 1));
+  LradiParams lp;
+  lp.tol = S.prm.tau_L;
+  lp.jmax = S.prm.j_max;
+  lp.ktol = S.prm.ktol;
+  lp.kmaxit = S.prm.kmaxit;
+  lp.check_every = S.prm.check_every;
+  double prev = 0.0;
+  int zcols = 0;
+  for (int i = 0; i < S.prm.k0_max; ++i) {
+    const int w = (i == 0 || m == 0) ? p : p + m;
+    d2d(ctx, W.get(), Cts.get(), (size_t)ld * p * sizeof(T));
+    if (w > p) d2d(ctx, W.get() + (int64_t)p * ld, K.get(), (size_t)ld * m * sizeof(T));
+    LradiOut lo = lradi_run<T>(ctx, *S.As, Bs.get(), (i > 0 && m > 0) ? K.get() : nullptr, m, W.get(), w, S.shifts,
+                               lp, Zb.get(), zcap);
+    st->iter0_outer += 1;
+    st->iter0_inner += lo.steps;
+    zcols = lo.zcols;
+    double rel;
+    if (m > 0) {
+      // K_{i+1} = Z (Z^T B)
+      gram(ctx, n, Zb.get(), ld, zcols, Bs.get(), ld, m, Y.get(), zcols);
+      tsgemm<T, T>(ctx, n, Zb.get(), ld, zcols, Y.get(), zcols, m, 1.0, 0.0, Kn.get(), ld);
+      d2d(ctx, dK.get(), Kn.get(), (size_t)ld * m * sizeof(T));
+      if (i > 0) axpby<T>(ctx, n, m, -1.0, K.get(), ld, 1.0, dK.get(), ld);
+      // Riccati residual of X_{i+1} = Z Z^T:  R = W W^T - dK dK^T
+      rel = kleinman_residual<T>(ctx, n, W.get(), w, dK.get(), m) / S.nrm_ctc;
+      std::swap(K, Kn);
+    } else {
+      rel = kleinman_residual<T>(ctx, n, W.get(), w, dK.get(), 0) / S.nrm_ctc;
+    }
+    hist.push_back(rel);
+    if (!std::isfinite(rel)) fail(CARE_ERR_NONFINITE, "initial NLR-ADI residual is not finite");
+    if (rel <= S.prm.tau_0 || m == 0) break;
+    if (i > 0 && rel / prev > S.prm.stagnation) break;
+    prev = rel;
+  }
+  // promote to FP64 and compress: positive part above 10 u_s (Alg. 2, N = I)
+  DBuf<double> G(ctx, (size_t)ld * std::max(zcols, 1));
+  copy_cols<T, double>(ctx, n, zcols, Zb.get(), ld, G.get(), ld);
+  std::vector<double> sign(zcols, 1.0);
+  signed_truncate(ctx, n, G.get(), ld, zcols, sign, 10.0 * unit_roundoff(S.prm.prec), Zout);
+}
+
+// one inner correction: LR-ADI on [C+, C-] with A_k = A - B (Z Z^T B)^T in
+// precision T; returns the combined factor promoted to FP64 with its signs
+template <typename T>
+static void correction(Ctx* ctx, SolveState& S, const TruncResult& Zk, const ResidualFactor& rf, DBuf<double>& Zpm,
+                       int& zcols, std::vector<double>& sign, care_stats* st) {
+  const int64_t n = S.n, ld = S.ld;
+  const int m = S.m;
+  const int w = rf.rp + rf.rm;
+  DBuf<T> Bs, Ks, W(ctx, (size_t)ld * std::max(w, 1));
+  cast_in<T>(ctx, n, m, S.B64.get(), ld, Bs);
+  // K = Z (Z^T B) in FP64, then rounded to the inner precision
+  DBuf<double> K64(ctx, (size_t)ld * std::max(m, 1));
+  if (m > 0 && Zk.r > 0) {
+    DBuf<double> Y(ctx, (size_t)Zk.r * m);
+    gram(ctx, n, Zk.Z.get(), ld, Zk.r, S.B64.get(), ld, m, Y.get(), Zk.r);
+    tsgemm<double, double>(ctx, n, Zk.Z.get(), ld, Zk.r, Y.get(), Zk.r, m, 1.0, 0.0, K64.get(), ld);
+  } else if (m > 0) {
+    dzero(ctx, K64.get(), (size_t)ld * m * sizeof(double));
+  }
+  cast_in<T>(ctx, n, m, K64.get(), ld, Ks);
+  if (rf.rp) copy_cols<double, T>(ctx, n, rf.rp, rf.Cp.get(), ld, W.get(), ld);
+  if (rf.rm) copy_cols<double, T>(ctx, n, rf.rm, rf.Cm.get(), ld, W.get() + (int64_t)rf.rp * ld, ld);
+  const int zcap = lradi_capacity(w, S.prm.j_max);
+  DBuf<T> Zb(ctx, (size_t)ld * zcap);
+  LradiParams lp;
+  lp.tol = S.prm.tau_L;
+  lp.jmax = S.prm.j_max;
+  lp.ktol = S.prm.ktol;
+  lp.kmaxit = S.prm.kmaxit;
+  lp.check_every = S.prm.check_every;
+  LradiOut lo = lradi_run<T>(ctx, *S.As, Bs.get(), (m > 0 && Zk.r > 0) ? Ks.get() : nullptr, m, W.get(), w,
+                             S.shifts, lp, Zb.get(), zcap);
+  st->iter_inner += lo.steps;
+  zcols = lo.zcols;
+  Zpm.resize(ctx, (size_t)ld * std::max(zcols, 1));
+  copy_cols<T, double>(ctx, n, zcols, Zb.get(), ld, Zpm.get(), ld);
+  sign.assign(zcols, 1.0);
+  for (int c = 0; c < zcols; ++c) sign[c] = (c % w) < rf.rp ? 1.0 : -1.0;
+}
+
+static double fro_of_gram(Ctx* ctx, int64_t n, const double* X, int64_t ld, int k) {
+  if (k <= 0) return 0.0;
+  DBuf<double> G(ctx, (size_t)k * k);
+  gram(ctx, n, X, ld, k, X, ld, k, G.get(), k);
+  std::vector<double> h((size_t)k * k);
+  d2h(ctx, h.data(), G.get(), h.size() * sizeof(double));
+  double s = 0;
+  for (double v : h) s += v * v;
+  return std::sqrt(s);
+}
+
+void care_solve_impl(Ctx* ctx, const care_csr* A, const double* B, int m, const double* C, int p, double tol,
+                     const care_shift* shifts, int nshifts, const care_opts* opts, double* Zout, int64_t ldz,
+                     int rmax, int* r_out, care_stats* st, care_status* warn) {
+  const double t0 = now_s();
+  *warn = CARE_OK;
+  std::memset(st, 0, sizeof(*st));
+  if (!A) fail(CARE_ERR_ARG, "A is NULL");
+  const int64_t n = A->n;
+  if (m < 0 || p < 1) fail(CARE_ERR_ARG, "need m >= 0 and p >= 1");
+  if (m > 0 && !B) fail(CARE_ERR_ARG, "B is NULL");
+  if (!C) fail(CARE_ERR_ARG, "C is NULL");
+  if (!(tol > 0)) fail(CARE_ERR_ARG, "tol must be positive");
+  if (!Zout || ldz < n || rmax < 0 || !r_out) fail(CARE_ERR_ARG, "invalid output factor arguments");
+  if (opts && opts->Z_init && (opts->ldz_init < n || opts->r_init < 0)) fail(CARE_ERR_ARG, "invalid Z_init");
+  SolveState S;
+  S.prm = resolve_opts(opts, tol);
+  S.n = n;
+  S.ld = pad_ld(n);
+  S.m = m;
+  S.p = p;
+  ctx->reset_counters();
+  ctx->profile = opts ? opts->profile : 0;
+
+  SellOp A64, As;
+  build_sell(ctx, A, Prec::F64, A64);
+  S.A64 = &A64;
+  if (S.prm.prec == Prec::F64) {
+    S.As = &A64;
+  } else {
+    build_sell(ctx, A, S.prm.prec, As);
+    S.As = &As;
+  }
+  if (nshifts > 0) {
+    S.shifts = check_shifts(shifts, nshifts);
+  } else {
+    care_opts d;
+    care_opts_default(&d, CARE_FP64);
+    const care_opts* o = opts ? opts : &d;
+    S.shifts = penzl_shifts(ctx, A64, o->penzl_l0, o->penzl_kp, o->penzl_km);
+  }
+  // B and C^T in internal layout (ld = pad_ld(n)); C is p x n row-major = C^T col-major with ld n
+  S.B64.resize(ctx, (size_t)S.ld * std::max(m, 1));
+  S.Ct64.resize(ctx, (size_t)S.ld * p);
+  if (m > 0) copy_cols<double, double>(ctx, n, m, B, n, S.B64.get(), S.ld);
+  copy_cols<double, double>(ctx, n, p, C, n, S.Ct64.get(), S.ld);
+  S.nrm_ctc = fro_of_gram(ctx, n, S.Ct64.get(), S.ld, p);
+  if (!std::isfinite(S.nrm_ctc)) fail(CARE_ERR_NONFINITE, "C has non-finite entries");
+  if (m > 0 && !std::isfinite(fro_of_gram(ctx, n, S.B64.get(), S.ld, m)))
+    fail(CARE_ERR_NONFINITE, "B has non-finite entries");
+  ctx->sync();
+  const double t1 = now_s();
+  st->t_setup = t1 - t0;
+
+  // ---------------- stage 0 ----------------
+  TruncResult Z;
+  std::vector<double> hist0, hist;
+  if (opts && opts->Z_init) {
+    const int r0 = opts->r_init;
+    DBuf<double> G(ctx, (size_t)S.ld * std::max(r0, 1));
+    copy_cols<double, double>(ctx, n, r0, opts->Z_init, opts->ldz_init, G.get(), S.ld);
+    Z.Z = std::move(G);
+    Z.r = r0;
+  } else if (S.prm.prec == Prec::F64) {
+    stage0<double>(ctx, S, Z, st, hist0);
+  } else {
+    stage0<float>(ctx, S, Z, st, hist0);
+  }
+  ctx->sync();
+  const double t2 = now_s();
+  st->t_stage0 = t2 - t1;
+
+  // ---------------- refinement (Framework 1) ----------------
+  double prev = 0.0, best = INFINITY;
+  TruncResult bestZ;
+  bool converged = false, stagnated = false;
+  double last_res = NAN;
+  for (int k = 0; k < S.prm.k_max; ++k) {
+    ResidualFactor rf;
+    residual_factor(ctx, A64, S.B64.get(), m, S.Ct64.get(), p, Z.Z.get(), S.ld, Z.r, S.prm.eta_r_rel, rf);
+    st->iter_outer += 1;
+    const double rel = rf.res_fro / S.nrm_ctc;
+    if (!std::isfinite(rel)) fail(CARE_ERR_NONFINITE, "Riccati residual is not finite");
+    hist.push_back(rel);
+    last_res = rel;
+    if (rel < best) {
+      best = rel;
+      bestZ.Z.resize(ctx, (size_t)S.ld * std::max(Z.r, 1));
+      d2d(ctx, bestZ.Z.get(), Z.Z.get(), (size_t)S.ld * Z.r * sizeof(double));
+      bestZ.r = Z.r;
+      bestZ.eta_n = Z.eta_n;
+    }
+    if (rel <= tol) {
+      converged = true;
+      break;
+    }
+    if (k > 0 && rel / prev > S.prm.stagnation) {
+      stagnated = true;
+      break;
+    }
+    prev = rel;
+    if (k == S.prm.k_max - 1) break;     // no correction whose residual would go unchecked
+    DBuf<double> Zpm;
+    int zcols = 0;
+    std::vector<double> sgn;
+    if (S.prm.prec == Prec::F64) correction<double>(ctx, S, Z, rf, Zpm, zcols, sgn, st);
+    else correction<float>(ctx, S, Z, rf, Zpm, zcols, sgn, st);
+    // G = [Z, Z+-], Algorithm 2
+    const int s = Z.r + zcols;
+    DBuf<double> G(ctx, (size_t)S.ld * std::max(s, 1));
+    d2d(ctx, G.get(), Z.Z.get(), (size_t)S.ld * Z.r * sizeof(double));
+    d2d(ctx, G.get() + (int64_t)Z.r * S.ld, Zpm.get(), (size_t)S.ld * zcols * sizeof(double));
+    std::vector<double> sign(s, 1.0);
+    for (int c = 0; c < zcols; ++c) sign[Z.r + c] = sgn[c];
+    TruncResult Zn;
+    signed_truncate(ctx, n, G.get(), S.ld, s, sign, S.prm.eta_s_rel, Zn);
+    st->eta_n = Zn.eta_n;
+    Z = std::move(Zn);
+  }
+  ctx->sync();
+  const double t3 = now_s();
+  st->t_refine = t3 - t2;
+  // return the best factor met
+  const TruncResult& R = bestZ.r > 0 || Z.r == 0 ? bestZ : Z;
+  st->rank = R.r;
+  st->res_rel = best;
+  st->stagnated = stagnated ? 1 : 0;
+  *r_out = R.r;
+  if (R.r > rmax) fail(CARE_ERR_CAPACITY, "output factor needs " + std::to_string(R.r) + " columns");
+  if (R.r > 0) copy_cols<double, double>(ctx, n, R.r, R.Z.get(), S.ld, Zout, ldz);
+  // the paper's normalised residual
+  const double ztz = fro_of_gram(ctx, n, R.Z.get(), S.ld, R.r);
+  const double btb = m > 0 ? fro_of_gram(ctx, n, S.B64.get(), S.ld, m) : 0.0;
+  st->res_paper = best * S.nrm_ctc / (2.0 * A64.frob * ztz + btb * ztz * ztz + S.nrm_ctc);
+  ctx->sync();
+  int hl = 0;
+  for (double v : hist0)
+    if (hl < 48) st->res_hist[hl++] = v;
+  for (double v : hist)
+    if (hl < 48) st->res_hist[hl++] = v;
+  st->hist_len = hl;
+  st->t_total = now_s() - t0;
+  st->spmm_calls = ctx->spmm_calls;
+  st->spmm_bytes = ctx->spmm_bytes;
+  st->t_spmm = ctx->t_spmm;
+  st->krylov_iters = ctx->krylov_iters;
+  (void)last_res;
+  if (!converged) *warn = stagnated ? CARE_WARN_STAGNATED : CARE_WARN_MAXIT;
+}
+
+}  // namespace mpcare

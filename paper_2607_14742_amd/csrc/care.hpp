@@ -1,0 +1,25 @@
+// Framework 1 driver: NLR-ADI initial solve in the inner precision, then the
+// FP64 residual / inner correction / FP64 update loop.
+#pragma once
+
+#include "adi.hpp"
+#include "lowrank.hpp"
+
+namespace mpcare {
+
+struct Resolved {
+  Prec prec = Prec::F64;
+  double tau_L = 1e-12, tau_0 = 1e-10, ktol = 1e-10;
+  double eta_r_rel = 1e-4, eta_s_rel = 1.1102230246251565e-15, stagnation = 0.999;
+  int k_max = 20, k0_max = 20, j_max = 50, kmaxit = 4000, check_every = 8;
+};
+
+Resolved resolve_opts(const care_opts* o, double tol);
+
+void care_solve_impl(Ctx* ctx, const care_csr* A, const double* B, int m, const double* C, int p, double tol,
+                     const care_shift* shifts, int nshifts, const care_opts* opts, double* Z, int64_t ldz, int rmax,
+                     int* r_out, care_stats* stats, care_status* warn);
+
+std::vector<Shift> penzl_shifts(Ctx* ctx, const SellOp& A64, int l0, int kp, int km);
+
+}  // namespace mpcare

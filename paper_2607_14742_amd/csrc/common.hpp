@@ -1,0 +1,177 @@
+// Internal declarations shared by the library's translation units.
+// Host-side runtime: errors, the device-memory arena, the context, and the
+// launch helpers every kernel file uses.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <rocblas/rocblas.h>
+
+#include <chrono>
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "mpcare.h"
+
+namespace mpcare {
+
+// ----------------------------------------------------------------------------
+// errors: internal code throws CareError; the ABI layer converts it to a status
+// ----------------------------------------------------------------------------
+struct CareError {
+  care_status status;
+  std::string msg;
+};
+
+void set_last_error(const std::string& msg);
+const char* last_error_cstr();
+[[noreturn]] void fail(care_status st, const std::string& msg);
+
+#define HIP_CHECK(expr)                                                                   \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      ::mpcare::fail(_e == hipErrorOutOfMemory ? CARE_ERR_NOMEM : CARE_ERR_DEVICE,        \
+                     std::string(#expr) + ": " + hipGetErrorString(_e));                  \
+  } while (0)
+
+#define ROCBLAS_CHECK(expr)                                                               \
+  do {                                                                                    \
+    rocblas_status _s = (expr);                                                           \
+    if (_s != rocblas_status_success)                                                     \
+      ::mpcare::fail(CARE_ERR_DEVICE, std::string(#expr) + ": rocblas status " +          \
+                                          std::to_string((int)_s));                       \
+  } while (0)
+
+#define KERNEL_CHECK() HIP_CHECK(hipGetLastError())
+
+// ----------------------------------------------------------------------------
+// precision tags
+// ----------------------------------------------------------------------------
+using bf16 = __hip_bfloat16;
+
+enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2 };
+
+inline Prec prec_from_abi(int32_t p) {
+  if (p == CARE_FP64) return Prec::F64;
+  if (p == CARE_FP32) return Prec::F32;
+  if (p == CARE_BF16_SPMM) return Prec::BF16;
+  fail(CARE_ERR_ARG, "unknown precision " + std::to_string(p));
+}
+inline size_t vec_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }   // Krylov vectors
+inline size_t val_bytes(Prec p) { return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2); }
+
+// ----------------------------------------------------------------------------
+// device memory arena (grow-only caching allocator owned by a context)
+// ----------------------------------------------------------------------------
+class Arena {
+ public:
+  explicit Arena(hipStream_t s) : stream_(s) {}
+  ~Arena();
+  void* get(size_t bytes);
+  void put(void* p);
+  size_t in_use() const { return in_use_; }
+
+ private:
+  hipStream_t stream_;
+  std::multimap<size_t, void*> free_;
+  std::map<void*, size_t> live_;
+  size_t in_use_ = 0;
+};
+
+// ----------------------------------------------------------------------------
+// context
+// ----------------------------------------------------------------------------
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  rocblas_handle blas = nullptr;
+  Arena* arena = nullptr;
+  void* pinned = nullptr;          // small pinned host staging buffer
+  size_t pinned_bytes = 0;
+  int num_cu = 256;
+  // sparse-product accounting (care_stats)
+  int profile = 0;
+  int64_t spmm_calls = 0;
+  double spmm_bytes = 0.0;
+  double t_spmm = 0.0;
+  int64_t krylov_iters = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_events;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
+  void reset_counters() {
+    spmm_calls = 0;
+    spmm_bytes = 0;
+    t_spmm = 0;
+    krylov_iters = 0;
+  }
+  void* host_stage(size_t bytes);  // pinned buffer of at least `bytes`
+  void sync();                     // stream synchronize + harvest profile events
+  std::pair<hipEvent_t, hipEvent_t> event_pair();
+};
+
+// RAII device buffer from the context arena
+template <typename T>
+struct DBuf {
+  Ctx* ctx = nullptr;
+  T* ptr = nullptr;
+  size_t count = 0;
+  DBuf() = default;
+  DBuf(Ctx* c, size_t n) : ctx(c), count(n) {
+    ptr = n ? static_cast<T*>(c->arena->get(n * sizeof(T))) : nullptr;
+  }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : ctx(o.ctx), ptr(o.ptr), count(o.count) { o.ptr = nullptr; o.count = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    release();
+    ctx = o.ctx; ptr = o.ptr; count = o.count;
+    o.ptr = nullptr; o.count = 0;
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void release() {
+    if (ptr && ctx) ctx->arena->put(ptr);
+    ptr = nullptr;
+    count = 0;
+  }
+  void resize(Ctx* c, size_t n) {   // discards contents
+    if (n <= count && ptr) return;
+    release();
+    ctx = c;
+    count = n;
+    ptr = n ? static_cast<T*>(c->arena->get(n * sizeof(T))) : nullptr;
+  }
+  T* get() const { return ptr; }
+};
+
+// copies between host and device on the context stream (synchronous)
+void d2h(Ctx* ctx, void* host, const void* dev, size_t bytes);
+void h2d(Ctx* ctx, void* dev, const void* host, size_t bytes);
+void d2d(Ctx* ctx, void* dst, const void* src, size_t bytes);
+void dzero(Ctx* ctx, void* dst, size_t bytes);   // fill kernel, never a memset node
+
+inline double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// leading dimension of internal n x k panels: rows rounded up to 64
+inline int64_t pad_ld(int64_t n) { return (n + 63) / 64 * 64; }
+
+// XCD-aware workgroup remap: consecutive logical blocks land on the same XCD
+// (8 XCDs, round-robin dispatch), so neighbouring row blocks share an L2.
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
+  const unsigned nx = 8;
+  unsigned per = nb / nx, rem = nb % nx;
+  unsigned x = b % nx, i = b / nx;
+  // blocks of XCD x get logical ids [x*per + min(x, rem), ...)
+  unsigned base = x * per + (x < rem ? x : rem);
+  unsigned cnt = per + (x < rem ? 1u : 0u);
+  return i < cnt ? base + i : b;
+}
+
+}  // namespace mpcare

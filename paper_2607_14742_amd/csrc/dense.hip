@@ -1,0 +1,503 @@
+// Dense tall-skinny kernels on the FP64 matrix cores of gfx950, the small
+// dense helpers, and the rank-revealing orthogonalisation used by
+// Algorithms 1 and 2.
+#include "dense.hpp"
+
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <numeric>
+
+namespace mpcare {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64 operand layout (wave64): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; the 16 x 16 result is returned as
+// four doubles per lane, D[(l / 16) + 4 v][l % 16], v = 0..3 (checked on
+// gfx950 against a host product).
+__device__ __forceinline__ double4_t mfma16(double a, double b, double4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ double ldg_d(const T* p) {
+  return (double)*p;
+}
+
+// ---------------------------------------------------------------------------
+// Gram  C = X^T Y
+// ---------------------------------------------------------------------------
+// Grid: x = output tile (32 x 32) index, y = row split.  Each of the 4 waves
+// accumulates the whole tile over every 4th 16-row group of its split; the
+// waves are then summed through LDS and the tile is written to
+// part[split][tile][32 x 32].  Row k of a 16-row group is fed to MFMA t from
+// lane group g with k = 4 g + t, so each lane reads 4 consecutive rows of
+// one column (32 B) per operand.
+template <typename TX, typename TY>
+__global__ void __launch_bounds__(256) k_gram(int64_t n, const TX* __restrict__ X, int64_t ldx, int a,
+                                              const TY* __restrict__ Y, int64_t ldy, int b, int tiles_j,
+                                              int64_t rows_per_split, const int* __restrict__ tile_list,
+                                              double* __restrict__ part) {
+  const int tl = blockIdx.x;
+  const int tcode = tile_list[tl];
+  const int ti = tcode / tiles_j, tj = tcode % tiles_j;
+  const int i0 = ti * 32, j0 = tj * 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = lane & 15, g = lane >> 4;
+  const int64_t rbeg = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t rend = min(n, rbeg + rows_per_split);
+
+  double4_t acc[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+  // column pointers (clamped; out-of-range columns are zeroed by a flag)
+  const int xc0 = i0 + cl, xc1 = i0 + 16 + cl, yc0 = j0 + cl, yc1 = j0 + 16 + cl;
+  const bool xv0 = xc0 < a, xv1 = xc1 < a, yv0 = yc0 < b, yv1 = yc1 < b;
+  const TX* xp0 = X + (int64_t)(xv0 ? xc0 : 0) * ldx;
+  const TX* xp1 = X + (int64_t)(xv1 ? xc1 : 0) * ldx;
+  const TY* yp0 = Y + (int64_t)(yv0 ? yc0 : 0) * ldy;
+  const TY* yp1 = Y + (int64_t)(yv1 ? yc1 : 0) * ldy;
+
+  for (int64_t r0 = rbeg + (int64_t)wave * 16; r0 < rend; r0 += 64) {
+    const int64_t rr = r0 + 4 * g;
+    double x0[4], x1[4], y0[4], y1[4];
+    if (rr + 3 < rend) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        x0[t] = xv0 ? ldg_d(xp0 + rr + t) : 0.0;
+        x1[t] = xv1 ? ldg_d(xp1 + rr + t) : 0.0;
+        y0[t] = yv0 ? ldg_d(yp0 + rr + t) : 0.0;
+        y1[t] = yv1 ? ldg_d(yp1 + rr + t) : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bool ok = rr + t < rend;
+        x0[t] = (xv0 && ok) ? ldg_d(xp0 + rr + t) : 0.0;
+        x1[t] = (xv1 && ok) ? ldg_d(xp1 + rr + t) : 0.0;
+        y0[t] = (yv0 && ok) ? ldg_d(yp0 + rr + t) : 0.0;
+        y1[t] = (yv1 && ok) ? ldg_d(yp1 + rr + t) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      acc[0][0] = mfma16(x0[t], y0[t], acc[0][0]);
+      acc[0][1] = mfma16(x0[t], y1[t], acc[0][1]);
+      acc[1][0] = mfma16(x1[t], y0[t], acc[1][0]);
+      acc[1][1] = mfma16(x1[t], y1[t], acc[1][1]);
+    }
+  }
+  // reduce the 4 waves through LDS: tile element (i, j) at red[i * 33 + j]
+  __shared__ double red[3][32 * 33];
+  if (wave > 0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int ii = 16 * u + g + 4 * e, jj = 16 * v + cl;
+          red[wave - 1][ii * 33 + jj] = acc[u][v][e];
+        }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    double* out = part + ((int64_t)blockIdx.y * gridDim.x + tl) * 1024;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int ii = 16 * u + g + 4 * e, jj = 16 * v + cl;
+          double s = acc[u][v][e];
+          s += red[0][ii * 33 + jj];
+          s += red[1][ii * 33 + jj];
+          s += red[2][ii * 33 + jj];
+          out[ii * 32 + jj] = s;
+        }
+  }
+}
+
+// C(i, j) = sum over splits (fixed order); symmetric: mirror the upper tiles
+__global__ void k_gram_reduce(const double* __restrict__ part, int ntl, int nsplit, const int* __restrict__ tile_list,
+                              int tiles_j, int a, int b, int sym, double* __restrict__ C, int64_t ldc) {
+  const int tl = blockIdx.x;
+  const int tcode = tile_list[tl];
+  const int ti = tcode / tiles_j, tj = tcode % tiles_j;
+  for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
+    const int ii = e >> 5, jj = e & 31;
+    const int i = ti * 32 + ii, j = tj * 32 + jj;
+    if (i >= a || j >= b) continue;
+    double s = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) s += part[((int64_t)sp * ntl + tl) * 1024 + e];
+    C[(int64_t)j * ldc + i] = s;
+    if (sym && ti != tj) C[(int64_t)i * ldc + j] = s;
+  }
+}
+
+template <typename TX, typename TY>
+void gram(Ctx* ctx, int64_t n, const TX* X, int64_t ldx, int a, const TY* Y, int64_t ldy, int b, double* C,
+          int64_t ldc) {
+  if (a <= 0 || b <= 0) return;
+  if (n <= 0) {
+    for (int j = 0; j < b; ++j) dzero(ctx, C + (int64_t)j * ldc, a * sizeof(double));
+    return;
+  }
+  const bool sym = (const void*)X == (const void*)Y && ldx == ldy && a == b && sizeof(TX) == sizeof(TY);
+  const int tiles_i = (a + 31) / 32, tiles_j = (b + 31) / 32;
+  std::vector<int> tl;
+  for (int i = 0; i < tiles_i; ++i)
+    for (int j = 0; j < tiles_j; ++j)
+      if (!sym || j >= i) tl.push_back(i * tiles_j + j);
+  const int ntl = (int)tl.size();
+  // aim at ~4 workgroups per CU, at least 256 rows per split
+  int64_t want = std::max<int64_t>(1, (int64_t)4 * ctx->num_cu / ntl);
+  int64_t rps = std::max<int64_t>(256, (n + want - 1) / want);
+  rps = (rps + 63) / 64 * 64;
+  const int nsplit = (int)((n + rps - 1) / rps);
+  DBuf<int> dtl(ctx, ntl);
+  h2d(ctx, dtl.get(), tl.data(), ntl * sizeof(int));
+  DBuf<double> part(ctx, (size_t)nsplit * ntl * 1024);
+  hipLaunchKernelGGL((k_gram<TX, TY>), dim3(ntl, nsplit), dim3(256), 0, ctx->stream, n, X, ldx, a, Y, ldy, b, tiles_j,
+                     rps, dtl.get(), part.get());
+  KERNEL_CHECK();
+  hipLaunchKernelGGL(k_gram_reduce, dim3(ntl), dim3(256), 0, ctx->stream, part.get(), ntl, nsplit, dtl.get(), tiles_j,
+                     a, b, sym ? 1 : 0, C, ldc);
+  KERNEL_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// tall-skinny GEMM  Y = alpha X S + beta Y
+// ---------------------------------------------------------------------------
+// Each wave computes a 16-row x 64-column block of Y as Y^T = S^T X^T:
+// A' = S^T (lane: S[k][j0 + l % 16]), B' = X^T (lane: X[r0 + l % 16][k]),
+// result lane l, v -> Y[r0 + l % 16][j0 + (l / 16) + 4 v], so every store
+// instruction writes 16 consecutive rows of a column.
+template <typename TX, typename TY>
+__global__ void __launch_bounds__(256) k_tsgemm(int64_t n, const TX* __restrict__ X, int64_t ldx, int q,
+                                                const double* __restrict__ S, int64_t lds, int k, double alpha,
+                                                double beta, TY* __restrict__ Yp, int64_t ldy) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = lane & 15, g = lane >> 4;
+  const int64_t r0 = ((int64_t)xcd_remap(blockIdx.x, gridDim.x) * 4 + wave) * 16;
+  const int jbase = blockIdx.y * 64;
+  if (r0 >= n) return;
+  const int64_t row = r0 + cl;
+  const bool rv = row < n;
+  double4_t acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  int jc[4];
+  bool jv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    jc[u] = jbase + 16 * u + cl;
+    jv[u] = jc[u] < k;
+  }
+  for (int k0 = 0; k0 < q; k0 += 16) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int kk = k0 + 4 * g + t;       // row of S / column of X fed by this lane
+      const bool kv = kk < q;
+      const double xb = (kv && rv) ? ldg_d(X + (int64_t)kk * ldx + row) : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double sa = (kv && jv[u]) ? S[(int64_t)jc[u] * lds + kk] : 0.0;
+        acc[u] = mfma16(sa, xb, acc[u]);
+      }
+    }
+  }
+  // lane holds Y[r0 + cl][jbase + 16 u + g + 4 v]
+  if (!rv) return;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = jbase + 16 * u + g + 4 * v;
+      if (j < k) {
+        TY* yp = Yp + (int64_t)j * ldy + row;
+        double val = alpha * acc[u][v];
+        if (beta != 0.0) val += beta * (double)*yp;
+        *yp = (TY)val;
+      }
+    }
+}
+
+template <typename TX, typename TY>
+void tsgemm(Ctx* ctx, int64_t n, const TX* X, int64_t ldx, int q, const double* S, int64_t lds, int k, double alpha,
+            double beta, TY* Y, int64_t ldy) {
+  if (n <= 0 || k <= 0) return;
+  if (q <= 0) {   // X S is empty: Y = beta Y
+    if (beta == 0.0) {
+      for (int j = 0; j < k; ++j) dzero(ctx, Y + (int64_t)j * ldy, n * sizeof(TY));
+    } else if (beta != 1.0) {
+      axpby<TY>(ctx, n, k, 0.0, Y, ldy, beta, Y, ldy);
+    }
+    return;
+  }
+  dim3 grid(ceil_div(n, 64), ceil_div(k, 64));
+  hipLaunchKernelGGL((k_tsgemm<TX, TY>), grid, dim3(256), 0, ctx->stream, n, X, ldx, q, S, lds, k, alpha, beta, Y,
+                     ldy);
+  KERNEL_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// column copies
+// ---------------------------------------------------------------------------
+template <typename TI, typename TO>
+__global__ void k_copy_cols(int64_t n, int ncols, const TI* __restrict__ in, int64_t ldi, TO* __restrict__ out,
+                            int64_t ldo, const int* __restrict__ map, const double* __restrict__ scale) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n || c >= ncols) return;
+  const int src = map ? map[c] : c;
+  double v = 0.0;
+  if (src >= 0) v = (double)in[(int64_t)src * ldi + i];
+  if (scale) v *= scale[c];
+  out[(int64_t)c * ldo + i] = (TO)v;
+}
+
+template <typename TI, typename TO>
+void copy_cols(Ctx* ctx, int64_t n, int ncols, const TI* in, int64_t ldi, TO* out, int64_t ldo, const int* map,
+               const double* scale) {
+  if (n <= 0 || ncols <= 0) return;
+  DBuf<int> dmap;
+  DBuf<double> dscale;
+  if (map) {
+    dmap.resize(ctx, ncols);
+    h2d(ctx, dmap.get(), map, ncols * sizeof(int));
+  }
+  if (scale) {
+    dscale.resize(ctx, ncols);
+    h2d(ctx, dscale.get(), scale, ncols * sizeof(double));
+  }
+  for (int c0 = 0; c0 < ncols; c0 += 65535) {
+    const int nc = std::min(ncols - c0, 65535);
+    dim3 g(ceil_div(n, 256), nc);
+    hipLaunchKernelGGL((k_copy_cols<TI, TO>), g, dim3(256), 0, ctx->stream, n, nc, in, ldi, out + (int64_t)c0 * ldo,
+                       ldo, map ? dmap.get() + c0 : nullptr, scale ? dscale.get() + c0 : nullptr);
+    KERNEL_CHECK();
+  }
+}
+
+template <typename T>
+__global__ void k_axpby(int64_t n, int ncols, double a, const T* __restrict__ X, int64_t ldx, double b,
+                        T* __restrict__ Y, int64_t ldy) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n || c >= ncols) return;
+  T* y = Y + (int64_t)c * ldy + i;
+  const double xv = (double)X[(int64_t)c * ldx + i];
+  *y = (T)(a * xv + (b != 0.0 ? b * (double)*y : 0.0));
+}
+
+template <typename T>
+void axpby(Ctx* ctx, int64_t n, int ncols, double a, const T* X, int64_t ldx, double b, T* Y, int64_t ldy) {
+  if (n <= 0 || ncols <= 0) return;
+  dim3 g(ceil_div(n, 256), ncols);
+  hipLaunchKernelGGL((k_axpby<T>), g, dim3(256), 0, ctx->stream, n, ncols, a, X, ldx, b, Y, ldy);
+  KERNEL_CHECK();
+}
+template void axpby<double>(Ctx*, int64_t, int, double, const double*, int64_t, double, double*, int64_t);
+template void axpby<float>(Ctx*, int64_t, int, double, const float*, int64_t, double, float*, int64_t);
+
+#define INST_GRAM(TX, TY) \
+  template void gram<TX, TY>(Ctx*, int64_t, const TX*, int64_t, int, const TY*, int64_t, int, double*, int64_t);
+INST_GRAM(double, double)
+INST_GRAM(float, float)
+INST_GRAM(float, double)
+INST_GRAM(double, float)
+#define INST_TS(TX, TY)                                                                                      \
+  template void tsgemm<TX, TY>(Ctx*, int64_t, const TX*, int64_t, int, const double*, int64_t, int, double, \
+                               double, TY*, int64_t);
+INST_TS(double, double)
+INST_TS(float, float)
+INST_TS(double, float)
+INST_TS(float, double)
+#define INST_CP(TI, TO) \
+  template void copy_cols<TI, TO>(Ctx*, int64_t, int, const TI*, int64_t, TO*, int64_t, const int*, const double*);
+INST_CP(double, double)
+INST_CP(double, float)
+INST_CP(float, double)
+INST_CP(float, float)
+
+// ---------------------------------------------------------------------------
+// small dense helpers
+// ---------------------------------------------------------------------------
+void dgemm(Ctx* ctx, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B,
+           int ldb, double beta, double* C, int ldc) {
+  if (m <= 0 || n <= 0) return;
+  if (k <= 0) {
+    if (beta == 0.0)
+      for (int j = 0; j < n; ++j) dzero(ctx, C + (int64_t)j * ldc, m * sizeof(double));
+    return;
+  }
+  ROCBLAS_CHECK(rocblas_dgemm(ctx->blas, ta ? rocblas_operation_transpose : rocblas_operation_none,
+                              tb ? rocblas_operation_transpose : rocblas_operation_none, m, n, k, &alpha, A, lda, B,
+                              ldb, &beta, C, ldc));
+}
+
+void dsyevd(Ctx* ctx, int n, double* A, int lda, std::vector<double>& w) {
+  w.assign(n, 0.0);
+  if (n <= 0) return;
+  DBuf<double> D(ctx, n), E(ctx, n);
+  DBuf<int> info(ctx, 1);
+  ROCBLAS_CHECK(rocsolver_dsyevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, n, A, lda, D.get(), E.get(),
+                                 info.get()));
+  int hinfo = 0;
+  d2h(ctx, &hinfo, info.get(), sizeof(int));
+  if (hinfo != 0) fail(CARE_ERR_DEVICE, "rocsolver_dsyevd did not converge (info " + std::to_string(hinfo) + ")");
+  d2h(ctx, w.data(), D.get(), n * sizeof(double));
+}
+
+__global__ void k_scale_sym(double* __restrict__ G, int64_t ldg, int q, const double* __restrict__ s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i < q) G[(int64_t)j * ldg + i] *= s[i] * s[j];
+}
+__global__ void k_scale_rows(double* __restrict__ A, int64_t lda, int m, int ncols, const double* __restrict__ s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i < m && j < ncols) A[(int64_t)j * lda + i] *= s[i];
+}
+
+// ---------------------------------------------------------------------------
+// rank-revealing orthogonalisation
+// ---------------------------------------------------------------------------
+// Pass structure (all FP64):
+//   E_0 = F.  Pass p: G = E_p^T E_p, scaled by the inverse column norms of F
+//   (so thresholds are relative to each column of F); G~ = W L W^T.  Keep
+//   directions with l > max(1e-11 max l, noise), noise = (64 u)^2 q: they
+//   give U_new = E_p S W_sel L_sel^{-1/2}, whose Gram has condition number
+//   <= 1e11 * (1 + O(u)), so one Cholesky polish makes it orthonormal.  U_new
+//   is made orthogonal to the previous U (two Gram-Schmidt passes), then
+//   E_{p+1} = F - U U^T F (two passes).  The loop ends when E carries no
+//   direction above the noise level; T = U^T F.  Unlike Cholesky QR this
+//   handles rank-deficient F (columns of Z Z^T B lie in range(Z); ADI blocks
+//   are nearly collinear) and keeps the small directions that carry the
+//   Riccati residual, to the accuracy of Householder QR.
+// Re-orthonormalise the k nearly orthonormal columns of U in place:
+// U^T U = V D V^T, U <- U V D^{-1/2} over the eigenvalues D > 1e-8 max D.
+// Returns the number of columns kept (at the front of U); a column that the
+// projection against earlier passes reduced to noise is dropped here and
+// its direction, if real, is met again by the next pass.
+static int polish(Ctx* ctx, int64_t n, double* U, int64_t ldu, int k, bool trace) {
+  if (k <= 0) return 0;
+  DBuf<double> G(ctx, (size_t)k * k);
+  gram(ctx, n, U, ldu, k, U, ldu, k, G.get(), k);
+  std::vector<double> d;
+  dsyevd(ctx, k, G.get(), k, d);
+  const double dmax = d.empty() ? 0.0 : d.back();
+  std::vector<int> sel;
+  std::vector<double> isq;
+  for (int i = k - 1; i >= 0; --i)
+    if (d[i] > 1e-8 * dmax) {
+      sel.push_back(i);
+      isq.push_back(1.0 / std::sqrt(d[i]));
+    }
+  if (trace)
+    std::fprintf(stderr, "[rr_orth] polish k %d kept %zu eig [%.3e, %.3e]\n", k, sel.size(), d.empty() ? 0.0 : d[0],
+                 dmax);
+  const int kk = (int)sel.size();
+  if (kk == 0) return 0;
+  DBuf<double> B(ctx, (size_t)k * kk);
+  copy_cols<double, double>(ctx, k, kk, G.get(), k, B.get(), k, sel.data(), isq.data());
+  DBuf<double> tmp(ctx, (size_t)pad_ld(n) * kk);
+  tsgemm(ctx, n, U, ldu, k, B.get(), k, kk, 1.0, 0.0, tmp.get(), pad_ld(n));
+  for (int j = 0; j < kk; ++j)
+    d2d(ctx, U + (int64_t)j * ldu, tmp.get() + (int64_t)j * pad_ld(n), n * sizeof(double));
+  return kk;
+}
+
+void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out) {
+  const double u = 1.1102230246251565e-16;
+  const bool trace = std::getenv("MPCARE_TRACE") != nullptr;
+  const int64_t ld = pad_ld(n);
+  out.ldu = ld;
+  out.k = 0;
+  out.U.resize(ctx, (size_t)ld * std::max(q, 1));
+  out.T.resize(ctx, (size_t)std::max(q, 1) * std::max(q, 1));
+  if (q <= 0) return;
+
+  // column norms of F -> s = 1 / ||F_j|| (0 for zero columns)
+  DBuf<double> G(ctx, (size_t)q * q);
+  gram(ctx, n, F, ldf, q, F, ldf, q, G.get(), q);
+  std::vector<double> hG((size_t)q * q);
+  d2h(ctx, hG.data(), G.get(), hG.size() * sizeof(double));
+  std::vector<double> s(q);
+  for (int j = 0; j < q; ++j) {
+    const double d = hG[(size_t)j * q + j];
+    s[j] = d > 0 ? 1.0 / std::sqrt(d) : 0.0;
+  }
+  DBuf<double> ds(ctx, q);
+  h2d(ctx, ds.get(), s.data(), q * sizeof(double));
+
+  DBuf<double> E(ctx, (size_t)ld * q);
+  const double* Ecur = F;
+  int64_t lde = ldf;
+  const double noise = (64.0 * u) * (64.0 * u) * q;
+  DBuf<double> W(ctx, (size_t)q * q), B(ctx, (size_t)q * q), Tf(ctx, (size_t)q * q), T2(ctx, (size_t)q * q);
+  std::vector<double> lam;
+  for (int pass = 0; pass < 5; ++pass) {
+    if (pass > 0) gram(ctx, n, Ecur, lde, q, Ecur, lde, q, G.get(), q);
+    d2d(ctx, W.get(), G.get(), (size_t)q * q * sizeof(double));
+    dim3 gs(ceil_div(q, 64), q);
+    hipLaunchKernelGGL(k_scale_sym, gs, dim3(64), 0, ctx->stream, W.get(), (int64_t)q, q, ds.get());
+    KERNEL_CHECK();
+    dsyevd(ctx, q, W.get(), q, lam);
+    const double lmax = *std::max_element(lam.begin(), lam.end());
+    const double thr = std::max(1e-11 * lmax, noise);
+    std::vector<int> sel;
+    std::vector<double> isq;
+    for (int i = q - 1; i >= 0; --i)
+      if (lam[i] > thr && out.k + (int)sel.size() < q) {
+        sel.push_back(i);
+        isq.push_back(1.0 / std::sqrt(lam[i]));
+      }
+    if (sel.empty()) break;
+    const int kk = (int)sel.size();
+    // B = S W_sel L_sel^{-1/2}
+    copy_cols<double, double>(ctx, q, kk, W.get(), q, B.get(), q, sel.data(), isq.data());
+    dim3 gr(ceil_div(q, 64), kk);
+    hipLaunchKernelGGL(k_scale_rows, gr, dim3(64), 0, ctx->stream, B.get(), (int64_t)q, q, kk, ds.get());
+    KERNEL_CHECK();
+    double* Unew = out.U.get() + (int64_t)out.k * ld;
+    tsgemm(ctx, n, Ecur, lde, q, B.get(), q, kk, 1.0, 0.0, Unew, ld);
+    if (out.k > 0) {
+      for (int rep = 0; rep < 2; ++rep) {   // Unew -= U (U^T Unew)
+        gram(ctx, n, out.U.get(), ld, out.k, Unew, ld, kk, T2.get(), out.k);
+        tsgemm(ctx, n, out.U.get(), ld, out.k, T2.get(), out.k, kk, -1.0, 1.0, Unew, ld);
+      }
+    }
+    if (trace)
+      std::fprintf(stderr, "[rr_orth] n %lld q %d pass %d lmax %.3e thr %.3e new %d\n", (long long)n, q, pass, lmax,
+                   thr, kk);
+    const int kept = polish(ctx, n, Unew, ld, kk, trace);
+    if (kept == 0) break;
+    out.k += kept;
+    // E = F - U (U^T F), twice; Tf = U^T F
+    gram(ctx, n, out.U.get(), ld, out.k, F, ldf, q, Tf.get(), out.k);
+    for (int j = 0; j < q; ++j) d2d(ctx, E.get() + (int64_t)j * ld, F + (int64_t)j * ldf, n * sizeof(double));
+    tsgemm(ctx, n, out.U.get(), ld, out.k, Tf.get(), out.k, q, -1.0, 1.0, E.get(), ld);
+    gram(ctx, n, out.U.get(), ld, out.k, E.get(), ld, q, T2.get(), out.k);
+    tsgemm(ctx, n, out.U.get(), ld, out.k, T2.get(), out.k, q, -1.0, 1.0, E.get(), ld);
+    // Tf += T2 (k x q, ld k): small add through rocBLAS geam-free path
+    {
+      const double one = 1.0;
+      ROCBLAS_CHECK(rocblas_dgeam(ctx->blas, rocblas_operation_none, rocblas_operation_none, out.k, q, &one,
+                                  Tf.get(), out.k, &one, T2.get(), out.k, out.T.get(), out.k));
+    }
+    Ecur = E.get();
+    lde = ld;
+    if (out.k >= q) break;
+  }
+  if (out.k == 0) return;
+  ctx->sync();
+}
+
+}  // namespace mpcare

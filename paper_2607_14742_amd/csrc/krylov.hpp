@@ -1,0 +1,28 @@
+// Column-batched BiCGStab for the shifted block solves (A^T + p I) X = B
+// that dominate LR-ADI (Sec. 4: "the dominant computation is the application
+// of M_alpha^{-1} to block right hand sides").  The paper uses restarted
+// GMRES; this library uses BiCGStab (two sparse products and a handful of
+// fused vector passes per iteration, no basis storage) with one independent
+// recurrence per right-hand-side column, all columns sharing each launch.
+#pragma once
+
+#include "sparse.hpp"
+
+namespace mpcare {
+
+struct KrylovResult {
+  int max_iters = 0;        // largest per-column iteration count
+  int unconverged = 0;      // columns that stopped above tol
+  int breakdown = 0;        // columns stopped by a breakdown
+  double worst_relres = 0;  // largest ||r|| / ||b|| at exit (recursive residual)
+};
+
+// Solve (A^T + p I) x_c = b_c for every column c.  T = double needs an FP64
+// operator, T = float an FP32 or BF16 operator.  Complex p (pi != 0): b and
+// x hold ncols_real/2 complex columns as interleaved (re, im) column pairs.
+// x is overwritten (zero initial guess).  Columns with b_c = 0 return 0.
+template <typename T>
+KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncols_real, const T* b,
+                      int64_t ldb, T* x, int64_t ldx, double tol, int maxit, int check_every);
+
+}  // namespace mpcare

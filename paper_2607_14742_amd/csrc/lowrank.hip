@@ -1,0 +1,161 @@
+// Algorithms 1 and 2 (FP64).
+#include "lowrank.hpp"
+
+#include <cmath>
+
+namespace mpcare {
+
+// Algorithm 1.  The paper factors R(Z) = F M F^T with
+// F = [Z, A^T Z, Z Z^T B, C^T].  The third block lies in range(Z)
+// (Z Z^T B = Z Y with Y = Z^T B), so the same residual is formed here as
+//   R(Z) = F' M' F'^T,   F' = [Z, A^T Z, C^T],
+//   M' = [[-Y Y^T, I, 0], [I, 0, 0], [0, 0, I_p]],
+// which is identical in exact arithmetic and avoids m exactly dependent
+// columns in the thin QR.  Then F' = U T (rank-revealing, Householder
+// accuracy), H = T M' T^T, H = Q Lambda Q^T, J+- = {lambda >= eta} / {lambda <= -eta},
+// C+ = U Q+ Lambda+^(1/2), C- = U Q- (-Lambda-)^(1/2), ||R||_F = ||Lambda||_2.
+void residual_factor(Ctx* ctx, const SellOp& A64, const double* B, int m, const double* Ct, int p, const double* Z,
+                     int64_t ldz, int r, double eta_r_rel, ResidualFactor& out) {
+  const int64_t n = A64.n;
+  const int64_t ld = pad_ld(n);
+  const int q = 2 * r + p;
+  out.rp = out.rm = 0;
+  out.res_fro = 0.0;
+  if (q == 0) return;
+  DBuf<double> F(ctx, (size_t)ld * q);
+  for (int j = 0; j < r; ++j) d2d(ctx, F.get() + (int64_t)j * ld, Z + (int64_t)j * ldz, n * sizeof(double));
+  if (r > 0) spmm_plain(ctx, A64, 0.0, 0.0, Z, ldz, r, F.get() + (int64_t)r * ld, ld);
+  for (int j = 0; j < p; ++j)
+    d2d(ctx, F.get() + (int64_t)(2 * r + j) * ld, Ct + (int64_t)j * ld, n * sizeof(double));
+
+  // M'
+  std::vector<double> Mh((size_t)q * q, 0.0);
+  if (r > 0 && m > 0) {
+    DBuf<double> Y(ctx, (size_t)r * m);
+    gram(ctx, n, Z, ldz, r, B, ld, m, Y.get(), r);
+    std::vector<double> y((size_t)r * m);
+    d2h(ctx, y.data(), Y.get(), y.size() * sizeof(double));
+    for (int j = 0; j < r; ++j)
+      for (int i = 0; i < r; ++i) {
+        double s = 0;
+        for (int l = 0; l < m; ++l) s += y[(size_t)l * r + i] * y[(size_t)l * r + j];
+        Mh[(size_t)j * q + i] = -s;
+      }
+  }
+  for (int i = 0; i < r; ++i) {
+    Mh[(size_t)(r + i) * q + i] = 1.0;
+    Mh[(size_t)i * q + (r + i)] = 1.0;
+  }
+  for (int i = 0; i < p; ++i) Mh[(size_t)(2 * r + i) * q + (2 * r + i)] = 1.0;
+
+  Orth o;
+  rr_orth(ctx, n, F.get(), ld, q, o);
+  const int k = o.k;
+  if (k == 0) return;
+  DBuf<double> M(ctx, (size_t)q * q), TM(ctx, (size_t)k * q), H(ctx, (size_t)k * k), Hs(ctx, (size_t)k * k);
+  h2d(ctx, M.get(), Mh.data(), Mh.size() * sizeof(double));
+  dgemm(ctx, false, false, k, q, q, 1.0, o.T.get(), k, M.get(), q, 0.0, TM.get(), k);
+  dgemm(ctx, false, true, k, k, q, 1.0, TM.get(), k, o.T.get(), k, 0.0, H.get(), k);
+  {
+    const double half = 0.5;
+    ROCBLAS_CHECK(rocblas_dgeam(ctx->blas, rocblas_operation_none, rocblas_operation_transpose, k, k, &half, H.get(),
+                                k, &half, H.get(), k, Hs.get(), k));
+  }
+  std::vector<double> lam;
+  dsyevd(ctx, k, Hs.get(), k, lam);
+  double ss = 0.0, lmax = 0.0;
+  for (double v : lam) {
+    ss += v * v;
+    lmax = std::max(lmax, std::fabs(v));
+  }
+  out.res_fro = std::sqrt(ss);
+  out.lam_max = lmax;
+  const double eta = eta_r_rel * lmax;
+  std::vector<int> selp, selm;
+  std::vector<double> scp, scm;
+  for (int i = k - 1; i >= 0; --i) {
+    const bool pos = eta > 0 ? lam[i] >= eta : lam[i] > 0;
+    if (pos) {
+      selp.push_back(i);
+      scp.push_back(std::sqrt(lam[i]));
+    }
+  }
+  for (int i = 0; i < k; ++i) {
+    const bool neg = eta > 0 ? lam[i] <= -eta : lam[i] < 0;
+    if (neg) {
+      selm.push_back(i);
+      scm.push_back(std::sqrt(-lam[i]));
+    }
+  }
+  out.rp = (int)selp.size();
+  out.rm = (int)selm.size();
+  DBuf<double> coef(ctx, (size_t)k * std::max(1, out.rp + out.rm));
+  if (out.rp) copy_cols<double, double>(ctx, k, out.rp, Hs.get(), k, coef.get(), k, selp.data(), scp.data());
+  if (out.rm)
+    copy_cols<double, double>(ctx, k, out.rm, Hs.get(), k, coef.get() + (int64_t)out.rp * k, k, selm.data(),
+                              scm.data());
+  out.Cp.resize(ctx, (size_t)ld * std::max(1, out.rp));
+  out.Cm.resize(ctx, (size_t)ld * std::max(1, out.rm));
+  if (out.rp) tsgemm(ctx, n, o.U.get(), o.ldu, k, coef.get(), k, out.rp, 1.0, 0.0, out.Cp.get(), ld);
+  if (out.rm)
+    tsgemm(ctx, n, o.U.get(), o.ldu, k, coef.get() + (int64_t)out.rp * k, k, out.rm, 1.0, 0.0, out.Cm.get(), ld);
+  ctx->sync();
+}
+
+// Algorithm 2: G = V Gamma, P = Gamma N Gamma^T = Theta Sigma Theta^T,
+// keep sigma >= eta_s, Z = V Theta+ Sigma+^(1/2).
+void signed_truncate(Ctx* ctx, int64_t n, const double* G, int64_t ldg, int s, const std::vector<double>& sign,
+                     double eta_s_rel, TruncResult& out) {
+  const int64_t ld = pad_ld(n);
+  out.r = 0;
+  out.eta_n = 0.0;
+  if (s <= 0) {
+    out.Z.resize(ctx, ld);
+    return;
+  }
+  Orth o;
+  rr_orth(ctx, n, G, ldg, s, o);
+  const int k = o.k;
+  if (k == 0) {
+    out.Z.resize(ctx, ld);
+    return;
+  }
+  DBuf<double> GN(ctx, (size_t)k * s), P(ctx, (size_t)k * k), Ps(ctx, (size_t)k * k);
+  copy_cols<double, double>(ctx, k, s, o.T.get(), k, GN.get(), k, nullptr, sign.data());
+  dgemm(ctx, false, true, k, k, s, 1.0, GN.get(), k, o.T.get(), k, 0.0, P.get(), k);
+  {
+    const double half = 0.5;
+    ROCBLAS_CHECK(rocblas_dgeam(ctx->blas, rocblas_operation_none, rocblas_operation_transpose, k, k, &half, P.get(),
+                                k, &half, P.get(), k, Ps.get(), k));
+  }
+  std::vector<double> sig;
+  dsyevd(ctx, k, Ps.get(), k, sig);
+  double smax = 0.0, all2 = 0.0, neg2 = 0.0;
+  for (double v : sig) {
+    smax = std::max(smax, std::fabs(v));
+    all2 += v * v;
+    if (v < 0) neg2 += v * v;
+  }
+  out.sig_max = smax;
+  out.eta_n = all2 > 0 ? std::sqrt(neg2 / all2) : 0.0;
+  const double eta = eta_s_rel * smax;
+  std::vector<int> sel;
+  std::vector<double> sc;
+  for (int i = k - 1; i >= 0; --i) {
+    const bool keep = eta > 0 ? sig[i] >= eta : sig[i] > 0;
+    if (keep) {
+      sel.push_back(i);
+      sc.push_back(std::sqrt(sig[i]));
+    }
+  }
+  out.r = (int)sel.size();
+  out.Z.resize(ctx, (size_t)ld * std::max(1, out.r));
+  if (out.r) {
+    DBuf<double> coef(ctx, (size_t)k * out.r);
+    copy_cols<double, double>(ctx, k, out.r, Ps.get(), k, coef.get(), k, sel.data(), sc.data());
+    tsgemm(ctx, n, o.U.get(), o.ldu, k, coef.get(), k, out.r, 1.0, 0.0, out.Z.get(), ld);
+  }
+  ctx->sync();
+}
+
+}  // namespace mpcare

@@ -1,0 +1,33 @@
+// Algorithm 1 (residual factor decomposition) and Algorithm 2 (solution
+// factor decomposition) in FP64 on the GPU.
+#pragma once
+
+#include "dense.hpp"
+#include "sparse.hpp"
+
+namespace mpcare {
+
+struct ResidualFactor {
+  DBuf<double> Cp, Cm;      // n x rp, n x rm, ld = pad_ld(n)
+  int rp = 0, rm = 0;
+  double res_fro = 0.0;     // ||R(Z Z^T)||_F = ||H||_F before truncation
+  double lam_max = 0.0;
+};
+
+// Algorithm 1.  A64: FP64 operator; B (n x m) and Ct = C^T (n x p) FP64 with
+// leading dimension pad_ld(n); Z: n x r (ldz).
+void residual_factor(Ctx* ctx, const SellOp& A64, const double* B, int m, const double* Ct, int p,
+                     const double* Z, int64_t ldz, int r, double eta_r_rel, ResidualFactor& out);
+
+// Algorithm 2 for a general signature: Z Z^T = positive part of G N G^T
+// above eta_s_rel * max|lambda(P)|.  Output Z: n x *r (ld pad_ld(n)).
+struct TruncResult {
+  DBuf<double> Z;
+  int r = 0;
+  double eta_n = 0.0;
+  double sig_max = 0.0;
+};
+void signed_truncate(Ctx* ctx, int64_t n, const double* G, int64_t ldg, int s, const std::vector<double>& sign,
+                     double eta_s_rel, TruncResult& out);
+
+}  // namespace mpcare

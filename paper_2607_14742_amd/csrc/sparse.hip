@@ -1,0 +1,336 @@
+// Set-up of the sparse operator (CSR(A) -> SELL-64 of A^T, per precision)
+// and the launcher of the sparse-product kernel template.
+#include "sparse.hpp"
+
+#include <hipcub/hipcub.hpp>
+
+namespace mpcare {
+
+// ---------------------------------------------------------------------------
+// input validation (before any kernel indexes through the caller's arrays)
+// ---------------------------------------------------------------------------
+__global__ void k_check_rowptr(const int* __restrict__ rp, int64_t n, int64_t nnz, int* __restrict__ bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  const int v = rp[i];
+  bool ok = v >= 0 && v <= nnz;
+  if (i == 0) ok = ok && v == 0;
+  if (i == n) ok = ok && v == nnz;
+  if (i < n) ok = ok && rp[i + 1] >= v;
+  if (!ok) atomicOr(bad, 1);
+}
+
+__global__ void k_check_cols(const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ val,
+                             int64_t n, int* __restrict__ bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int prev = -1;
+  int flag = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const int c = ci[e];
+    if (c < 0 || c >= n) flag |= 2;
+    else if (c <= prev) flag |= 4;
+    prev = c;
+    const double v = val[e];
+    if (!__builtin_isfinite(v)) flag |= 8;
+  }
+  if (flag) atomicOr(bad, flag);
+}
+
+// ---------------------------------------------------------------------------
+// transpose CSR(A) -> CSR(A^T)
+// ---------------------------------------------------------------------------
+__global__ void k_count_cols(const int* __restrict__ ci, int64_t nnz, int* __restrict__ cnt) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) atomicAdd(&cnt[ci[e]], 1);
+}
+
+__global__ void k_scatter_t(const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ val,
+                            int64_t n, const int* __restrict__ rpt, int* __restrict__ fill,
+                            int* __restrict__ ct, double* __restrict__ vt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const int j = ci[e];
+    const int pos = rpt[j] + atomicAdd(&fill[j], 1);
+    ct[pos] = (int)i;
+    vt[pos] = val[e];
+  }
+}
+
+// sort each row of A^T by column index (insertion sort; rows are short)
+__global__ void k_sort_rows(const int* __restrict__ rpt, int64_t n, int* __restrict__ ct, double* __restrict__ vt) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int b = rpt[j], e = rpt[j + 1];
+  for (int u = b + 1; u < e; ++u) {
+    const int c = ct[u];
+    const double v = vt[u];
+    int w = u - 1;
+    while (w >= b && ct[w] > c) {
+      ct[w + 1] = ct[w];
+      vt[w + 1] = vt[w];
+      --w;
+    }
+    ct[w + 1] = c;
+    vt[w + 1] = v;
+  }
+}
+
+// off-diagonal row length of A^T, padded to whole slices
+__global__ void k_slice_width(const int* __restrict__ rpt, const int* __restrict__ ct, int64_t n, int nslices,
+                              int* __restrict__ width) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslices) return;
+  int w = 0;
+  for (int l = 0; l < 64; ++l) {
+    const int64_t i = (int64_t)s * 64 + l;
+    if (i >= n) break;
+    int len = rpt[i + 1] - rpt[i];
+    for (int e = rpt[i]; e < rpt[i + 1]; ++e)
+      if (ct[e] == i) { --len; break; }
+    w = len > w ? len : w;
+  }
+  width[s] = w;
+}
+
+template <typename TV, typename T>
+__global__ void k_fill_sell(const int* __restrict__ rpt, const int* __restrict__ ct, const double* __restrict__ vt,
+                            int64_t n, int nslices, const int* __restrict__ sptr, int* __restrict__ cols,
+                            TV* __restrict__ vals, T* __restrict__ diag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nslices * 64) return;
+  const int s = (int)(i >> 6), lane = (int)(i & 63);
+  const int base = sptr[s], w = sptr[s + 1] - base;
+  int t = 0;
+  double d = 0.0;
+  const int self = (int)(i < n ? i : n - 1);
+  if (i < n) {
+    for (int e = rpt[i]; e < rpt[i + 1]; ++e) {
+      if (ct[e] == i) {
+        d = vt[e];
+      } else {
+        const int64_t o = (int64_t)(base + t) * 64 + lane;
+        cols[o] = ct[e];
+        vals[o] = (TV)vt[e];
+        ++t;
+      }
+    }
+    diag[i] = (T)d;
+  }
+  for (; t < w; ++t) {
+    const int64_t o = (int64_t)(base + t) * 64 + lane;
+    cols[o] = self;
+    vals[o] = (TV)0.0;
+  }
+}
+
+__global__ void k_sumsq(const double* __restrict__ v, int64_t n, double* __restrict__ part) {
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    s += v[e] * v[e];
+  double vv[1] = {s};
+  block_reduce_to<1>(vv, [&](int, double val) { part[blockIdx.x] = val; });
+}
+
+template <typename T>
+static void exclusive_scan(Ctx* ctx, const T* in, T* out, int64_t count) {
+  size_t tmp = 0;
+  HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in, out, (int)count, ctx->stream));
+  DBuf<uint8_t> t(ctx, tmp + 16);
+  HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(t.get(), tmp, in, out, (int)count, ctx->stream));
+}
+
+void build_sell(Ctx* ctx, const care_csr* A, Prec prec, SellOp& op) {
+  if (!A) fail(CARE_ERR_ARG, "A is NULL");
+  const int64_t n = A->n, nnz = A->nnz;
+  if (n < 1 || n >= (int64_t(1) << 31) / 2) fail(CARE_ERR_ARG, "n out of range");
+  if (nnz < 0 || nnz >= (int64_t(1) << 31)) fail(CARE_ERR_ARG, "nnz out of range");
+  if (!A->row_ptr || (nnz > 0 && (!A->col_idx || !A->val))) fail(CARE_ERR_ARG, "CSR pointer is NULL");
+  hipStream_t st = ctx->stream;
+
+  DBuf<int> flag(ctx, 1);
+  dzero(ctx, flag.get(), sizeof(int));
+  hipLaunchKernelGGL(k_check_rowptr, dim3(ceil_div(n + 1, 256)), dim3(256), 0, st, A->row_ptr, n, nnz, flag.get());
+  KERNEL_CHECK();
+  int bad = 0;
+  d2h(ctx, &bad, flag.get(), sizeof(int));
+  if (bad) fail(CARE_ERR_ARG, "CSR row_ptr is not a valid monotone offset array");
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_check_cols, dim3(ceil_div(n, 256)), dim3(256), 0, st, A->row_ptr, A->col_idx, A->val, n,
+                       flag.get());
+    KERNEL_CHECK();
+    d2h(ctx, &bad, flag.get(), sizeof(int));
+    if (bad & 2) fail(CARE_ERR_ARG, "CSR column index out of range");
+    if (bad & 4) fail(CARE_ERR_ARG, "CSR column indices not strictly increasing within a row");
+    if (bad & 8) fail(CARE_ERR_NONFINITE, "A has a NaN or Inf value");
+  }
+
+  // transpose
+  DBuf<int> cnt(ctx, n + 1), rpt(ctx, n + 1), fill(ctx, n);
+  DBuf<int> ct(ctx, nnz ? nnz : 1);
+  DBuf<double> vt(ctx, nnz ? nnz : 1);
+  dzero(ctx, cnt.get(), (n + 1) * sizeof(int));
+  dzero(ctx, fill.get(), n * sizeof(int));
+  if (nnz) {
+    hipLaunchKernelGGL(k_count_cols, dim3(ceil_div(nnz, 256)), dim3(256), 0, st, A->col_idx, nnz, cnt.get());
+    KERNEL_CHECK();
+  }
+  exclusive_scan(ctx, cnt.get(), rpt.get(), n + 1);
+  hipLaunchKernelGGL(k_scatter_t, dim3(ceil_div(n, 256)), dim3(256), 0, st, A->row_ptr, A->col_idx, A->val, n,
+                     rpt.get(), fill.get(), ct.get(), vt.get());
+  KERNEL_CHECK();
+  hipLaunchKernelGGL(k_sort_rows, dim3(ceil_div(n, 256)), dim3(256), 0, st, rpt.get(), n, ct.get(), vt.get());
+  KERNEL_CHECK();
+
+  // slice widths and offsets
+  const int nsl = (int)((n + 63) / 64);
+  DBuf<int> width(ctx, nsl + 1);
+  dzero(ctx, width.get(), (nsl + 1) * sizeof(int));
+  hipLaunchKernelGGL(k_slice_width, dim3(ceil_div(nsl, 256)), dim3(256), 0, st, rpt.get(), ct.get(), n, nsl,
+                     width.get());
+  KERNEL_CHECK();
+  op.sptr.resize(ctx, nsl + 1);
+  exclusive_scan(ctx, width.get(), op.sptr.get(), nsl + 1);
+  int total = 0;
+  d2h(ctx, &total, op.sptr.get() + nsl, sizeof(int));
+
+  op.n = n;
+  op.nnz = nnz;
+  op.nslices = nsl;
+  op.width_total = total;
+  op.prec = prec;
+  const int64_t ents = (int64_t)total * 64;
+  op.cols.resize(ctx, ents ? ents : 1);
+  op.vals.resize(ctx, (ents ? ents : 1) * val_bytes(prec));
+  op.diag.resize(ctx, n * vec_bytes(prec));
+  dim3 g(ceil_div((int64_t)nsl * 64, 256));
+  if (prec == Prec::F64) {
+    hipLaunchKernelGGL((k_fill_sell<double, double>), g, dim3(256), 0, st, rpt.get(), ct.get(), vt.get(), n, nsl,
+                       op.sptr.get(), op.cols.get(), (double*)op.vals.get(), (double*)op.diag.get());
+  } else if (prec == Prec::F32) {
+    hipLaunchKernelGGL((k_fill_sell<float, float>), g, dim3(256), 0, st, rpt.get(), ct.get(), vt.get(), n, nsl,
+                       op.sptr.get(), op.cols.get(), (float*)op.vals.get(), (float*)op.diag.get());
+  } else {
+    hipLaunchKernelGGL((k_fill_sell<bf16, float>), g, dim3(256), 0, st, rpt.get(), ct.get(), vt.get(), n, nsl,
+                       op.sptr.get(), op.cols.get(), (bf16*)op.vals.get(), (float*)op.diag.get());
+  }
+  KERNEL_CHECK();
+
+  // ||A||_F
+  if (nnz) {
+    const int nb = 256;
+    DBuf<double> part(ctx, nb);
+    hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(256), 0, st, A->val, nnz, part.get());
+    KERNEL_CHECK();
+    std::vector<double> h(nb);
+    d2h(ctx, h.data(), part.get(), nb * sizeof(double));
+    double s = 0;
+    for (double v : h) s += v;
+    op.frob = std::sqrt(s);
+  }
+  ctx->sync();
+}
+
+// ---------------------------------------------------------------------------
+// launcher
+// ---------------------------------------------------------------------------
+template <typename TV, typename T, int CP>
+static void launch_cp(hipStream_t st, dim3 g, int mode, bool cplx, const SpmmArgs<T>& a) {
+  if constexpr (CP >= 2) {
+    if (cplx) {
+      if (mode == MODE_PLAIN) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_PLAIN, true>), g, dim3(256), 0, st, a);
+      else if (mode == MODE_BICG_P) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_P, true>), g, dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_S, true>), g, dim3(256), 0, st, a);
+      return;
+    }
+  }
+  if (mode == MODE_PLAIN) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_PLAIN, false>), g, dim3(256), 0, st, a);
+  else if (mode == MODE_BICG_P) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_P, false>), g, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_S, false>), g, dim3(256), 0, st, a);
+}
+
+template <typename TV, typename T>
+static void launch_tv(hipStream_t st, int64_t n, int mode, bool cplx, const SpmmArgs<T>& a) {
+  const int k = a.ncols;
+  int cp = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
+  if (cplx && cp < 2) cp = 2;
+  dim3 g(spmm_rowblocks(n), ceil_div(k, cp));
+  switch (cp) {
+    case 1: launch_cp<TV, T, 1>(st, g, mode, cplx, a); break;
+    case 2: launch_cp<TV, T, 2>(st, g, mode, cplx, a); break;
+    case 4: launch_cp<TV, T, 4>(st, g, mode, cplx, a); break;
+    case 8: launch_cp<TV, T, 8>(st, g, mode, cplx, a); break;
+    default: launch_cp<TV, T, 16>(st, g, mode, cplx, a); break;
+  }
+}
+
+template <typename T>
+int launch_spmm(Ctx* ctx, const SellOp& op, int mode, bool cplx, SpmmArgs<T>& a) {
+  a.n = (int)op.n;
+  a.sptr = op.sptr.get();
+  a.cols = op.cols.get();
+  a.vals = op.vals.get();
+  a.diag = (const T*)op.diag.get();
+  a.nrb = spmm_rowblocks(op.n);
+  if (a.ncols <= 0) return a.nrb;
+  if (cplx && (a.ncols % 2)) fail(CARE_ERR_ARG, "complex panel with an odd number of real columns");
+  SpmmTimer timer(ctx, op, a.ncols);
+  if constexpr (sizeof(T) == 8) {
+    if (op.prec != Prec::F64) fail(CARE_ERR_ARG, "FP64 vectors need the FP64 operator");
+    launch_tv<double, double>(ctx->stream, op.n, mode, cplx, a);
+  } else {
+    if (op.prec == Prec::F32) launch_tv<float, float>(ctx->stream, op.n, mode, cplx, a);
+    else if (op.prec == Prec::BF16) launch_tv<bf16, float>(ctx->stream, op.n, mode, cplx, a);
+    else fail(CARE_ERR_ARG, "FP32 vectors need an FP32 or BF16 operator");
+  }
+  KERNEL_CHECK();
+  return a.nrb;
+}
+
+template int launch_spmm<double>(Ctx*, const SellOp&, int, bool, SpmmArgs<double>&);
+template int launch_spmm<float>(Ctx*, const SellOp&, int, bool, SpmmArgs<float>&);
+
+SpmmTimer::SpmmTimer(Ctx* c, const SellOp& op, int k_real) : ctx(c) {
+  ctx->spmm_calls += 1;
+  ctx->spmm_bytes += op.bytes(k_real);
+  if (ctx->profile) {
+    ev = ctx->event_pair();
+    HIP_CHECK(hipEventRecord(ev.first, ctx->stream));
+  }
+}
+
+SpmmTimer::~SpmmTimer() {
+  if (ctx->profile && ev.first) {
+    (void)hipEventRecord(ev.second, ctx->stream);
+    ctx->pending_events.push_back(ev);
+  }
+}
+
+void spmm_plain(Ctx* ctx, const SellOp& op, double pr, double pi, const void* X, int64_t ldx, int k_real,
+                void* Y, int64_t ldy) {
+  const bool cplx = pi != 0.0;
+  if (op.prec == Prec::F64) {
+    SpmmArgs<double> a;
+    a.ncols = k_real;
+    a.sr = pr;
+    a.si = pi;
+    a.X = (const double*)X;
+    a.ldx = ldx;
+    a.Y = (double*)Y;
+    a.ldy = ldy;
+    launch_spmm<double>(ctx, op, MODE_PLAIN, cplx, a);
+  } else {
+    SpmmArgs<float> a;
+    a.ncols = k_real;
+    a.sr = pr;
+    a.si = pi;
+    a.X = (const float*)X;
+    a.ldx = ldx;
+    a.Y = (float*)Y;
+    a.ldy = ldy;
+    launch_spmm<float>(ctx, op, MODE_PLAIN, cplx, a);
+  }
+}
+
+}  // namespace mpcare

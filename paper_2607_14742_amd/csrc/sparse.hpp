@@ -1,0 +1,66 @@
+// Sparse operator M = A^T + p I used by every shifted solve (Sec. 4).
+//
+// Layout in HBM: A^T is stored once per precision in SELL-64 form (sliced
+// ELLPACK, 64 rows per slice = one wavefront, rows in their original order):
+//   * slice s covers rows [64 s, 64 s + 64); its width w_s is the largest
+//     off-diagonal row length of A^T in the slice;
+//   * entry t of row 64 s + l is at offset (sptr[s] + t) * 64 + l of `cols`
+//     and `vals`, so one wavefront reads 64 consecutive column indices and
+//     values per step (coalesced 256 B / 128 B / 512 B loads);
+//   * padding entries point at the row itself with value 0;
+//   * the diagonal is kept apart in the vector precision (`diag`), so the
+//     shift is applied as (d_i + p) x_i in that precision and the bf16
+//     variant rounds only off-diagonal values.
+// Dense n x k panels (Krylov vectors, ADI factors) are column-major with a
+// leading dimension rounded up to 64 rows.
+#pragma once
+
+#include "common.hpp"
+#include "spmm_kernel.hpp"
+
+namespace mpcare {
+
+struct SellOp {
+  int64_t n = 0, nnz = 0;          // of A
+  int nslices = 0;
+  int64_t width_total = 0;         // sum of slice widths
+  Prec prec = Prec::F64;
+  DBuf<int> sptr;                  // nslices + 1
+  DBuf<int> cols;                  // width_total * 64
+  DBuf<uint8_t> vals;              // width_total * 64 * val_bytes
+  DBuf<uint8_t> diag;              // n * vec_bytes
+  double frob = 0.0;               // ||A||_F (FP64)
+  // algorithmic bytes of one product with k real columns (CSR formula)
+  double bytes(int k) const {
+    return double(nnz) * (double(val_bytes(prec)) + 4.0) + 4.0 * double(n + 1) +
+           2.0 * double(n) * double(k) * double(vec_bytes(prec));
+  }
+};
+
+// Build A^T in SELL-64 form at precision `prec` from the caller's CSR(A).
+void build_sell(Ctx* ctx, const care_csr* A, Prec prec, SellOp& op);
+
+// Y = (A^T + p I) X for k real columns (complex shift: k complex columns in
+// interleaved [re, im] column pairs, i.e. 2k real columns).  X, Y in the
+// operator's vector precision.
+void spmm_plain(Ctx* ctx, const SellOp& op, double pr, double pi, const void* X, int64_t ldx,
+                int k_real, void* Y, int64_t ldy);
+
+// Launch one sparse product in `mode` (see spmm_kernel.hpp) with the panel
+// width picked from the column count; fills grid-dependent fields of `a`
+// (n, sptr, cols, vals, diag, nrb).  Returns the number of row blocks.
+template <typename T>
+int launch_spmm(Ctx* ctx, const SellOp& op, int mode, bool cplx, SpmmArgs<T>& a);
+
+inline int spmm_rowblocks(int64_t n) { return (int)((n + 255) / 256); }
+
+// record the algorithmic traffic of a product (and bracket it with events
+// when profiling is on)
+struct SpmmTimer {
+  Ctx* ctx;
+  std::pair<hipEvent_t, hipEvent_t> ev{};
+  SpmmTimer(Ctx* c, const SellOp& op, int k_real);
+  ~SpmmTimer();
+};
+
+}  // namespace mpcare

@@ -1,0 +1,262 @@
+// SELL-64 sparse-product kernel template (gfx950, wave64).
+//
+// One thread owns one row i of M = A^T + p I and a panel of CP real columns;
+// a wavefront owns one SELL slice, so the column-index and value loads of a
+// step are 64 consecutive entries, and the gathers X[j, c] of a stencil-like
+// matrix are contiguous across lanes because neighbouring rows have
+// neighbouring column indices.  Workgroups (256 rows) are remapped so that
+// consecutive row blocks run on the same XCD and share its L2.
+//
+// The same body serves three input/epilogue modes:
+//   MODE_PLAIN   y = (A^T + p I) x
+//   MODE_BICG_P  BiCGStab search direction formed on the fly:
+//                x~ = r + beta (p - omega v)   (x~ = r on a column's first
+//                iteration); writes p_new = x~, v = M x~, partial <rhat, v>
+//   MODE_BICG_S  x~ = s = r - alpha v formed on the fly; writes s, t = M s,
+//                partials <t, s>, <t, t>
+// With CPLX the panel holds CP/2 complex columns as interleaved (re, im)
+// column pairs; the shift is complex and dots are <u, v> = sum conj(u) v.
+#pragma once
+
+#include "common.hpp"
+
+namespace mpcare {
+
+enum SpmmMode { MODE_PLAIN = 0, MODE_BICG_P = 1, MODE_BICG_S = 2 };
+
+// per-logical-column BiCGStab scalars, KS doubles per column
+enum { KS_RHO = 0, KS_ALPHA = 2, KS_OMEGA = 4, KS_BETA = 6, KS_BNRM2 = 8, KS_RNRM2 = 9, KS_LAST_RHR = 10, KS = 12 };
+// per-logical-column status, KI ints per column
+enum { KI_ACTIVE = 0, KI_ITERS = 1, KI_FLAG = 2, KI = 4 };
+
+template <typename T>
+struct SpmmArgs {
+  int n = 0;
+  int ncols = 0;                 // real columns
+  const int* sptr = nullptr;
+  const int* cols = nullptr;
+  const void* vals = nullptr;
+  const T* diag = nullptr;
+  double sr = 0.0, si = 0.0;     // shift
+  int64_t ld = 0;                // leading dimension of Krylov panels
+  // plain mode
+  const T* X = nullptr;
+  int64_t ldx = 0;
+  T* Y = nullptr;
+  int64_t ldy = 0;
+  // BiCGStab modes
+  const T* r = nullptr;
+  const T* pold = nullptr;
+  const T* vold = nullptr;
+  T* pnew = nullptr;
+  T* vnew = nullptr;
+  const T* rhat = nullptr;
+  int64_t ldrhat = 0;
+  T* s = nullptr;
+  T* t = nullptr;
+  const double* sc = nullptr;
+  const int* st = nullptr;
+  double* part = nullptr;        // [(dot * ncols + col) * nrb + rowblock]
+  int nrb = 0;
+};
+
+template <typename T, typename TV>
+__device__ __forceinline__ T load_val(const TV* p, int64_t e) {
+  return (T)p[e];
+}
+template <>
+__device__ __forceinline__ float load_val<float, bf16>(const bf16* p, int64_t e) {
+  return __bfloat162float(p[e]);
+}
+
+// Reduce NV per-thread values over the 256-thread block in a fixed order
+// (LDS transpose, 16 lanes per value) and hand value k of the block to
+// dst(k, sum) on one lane.
+template <int NV, typename T, typename Dst>
+__device__ __forceinline__ void block_reduce_to(const T (&v)[NV], Dst dst) {
+  constexpr int CH = NV < 16 ? NV : 16;
+  __shared__ T red[CH][257];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k0 = 0; k0 < NV; k0 += CH) {
+#pragma unroll
+    for (int k = 0; k < CH; ++k)
+      if (k0 + k < NV) red[k][tid] = v[k0 + k];
+    __syncthreads();
+    const int nk = (NV - k0) < CH ? (NV - k0) : CH;
+    if (tid < nk * 16) {
+      const int k = tid >> 4, q = tid & 15;
+      T s = (T)0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += red[k][u * 16 + q];
+      s += __shfl_xor(s, 8, 16);
+      s += __shfl_xor(s, 4, 16);
+      s += __shfl_xor(s, 2, 16);
+      s += __shfl_xor(s, 1, 16);
+      if (q == 0) dst(k0 + k, (double)s);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename TV, typename T, int CP, int MODE, bool CPLX>
+__global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
+  constexpr int NDOT = MODE == MODE_PLAIN ? 0 : (MODE == MODE_BICG_P ? 1 : 2);
+  constexpr int NL = CPLX ? CP / 2 : CP;          // logical columns in the panel
+  static_assert(!CPLX || (CP % 2 == 0), "complex panels hold column pairs");
+
+  const int rb = (int)xcd_remap(blockIdx.x, gridDim.x);
+  const int tid = threadIdx.x;
+  const int i = rb * 256 + tid;
+  const int c0 = blockIdx.y * CP;                   // first real column of the panel
+  const int64_t ld = a.ld;
+
+  bool act[NL];
+  bool first[NL];
+  T sA_r[NL], sA_i[NL], sB_r[NL], sB_i[NL];       // mode scalars (beta/omega or alpha)
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int cr = c0 + (CPLX ? 2 * q : q);         // real column of the (re) part
+    const int lc = CPLX ? cr / 2 : cr;              // logical column
+    act[q] = cr < a.ncols;
+    first[q] = false;
+    sA_r[q] = sA_i[q] = sB_r[q] = sB_i[q] = (T)0;
+    if (MODE != MODE_PLAIN && act[q]) {
+      const int* st = a.st + (int64_t)lc * KI;
+      act[q] = st[KI_ACTIVE] != 0;
+      first[q] = st[KI_ITERS] == 0;
+      const double* sc = a.sc + (int64_t)lc * KS;
+      if (MODE == MODE_BICG_P) {
+        sA_r[q] = (T)sc[KS_BETA];
+        sA_i[q] = (T)sc[KS_BETA + 1];
+        sB_r[q] = (T)sc[KS_OMEGA];
+        sB_i[q] = (T)sc[KS_OMEGA + 1];
+      } else if (MODE == MODE_BICG_S) {
+        sA_r[q] = (T)sc[KS_ALPHA];
+        sA_i[q] = (T)sc[KS_ALPHA + 1];
+      }
+    }
+  }
+
+  // input value of logical column q at row j: (re, im)
+  auto input = [&](int q, int64_t j, T& xr, T& xi) {
+    const int cr = c0 + (CPLX ? 2 * q : q);
+    const int64_t o = (int64_t)cr * ld + j;
+    if (MODE == MODE_PLAIN) {
+      xr = a.X[(int64_t)cr * a.ldx + j];
+      xi = CPLX ? a.X[(int64_t)(cr + 1) * a.ldx + j] : (T)0;
+    } else if (MODE == MODE_BICG_P) {
+      if (!CPLX) {
+        const T rv = a.r[o];
+        xr = first[q] ? rv : rv + sA_r[q] * (a.pold[o] - sB_r[q] * a.vold[o]);
+        xi = (T)0;
+      } else {
+        const T rr = a.r[o], ri = a.r[o + ld];
+        if (first[q]) {
+          xr = rr;
+          xi = ri;
+        } else {
+          const T pr = a.pold[o], pi = a.pold[o + ld];
+          const T vr = a.vold[o], vi = a.vold[o + ld];
+          const T ur = pr - (sB_r[q] * vr - sB_i[q] * vi);
+          const T ui = pi - (sB_r[q] * vi + sB_i[q] * vr);
+          xr = rr + (sA_r[q] * ur - sA_i[q] * ui);
+          xi = ri + (sA_r[q] * ui + sA_i[q] * ur);
+        }
+      }
+    } else {  // MODE_BICG_S
+      if (!CPLX) {
+        xr = a.r[o] - sA_r[q] * a.vold[o];
+        xi = (T)0;
+      } else {
+        const T vr = a.vold[o], vi = a.vold[o + ld];
+        xr = a.r[o] - (sA_r[q] * vr - sA_i[q] * vi);
+        xi = a.r[o + ld] - (sA_r[q] * vi + sA_i[q] * vr);
+      }
+    }
+  };
+
+  T acc_r[NL], acc_i[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) acc_r[q] = acc_i[q] = (T)0;
+
+  T dots[NDOT > 0 ? NDOT * CP : 1];
+#pragma unroll
+  for (int k = 0; k < (NDOT > 0 ? NDOT * CP : 1); ++k) dots[k] = (T)0;
+
+  if (i < a.n) {
+    const int s = i >> 6, lane = i & 63;
+    const int beg = a.sptr[s], end = a.sptr[s + 1];
+    const TV* vals = (const TV*)a.vals;
+    for (int t = beg; t < end; ++t) {
+      const int64_t e = (int64_t)t * 64 + lane;
+      const int j = a.cols[e];
+      const T av = load_val<T, TV>(vals, e);
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        if (act[q]) {
+          T xr, xi;
+          input(q, j, xr, xi);
+          acc_r[q] += av * xr;
+          if (CPLX) acc_i[q] += av * xi;
+        }
+      }
+    }
+    const T d = a.diag[i] + (T)a.sr;
+    const T sim = (T)a.si;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      if (!act[q]) continue;
+      T xr, xi;
+      input(q, i, xr, xi);
+      T yr, yi = (T)0;
+      if (!CPLX) {
+        yr = acc_r[q] + d * xr;
+      } else {
+        yr = acc_r[q] + d * xr - sim * xi;
+        yi = acc_i[q] + d * xi + sim * xr;
+      }
+      const int cr = c0 + (CPLX ? 2 * q : q);
+      const int64_t o = (int64_t)cr * ld + i;
+      if (MODE == MODE_PLAIN) {
+        a.Y[(int64_t)cr * a.ldy + i] = yr;
+        if (CPLX) a.Y[(int64_t)(cr + 1) * a.ldy + i] = yi;
+      } else if (MODE == MODE_BICG_P) {
+        a.pnew[o] = xr;
+        a.vnew[o] = yr;
+        const int64_t oh = (int64_t)cr * a.ldrhat + i;
+        if (!CPLX) {
+          dots[q] = a.rhat[oh] * yr;
+        } else {
+          a.pnew[o + ld] = xi;
+          a.vnew[o + ld] = yi;
+          const T hr = a.rhat[oh], hi = a.rhat[oh + a.ldrhat];
+          dots[2 * q] = hr * yr + hi * yi;          // conj(rhat) v
+          dots[2 * q + 1] = hr * yi - hi * yr;
+        }
+      } else {
+        a.s[o] = xr;
+        a.t[o] = yr;
+        if (!CPLX) {
+          dots[q] = yr * xr;                         // <t, s>
+          dots[CP + q] = yr * yr;                    // <t, t>
+        } else {
+          a.s[o + ld] = xi;
+          a.t[o + ld] = yi;
+          dots[2 * q] = yr * xr + yi * xi;           // conj(t) s
+          dots[2 * q + 1] = yr * xi - yi * xr;
+          dots[CP + 2 * q] = yr * yr + yi * yi;      // |t|^2
+          dots[CP + 2 * q + 1] = (T)0;
+        }
+      }
+    }
+  }
+  if constexpr (NDOT > 0) {
+    block_reduce_to<NDOT * CP>(dots, [&](int kk, double val) {
+      const int dot = kk / CP, c = c0 + kk % CP;
+      if (c < a.ncols) a.part[((int64_t)dot * a.ncols + c) * a.nrb + rb] = val;
+    });
+  }
+}
+
+}  // namespace mpcare
