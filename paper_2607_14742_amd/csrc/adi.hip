@@ -2,6 +2,7 @@
 #include "adi.hpp"
 
 #include <cmath>
+#include <cstdlib>
 
 #include "dense.hpp"
 
@@ -202,6 +203,7 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
   std::vector<ShiftCache> cache(shifts.size());
   DBuf<double> dYr(ctx, (size_t)std::max(m, 1) * w), dYi(ctx, (size_t)std::max(m, 1) * w);
   std::vector<double> yr, yi;
+  const bool trace = std::getenv("MPCARE_TRACE") != nullptr;
 
   size_t idx = 0;
   while (out.steps < prm.jmax) {
@@ -240,6 +242,10 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
     const double res = fro_gram(ctx, n, W, ld, w);
     if (!std::isfinite(res)) fail(CARE_ERR_NONFINITE, "LR-ADI residual became non-finite");
     out.res_rel = res / out.res0;
+    if (trace)
+      std::fprintf(stderr, "[lradi] step %d p (%.4e, %.4e) w %d smw %d krylov it %d unconv %d relres %.2e adi res %.3e\n",
+                   out.steps, p.re, p.im, w, smw ? 1 : 0, kr.max_iters, kr.unconverged, kr.worst_relres,
+                   out.res_rel);
     if (out.res_rel > 1e8) fail(CARE_ERR_UNSTABLE, "LR-ADI diverged (is A - B K^T stable?)");
     if (out.res_rel <= prm.tol) break;
   }

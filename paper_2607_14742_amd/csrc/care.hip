@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 namespace mpcare {
@@ -124,16 +125,21 @@ static void stage0(Ctx* ctx, SolveState& S, TruncResult& Zout, care_stats* st, s
       rel = kleinman_residual<T>(ctx, n, W.get(), w, dK.get(), 0) / S.nrm_ctc;
     }
     hist.push_back(rel);
+    if (std::getenv("MPCARE_TRACE"))
+      std::fprintf(stderr, "[stage0] newton %d adi steps %d zcols %d relres %.3e\n", i, lo.steps, zcols, rel);
     if (!std::isfinite(rel)) fail(CARE_ERR_NONFINITE, "initial NLR-ADI residual is not finite");
     if (rel <= S.prm.tau_0 || m == 0) break;
     if (i > 0 && rel / prev > S.prm.stagnation) break;
     prev = rel;
   }
-  // promote to FP64 and compress: positive part above 10 u_s (Alg. 2, N = I)
+  // promote to FP64 (storage precision u) and compress with Algorithm 2
+  // (N = I) at the update threshold eta_s.  A threshold tied to u_s instead
+  // would drop directions whose absence costs ~ ||A|| ||X|| 10 u_s in the
+  // residual, far above what the FP32 factor itself carries.
   DBuf<double> G(ctx, (size_t)ld * std::max(zcols, 1));
   copy_cols<T, double>(ctx, n, zcols, Zb.get(), ld, G.get(), ld);
   std::vector<double> sign(zcols, 1.0);
-  signed_truncate(ctx, n, G.get(), ld, zcols, sign, 10.0 * unit_roundoff(S.prm.prec), Zout);
+  signed_truncate(ctx, n, G.get(), ld, zcols, sign, S.prm.eta_s_rel, Zout);
 }
 
 // one inner correction: LR-ADI on [C+, C-] with A_k = A - B (Z Z^T B)^T in
@@ -271,6 +277,8 @@ void care_solve_impl(Ctx* ctx, const care_csr* A, const double* B, int m, const 
     if (!std::isfinite(rel)) fail(CARE_ERR_NONFINITE, "Riccati residual is not finite");
     hist.push_back(rel);
     last_res = rel;
+    if (std::getenv("MPCARE_TRACE"))
+      std::fprintf(stderr, "[refine] k %d rank %d relres %.3e  C+ %d C- %d\n", k, Z.r, rel, rf.rp, rf.rm);
     if (rel < best) {
       best = rel;
       bestZ.Z.resize(ctx, (size_t)S.ld * std::max(Z.r, 1));

@@ -17,7 +17,13 @@
 
 namespace mpcare {
 
-enum { FLAG_NONE = 0, FLAG_CONVERGED = 1, FLAG_BREAKDOWN = 2, FLAG_NONFINITE = 3 };
+enum { FLAG_NONE = 0, FLAG_CONVERGED = 1, FLAG_BREAKDOWN = 2, FLAG_NONFINITE = 3, FLAG_STAGNATED = 4, FLAG_DIVERGED = 5 };
+// a column stops when its residual norm has not dropped by 10 % for
+// STALL_MAX iterations (the attainable accuracy of the working precision is
+// reached), or when it exceeds 1e3 x the smallest residual met (divergence);
+// it then returns the best checkpointed iterate
+constexpr int STALL_MAX = 200;
+constexpr double DIVERGE_RR = 1e6;
 enum { UPD_INIT = 0, UPD_XR = 1 };
 
 template <typename T>
@@ -152,7 +158,11 @@ __global__ void __launch_bounds__(64) k_bicg_scalar(double* __restrict__ scv, in
       sc[KS_RNRM2] = bb;
       sc[KS_RHO] = bb;              // <rhat, r0> = ||b||^2
       sc[KS_OMEGA] = 1.0;
+      sc[KS_RMIN] = bb;
+      sc[KS_RREF] = bb;
+      sc[KS_RCKPT] = bb;            // the checkpoint starts as x0 = 0
       st[KI_ITERS] = 0;
+      st[KI_STALL] = 0;
       const bool ok = finite_d(bb);
       st[KI_ACTIVE] = (ok && bb > 0.0) ? 1 : 0;
       st[KI_FLAG] = ok ? (bb > 0.0 ? FLAG_NONE : FLAG_CONVERGED) : FLAG_NONFINITE;
@@ -218,6 +228,24 @@ __global__ void __launch_bounds__(64) k_bicg_scalar(double* __restrict__ scv, in
       st[KI_FLAG] = FLAG_CONVERGED;
       return;
     }
+    const double rmin = sc[KS_RMIN];
+    if (rr < 0.81 * sc[KS_RREF]) {      // norm dropped by 10 % since the reference
+      st[KI_STALL] = 0;
+      sc[KS_RREF] = rr;
+    } else {
+      st[KI_STALL] += 1;
+    }
+    if (rr < rmin) sc[KS_RMIN] = rr;
+    if (rr > DIVERGE_RR * rmin) {
+      st[KI_ACTIVE] = 0;
+      st[KI_FLAG] = FLAG_DIVERGED;
+      return;
+    }
+    if (st[KI_STALL] > STALL_MAX) {
+      st[KI_ACTIVE] = 0;
+      st[KI_FLAG] = FLAG_STAGNATED;
+      return;
+    }
     const double wr = sc[KS_OMEGA], wi = sc[KS_OMEGA + 1];
     if (wr == 0.0 && wi == 0.0) {
       st[KI_ACTIVE] = 0;
@@ -246,6 +274,49 @@ __global__ void __launch_bounds__(64) k_bicg_scalar(double* __restrict__ scv, in
     sc[KS_RHO] = rhr;
     sc[KS_RHO + 1] = rhi;
   }
+}
+
+// Checkpoint (RESTORE = false): active columns whose current residual is the
+// smallest checkpointed so far copy x -> xb.  Restore (RESTORE = true):
+// columns stopped without convergence whose checkpoint is better copy
+// xb -> x.  The per-column decision reads scalars that only this launch's
+// first row block changes, and only towards an equal value, so every block
+// takes the same decision.
+template <typename T, bool RESTORE, bool CPLX>
+__global__ void __launch_bounds__(256) k_bicg_ckpt(int n, int ncols, T* __restrict__ x, int64_t ldx,
+                                                   T* __restrict__ xb, int64_t ld, double* __restrict__ scv,
+                                                   const int* __restrict__ stv) {
+  const int c = blockIdx.y;
+  const int lc = CPLX ? c / 2 : c;
+  double* sc = scv + (int64_t)lc * KS;
+  const int* st = stv + (int64_t)lc * KI;
+  const double rr = sc[KS_RNRM2], rk = sc[KS_RCKPT];
+  bool go;
+  if (!RESTORE) {
+    go = st[KI_ACTIVE] != 0 && rr <= rk;
+  } else {
+    const int f = st[KI_FLAG];
+    go = f != FLAG_CONVERGED && rk < rr;
+  }
+  if (!go) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    if (!RESTORE) xb[(int64_t)c * ld + i] = x[(int64_t)c * ldx + i];
+    else x[(int64_t)c * ldx + i] = xb[(int64_t)c * ld + i];
+  }
+  if (!RESTORE && blockIdx.x == 0 && threadIdx.x == 0 && (!CPLX || (c % 2) == 0)) sc[KS_RCKPT] = rr;
+}
+
+template <typename T, bool RESTORE>
+static void ckpt(Ctx* ctx, bool cplx, int n, int ncols, T* x, int64_t ldx, T* xb, int64_t ld, double* sc,
+                 const int* st) {
+  dim3 g(ceil_div(n, 256), ncols);
+  if (cplx)
+    hipLaunchKernelGGL((k_bicg_ckpt<T, RESTORE, true>), g, dim3(256), 0, ctx->stream, n, ncols, x, ldx, xb, ld, sc, st);
+  else
+    hipLaunchKernelGGL((k_bicg_ckpt<T, RESTORE, false>), g, dim3(256), 0, ctx->stream, n, ncols, x, ldx, xb, ld, sc,
+                       st);
+  KERNEL_CHECK();
 }
 
 template <typename T, int CP, int UMODE, bool CPLX>
@@ -289,12 +360,14 @@ KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncol
   if (cplx && (ncols % 2)) fail(CARE_ERR_ARG, "complex solve needs an even number of real columns");
   const int64_t n = op.n;
   const int64_t ld = pad_ld(n);
-  const bool trace = std::getenv("MPCARE_TRACE") != nullptr;
+  const char* tr_env = std::getenv("MPCARE_TRACE");
+  const bool trace = tr_env && std::atoi(tr_env) >= 2;
   const int nl = cplx ? ncols / 2 : ncols;
   const int nrb = spmm_rowblocks(n);
   const size_t panel = (size_t)ld * ncols;
   DBuf<T> r(ctx, panel), P0(ctx, panel), P1(ctx, panel), V0(ctx, panel), V1(ctx, panel), S(ctx, panel),
-      Tt(ctx, panel);
+      Tt(ctx, panel), Xb(ctx, panel);
+  dzero(ctx, Xb.get(), panel * sizeof(T));
   DBuf<double> part(ctx, (size_t)2 * ncols * nrb);
   DBuf<double> sc(ctx, (size_t)nl * KS);
   DBuf<int> st(ctx, (size_t)nl * KI);
@@ -376,6 +449,7 @@ KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncol
     ++it;
 
     if (it >= next_check || it >= maxit) {
+      ckpt<T, false>(ctx, cplx, (int)n, ncols, x, ldx, Xb.get(), ld, sc.get(), st.get());
       d2h(ctx, hst.data(), st.get(), hst.size() * sizeof(int));
       int active = 0;
       for (int c = 0; c < nl; ++c) active += hst[(size_t)c * KI + KI_ACTIVE];
@@ -383,6 +457,8 @@ KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncol
       next_check = it + check_every;
     }
   }
+  // columns that stopped without converging fall back to their best checkpoint
+  ckpt<T, true>(ctx, cplx, (int)n, ncols, x, ldx, Xb.get(), ld, sc.get(), st.get());
   std::vector<double> hsc((size_t)nl * KS);
   d2h(ctx, hsc.data(), sc.get(), hsc.size() * sizeof(double));
   d2h(ctx, hst.data(), st.get(), hst.size() * sizeof(int));
@@ -391,7 +467,8 @@ KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncol
     const double* v = &hsc[(size_t)c * KS];
     res.max_iters = std::max(res.max_iters, s[KI_ITERS]);
     ctx->krylov_iters += s[KI_ITERS];
-    const double rel = v[KS_BNRM2] > 0 ? std::sqrt(v[KS_RNRM2] / v[KS_BNRM2]) : 0.0;
+    const double rfin = s[KI_FLAG] == FLAG_CONVERGED ? v[KS_RNRM2] : std::min(v[KS_RNRM2], v[KS_RCKPT]);
+    const double rel = v[KS_BNRM2] > 0 ? std::sqrt(rfin / v[KS_BNRM2]) : 0.0;
     res.worst_relres = std::max(res.worst_relres, rel);
     if (s[KI_FLAG] == FLAG_NONFINITE) fail(CARE_ERR_NONFINITE, "non-finite value in the Krylov iteration");
     if (s[KI_FLAG] != FLAG_CONVERGED) {

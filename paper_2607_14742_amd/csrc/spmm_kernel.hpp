@@ -25,9 +25,14 @@ namespace mpcare {
 enum SpmmMode { MODE_PLAIN = 0, MODE_BICG_P = 1, MODE_BICG_S = 2 };
 
 // per-logical-column BiCGStab scalars, KS doubles per column
-enum { KS_RHO = 0, KS_ALPHA = 2, KS_OMEGA = 4, KS_BETA = 6, KS_BNRM2 = 8, KS_RNRM2 = 9, KS_LAST_RHR = 10, KS = 12 };
-// per-logical-column status, KI ints per column
-enum { KI_ACTIVE = 0, KI_ITERS = 1, KI_FLAG = 2, KI = 4 };
+// (RMIN: smallest ||r||^2 met; RCKPT: ||r||^2 of the checkpointed iterate)
+enum {
+  KS_RHO = 0, KS_ALPHA = 2, KS_OMEGA = 4, KS_BETA = 6, KS_BNRM2 = 8, KS_RNRM2 = 9, KS_LAST_RHR = 10,
+  KS_RMIN = 11, KS_RCKPT = 12, KS_RREF = 13, KS = 16
+};
+// per-logical-column status, KI ints per column (STALL: iterations since the
+// residual norm last dropped by 10 %)
+enum { KI_ACTIVE = 0, KI_ITERS = 1, KI_FLAG = 2, KI_STALL = 3, KI = 4 };
 
 template <typename T>
 struct SpmmArgs {
