@@ -17,9 +17,11 @@
  *  * Dense matrices are column-major FP64 with a leading dimension >= n.
  *    C is passed as stored by the problem statement, p x n ROW-major, which is
  *    the same bytes as C^T column-major n x p with leading dimension n.
- *  * Work is ordered on the context's HIP stream (given at creation).  Every
- *    call returns after its device work has completed, because the method
- *    takes host-side decisions (convergence checks, eigenvalue splits).
+ *  * Each call starts after the work already queued on the stream given at
+ *    context creation, runs on the context's own non-blocking stream (so
+ *    that Krylov iterations can be replayed as HIP graphs), and returns after
+ *    its device work has completed, because the method takes host-side
+ *    decisions (convergence checks, eigenvalue splits).
  *  * Every function returns care_status: 0 = OK, > 0 = warning (outputs are
  *    valid), < 0 = error.  On an error the outputs are unspecified, except for
  *    CARE_ERR_CAPACITY, where *r_out (or *rp/*rm) holds the number of columns
@@ -92,11 +94,12 @@ typedef struct {
   double tau_L;           /* inner LR-ADI stop ||W^T W||_F <= tau_L ||W0^T W0||_F;
                              <= 0 selects 1e-12 (FP64) / 1e-5 (FP32) / 1e-2 (BF16)    */
   double tau_0;           /* initial NLR-ADI stop on the relative Riccati residual;
-                             <= 0 selects max(tol, 10 tau_L)                          */
+                             <= 0 selects max(tol / 10, 10 tau_L)                     */
   double stagnation;      /* stop when ||R_{k+1}|| / ||R_k|| > stagnation (0.999)     */
   int32_t krylov_maxit;   /* BiCGStab iteration cap per shifted solve (4000)          */
-  double krylov_tol;      /* per-column relative residual; <= 0 selects 1e-5 for
-                             FP32/BF16 and 1e-10 for FP64                             */
+  double krylov_tol;      /* per-column relative residual; <= 0 selects 1e-10 (FP64),
+                             1e-7 (FP32) or 1e-3 (BF16 products).  Columns that
+                             stagnate above it are restarted on their true residual */
   int32_t check_every;    /* host convergence poll period of the Krylov loop (8)      */
   int32_t penzl_l0;       /* auto shifts: number of shifts (16)                       */
   int32_t penzl_kp;       /* auto shifts: Arnoldi steps on A^T (20)                   */
@@ -106,6 +109,10 @@ typedef struct {
                              skips the initial NLR-ADI solve (resume)               */
   int64_t ldz_init;
   int32_t r_init;
+  int32_t adi_deflate;    /* 1: LR-ADI stops iterating columns of W whose residual
+                             is negligible for the stopping test (default 1)       */
+  int32_t krylov_block_tol; /* 1: Krylov accuracy relative to the largest column of
+                             the right-hand side block instead of each column (0)  */
 } care_opts;
 
 /* Statistics written by the solvers (host struct). */

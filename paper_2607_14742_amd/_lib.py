@@ -36,6 +36,7 @@ class care_opts(C.Structure):
         ("stagnation", C.c_double), ("krylov_maxit", C.c_int32), ("krylov_tol", C.c_double),
         ("check_every", C.c_int32), ("penzl_l0", C.c_int32), ("penzl_kp", C.c_int32), ("penzl_km", C.c_int32),
         ("profile", C.c_int32), ("Z_init", C.c_void_p), ("ldz_init", C.c_int64), ("r_init", C.c_int32),
+        ("adi_deflate", C.c_int32), ("krylov_block_tol", C.c_int32),
     ]
 
 

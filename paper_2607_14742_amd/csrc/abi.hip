@@ -32,9 +32,14 @@ care_status guarded(F&& f) {
   }
 }
 
+// Every entry point runs on the context's own non-blocking stream (graph
+// capture is not possible on the legacy default stream), ordered after the
+// work already queued on the caller's stream.
 Ctx* unwrap(care_ctx* c) {
   if (!c) fail(CARE_ERR_ARG, "context is NULL");
   HIP_CHECK(hipSetDevice(c->c.device));
+  HIP_CHECK(hipEventRecord(c->c.order_event, c->c.user_stream));
+  HIP_CHECK(hipStreamWaitEvent(c->c.stream, c->c.order_event, 0));
   return &c->c;
 }
 
@@ -73,6 +78,8 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->Z_init = nullptr;
   o->ldz_init = 0;
   o->r_init = 0;
+  o->adi_deflate = 1;
+  o->krylov_block_tol = 0;
 }
 
 care_status care_ctx_create(care_ctx** out, int32_t device, void* stream) {
@@ -85,7 +92,9 @@ care_status care_ctx_create(care_ctx** out, int32_t device, void* stream) {
     HIP_CHECK(hipSetDevice(device));
     care_ctx* c = new care_ctx();
     c->c.device = device;
-    c->c.stream = (hipStream_t)stream;
+    c->c.user_stream = (hipStream_t)stream;
+    HIP_CHECK(hipStreamCreateWithFlags(&c->c.stream, hipStreamNonBlocking));   // default priority
+    HIP_CHECK(hipEventCreateWithFlags(&c->c.order_event, hipEventDisableTiming));
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
       c->c.num_cu = prop.multiProcessorCount;
@@ -116,6 +125,8 @@ void care_ctx_destroy(care_ctx* c) {
   if (c->c.blas) rocblas_destroy_handle(c->c.blas);
   delete c->c.arena;
   if (c->c.pinned) (void)hipHostFree(c->c.pinned);
+  if (c->c.order_event) (void)hipEventDestroy(c->c.order_event);
+  if (c->c.stream) (void)hipStreamDestroy(c->c.stream);
   delete c;
 }
 
@@ -258,6 +269,7 @@ care_status lyap_lradi(care_ctx* cx, const care_csr* A, const double* B, const d
     lp.ktol = r.ktol;
     lp.kmaxit = r.kmaxit;
     lp.check_every = r.check_every;
+    lp.deflate = false;      // keep the documented block layout of Z
     ctx->reset_counters();
     ctx->profile = o->profile;
     const double t0 = now_s();

@@ -1,6 +1,7 @@
 // LR-ADI driver and its fused update kernel.
 #include "adi.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 
@@ -101,14 +102,17 @@ __global__ void __launch_bounds__(256) k_adi_update(int64_t n, int w, int m, int
   }
 }
 
+// ||W^T W||_F and the squared column norms of W
 template <typename T>
-static double fro_gram(Ctx* ctx, int64_t n, const T* W, int64_t ld, int w) {
+static double gram_stats(Ctx* ctx, int64_t n, const T* W, int64_t ld, int w, std::vector<double>& colnorm2) {
   DBuf<double> G(ctx, (size_t)w * w);
   gram(ctx, n, W, ld, w, W, ld, w, G.get(), w);
   std::vector<double> h((size_t)w * w);
   d2h(ctx, h.data(), G.get(), h.size() * sizeof(double));
   double s = 0;
   for (double v : h) s += v * v;
+  colnorm2.resize(w);
+  for (int c = 0; c < w; ++c) colnorm2[c] = h[(size_t)c * w + c];
   return std::sqrt(s);
 }
 
@@ -142,8 +146,10 @@ static KrylovResult smw_step(Ctx* ctx, const SellOp& op, const T* B, const T* K,
     copy_cols<T, T>(ctx, n, 2 * w, W, ld, rhs, ld, map.data());
     if (need_s) copy_cols<T, T>(ctx, n, 2 * m, K, ld, rhs + (int64_t)2 * w * ld, ld, map.data());
   }
+  std::vector<int> groups(nrhs, 0);
+  for (int c = w; c < nrhs; ++c) groups[c] = 1;     // the K columns form their own group
   KrylovResult kr = bicgstab<T>(ctx, op, p.re, p.im, (cp ? 2 : 1) * nrhs, rhs, ld, sol, ld, prm.ktol, prm.kmaxit,
-                                prm.check_every);
+                                prm.check_every, prm.group_tol ? &groups : nullptr);
   yr.assign((size_t)std::max(m, 1) * w, 0.0);
   yi.assign((size_t)std::max(m, 1) * w, 0.0);
   if (!smw) return kr;
@@ -194,37 +200,48 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
   if (w <= 0) return out;
   if (shifts.empty()) fail(CARE_ERR_ARG, "empty shift set");
   const bool smw = K != nullptr && m > 0;
-  out.res0 = fro_gram(ctx, n, W, ld, w);
+  std::vector<double> cn;
+  out.res0 = gram_stats(ctx, n, W, ld, w, cn);
   if (!std::isfinite(out.res0)) fail(CARE_ERR_NONFINITE, "non-finite right-hand side factor");
   if (out.res0 == 0.0) return out;
 
   const int maxcols = smw ? w + m : w;
-  DBuf<T> rhs(ctx, (size_t)ld * 2 * maxcols), sol(ctx, (size_t)ld * 2 * maxcols);
+  DBuf<T> rhs(ctx, (size_t)ld * 2 * maxcols), sol(ctx, (size_t)ld * 2 * maxcols), tmp(ctx, (size_t)ld);
   std::vector<ShiftCache> cache(shifts.size());
   DBuf<double> dYr(ctx, (size_t)std::max(m, 1) * w), dYi(ctx, (size_t)std::max(m, 1) * w);
   std::vector<double> yr, yi;
   const bool trace = std::getenv("MPCARE_TRACE") != nullptr;
+  // Column deflation: ADI acts on each column of W independently.  The
+  // columns kept at the front (physical 0 .. wa-1) are iterated; a column is
+  // frozen once its squared norm, added to those already frozen, stays below
+  // a quarter of the stopping level tau_L ||W0^T W0||_F, so the frozen part
+  // alone can never keep the stopping test from being met.
+  std::vector<int> perm(w);
+  for (int c = 0; c < w; ++c) perm[c] = c;
+  int wa = w;
+  double frozen = 0.0;
+  const double budget = prm.deflate ? 0.25 * prm.tol * out.res0 : 0.0;
 
   size_t idx = 0;
-  while (out.steps < prm.jmax) {
+  while (out.steps < prm.jmax && wa > 0) {
     const Shift p = shifts[idx % shifts.size()];
     ShiftCache& sc = cache[idx % shifts.size()];
     const bool cp = p.im != 0.0;
-    const int width = (cp ? 2 : 1) * w;
+    const int width = (cp ? 2 : 1) * wa;
     if (out.zcols + width > zcap) fail(CARE_ERR_CAPACITY, "LR-ADI factor buffer too small");
-    KrylovResult kr = smw_step<T>(ctx, op, B, K, m, W, w, p, sc, prm, rhs.get(), sol.get(), yr, yi);
+    KrylovResult kr = smw_step<T>(ctx, op, B, K, m, W, wa, p, sc, prm, rhs.get(), sol.get(), yr, yi);
     out.krylov_unconverged += kr.unconverged;
     out.krylov_max_iters = std::max(out.krylov_max_iters, kr.max_iters);
     if (smw) {
-      h2d(ctx, dYr.get(), yr.data(), (size_t)m * w * sizeof(double));
-      if (cp) h2d(ctx, dYi.get(), yi.data(), (size_t)m * w * sizeof(double));
+      h2d(ctx, dYr.get(), yr.data(), (size_t)m * wa * sizeof(double));
+      if (cp) h2d(ctx, dYi.get(), yi.data(), (size_t)m * wa * sizeof(double));
     }
     T* Zb = Z + (int64_t)out.zcols * ld;
-    dim3 g(ceil_div(n, 256), w);
+    dim3 g(ceil_div(n, 256), wa);
     const T* Sp = smw ? (const T*)sc.S.get() : nullptr;
     if (!cp) {
       const double z1 = std::sqrt(-2.0 * p.re);
-      hipLaunchKernelGGL((k_adi_update<T, false>), g, dim3(256), 0, ctx->stream, n, w, smw ? m : 0, ld,
+      hipLaunchKernelGGL((k_adi_update<T, false>), g, dim3(256), 0, ctx->stream, n, wa, smw ? m : 0, ld,
                          (const T*)sol.get(), Sp, dYr.get(), dYi.get(), W, Zb, 2.0 * p.re, z1, 0.0, 0.0);
       out.steps += 1;
       idx += 1;
@@ -232,23 +249,56 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
       const double delta = p.re / p.im;
       const double gam = std::sqrt(-2.0 * p.re);
       const double z1 = std::sqrt(2.0) * gam, z2 = std::sqrt(2.0) * gam * std::sqrt(delta * delta + 1.0);
-      hipLaunchKernelGGL((k_adi_update<T, true>), g, dim3(256), 0, ctx->stream, n, w, smw ? m : 0, ld,
+      hipLaunchKernelGGL((k_adi_update<T, true>), g, dim3(256), 0, ctx->stream, n, wa, smw ? m : 0, ld,
                          (const T*)sol.get(), Sp, dYr.get(), dYi.get(), W, Zb, 4.0 * p.re, z1, z2, delta);
       out.steps += 2;
       idx += 2;
     }
     KERNEL_CHECK();
     out.zcols += width;
-    const double res = fro_gram(ctx, n, W, ld, w);
+    for (int rep = 0; rep < (cp ? 2 : 1); ++rep)
+      for (int c = 0; c < wa; ++c) out.zsrc.push_back(perm[c]);
+    const double res = gram_stats(ctx, n, W, ld, w, cn);
     if (!std::isfinite(res)) fail(CARE_ERR_NONFINITE, "LR-ADI residual became non-finite");
     out.res_rel = res / out.res0;
     if (trace)
-      std::fprintf(stderr, "[lradi] step %d p (%.4e, %.4e) w %d smw %d krylov it %d unconv %d relres %.2e adi res %.3e\n",
-                   out.steps, p.re, p.im, w, smw ? 1 : 0, kr.max_iters, kr.unconverged, kr.worst_relres,
+      std::fprintf(stderr,
+                   "[lradi] step %d p (%.4e, %.4e) w %d smw %d krylov it %d unconv %d relres %.2e adi res %.3e\n",
+                   out.steps, p.re, p.im, wa, smw ? 1 : 0, kr.max_iters, kr.unconverged, kr.worst_relres,
                    out.res_rel);
     if (out.res_rel > 1e8) fail(CARE_ERR_UNSTABLE, "LR-ADI diverged (is A - B K^T stable?)");
     if (out.res_rel <= prm.tol) break;
+    if (budget > 0.0) {
+      // freeze the smallest active columns while the frozen budget allows
+      std::vector<int> order(wa);
+      for (int c = 0; c < wa; ++c) order[c] = c;
+      std::sort(order.begin(), order.end(), [&](int a, int b) { return cn[a] < cn[b]; });
+      std::vector<char> freeze(wa, 0);
+      for (int c : order) {
+        if (frozen + cn[c] > budget) break;
+        frozen += cn[c];
+        freeze[c] = 1;
+      }
+      // compact: move frozen columns behind the active ones
+      int lo = 0, hi = wa - 1;
+      while (true) {
+        while (lo <= hi && !freeze[lo]) ++lo;
+        while (hi >= lo && freeze[hi]) --hi;
+        if (lo >= hi) break;
+        d2d(ctx, tmp.get(), W + (int64_t)lo * ld, n * sizeof(T));
+        d2d(ctx, W + (int64_t)lo * ld, W + (int64_t)hi * ld, n * sizeof(T));
+        d2d(ctx, W + (int64_t)hi * ld, tmp.get(), n * sizeof(T));
+        std::swap(perm[lo], perm[hi]);
+        std::swap(freeze[lo], freeze[hi]);
+        ++lo;
+        --hi;
+      }
+      int na = 0;
+      for (int c = 0; c < wa; ++c) na += freeze[c] ? 0 : 1;
+      wa = na;   // the cached S = M^{-1} K and T^{-1} do not depend on W
+    }
   }
+  out.w_final = wa;
   return out;
 }
 

@@ -28,6 +28,8 @@ struct LradiParams {
   double ktol = 1e-10;       // Krylov relative residual per column
   int kmaxit = 4000;
   int check_every = 8;
+  bool deflate = true;       // freeze converged columns of W (see lradi_run)
+  bool group_tol = true;     // Krylov accuracy relative to the block's largest column
 };
 
 struct LradiOut {
@@ -37,6 +39,8 @@ struct LradiOut {
   double res0 = 0.0;         // ||W0^T W0||_F
   int krylov_unconverged = 0;
   int krylov_max_iters = 0;
+  int w_final = 0;           // columns still iterated at the end
+  std::vector<int> zsrc;     // column of W0 that each column of Z comes from
 };
 
 // shift list checks: Re < 0, complex shifts as (p, conj p) with Im p > 0 first

@@ -20,10 +20,15 @@ Resolved resolve_opts(const care_opts* o, double tol) {
   if (!o) o = &d;
   r.prec = prec_from_abi(o->inner_prec);
   const double tl_def = r.prec == Prec::F64 ? 1e-12 : (r.prec == Prec::F32 ? 1e-5 : 1e-3);
-  const double kt_def = r.prec == Prec::F64 ? 1e-10 : (r.prec == Prec::F32 ? 1e-5 : 1e-3);
+  // Krylov tolerance: 1e-10 (FP64) as in Sec. 5; FP32 uses 1e-7 instead of
+  // the paper's 1e-5 (unpreconditioned BiCGStab: the tighter inner solves
+  // leave a smaller, narrower residual and save refinement work)
+  const double kt_def = r.prec == Prec::F64 ? 1e-10 : (r.prec == Prec::F32 ? 1e-7 : 1e-3);
   r.tau_L = o->tau_L > 0 ? o->tau_L : tl_def;
   r.ktol = o->krylov_tol > 0 ? o->krylov_tol : kt_def;
-  r.tau_0 = o->tau_0 > 0 ? o->tau_0 : std::max(tol, 10.0 * r.tau_L);
+  // the initial solve's residual estimate ignores the inner solves' own
+  // errors, so it is asked for a tenth of the final tolerance
+  r.tau_0 = o->tau_0 > 0 ? o->tau_0 : std::max(0.1 * tol, 10.0 * r.tau_L);
   r.eta_r_rel = o->eta_r_rel;
   r.eta_s_rel = o->eta_s_rel;
   r.stagnation = o->stagnation > 0 ? o->stagnation : 0.999;
@@ -32,6 +37,8 @@ Resolved resolve_opts(const care_opts* o, double tol) {
   r.j_max = o->j_max;
   r.kmaxit = o->krylov_maxit > 0 ? o->krylov_maxit : 4000;
   r.check_every = o->check_every > 0 ? o->check_every : 8;
+  r.deflate = o->adi_deflate != 0;
+  r.block_tol = o->krylov_block_tol != 0;
   if (r.k_max < 1 || r.k0_max < 1 || r.j_max < 1) fail(CARE_ERR_ARG, "k_max, k0_max and j_max must be >= 1");
   if (r.eta_r_rel < 0 || r.eta_s_rel < 0) fail(CARE_ERR_ARG, "truncation thresholds must be >= 0");
   return r;
@@ -100,6 +107,8 @@ static void stage0(Ctx* ctx, SolveState& S, TruncResult& Zout, care_stats* st, s
   lp.ktol = S.prm.ktol;
   lp.kmaxit = S.prm.kmaxit;
   lp.check_every = S.prm.check_every;
+  lp.deflate = S.prm.deflate;
+  lp.group_tol = S.prm.block_tol;
   double prev = 0.0;
   int zcols = 0;
   for (int i = 0; i < S.prm.k0_max; ++i) {
@@ -172,6 +181,8 @@ static void correction(Ctx* ctx, SolveState& S, const TruncResult& Zk, const Res
   lp.ktol = S.prm.ktol;
   lp.kmaxit = S.prm.kmaxit;
   lp.check_every = S.prm.check_every;
+  lp.deflate = S.prm.deflate;
+  lp.group_tol = S.prm.block_tol;
   LradiOut lo = lradi_run<T>(ctx, *S.As, Bs.get(), (m > 0 && Zk.r > 0) ? Ks.get() : nullptr, m, W.get(), w,
                              S.shifts, lp, Zb.get(), zcap);
   st->iter_inner += lo.steps;
@@ -179,7 +190,7 @@ static void correction(Ctx* ctx, SolveState& S, const TruncResult& Zk, const Res
   Zpm.resize(ctx, (size_t)ld * std::max(zcols, 1));
   copy_cols<T, double>(ctx, n, zcols, Zb.get(), ld, Zpm.get(), ld);
   sign.assign(zcols, 1.0);
-  for (int c = 0; c < zcols; ++c) sign[c] = (c % w) < rf.rp ? 1.0 : -1.0;
+  for (int c = 0; c < zcols; ++c) sign[c] = lo.zsrc[c] < rf.rp ? 1.0 : -1.0;
 }
 
 static double fro_of_gram(Ctx* ctx, int64_t n, const double* X, int64_t ld, int k) {

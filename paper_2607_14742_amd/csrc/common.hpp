@@ -87,7 +87,9 @@ class Arena {
 // ----------------------------------------------------------------------------
 struct Ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;        // the library's own stream (non-blocking)
+  hipStream_t user_stream = nullptr;   // the caller's stream: calls are ordered after it
+  hipEvent_t order_event = nullptr;
   rocblas_handle blas = nullptr;
   Arena* arena = nullptr;
   void* pinned = nullptr;          // small pinned host staging buffer

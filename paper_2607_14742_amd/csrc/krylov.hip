@@ -14,15 +14,19 @@
 #include "krylov.hpp"
 
 #include <cstdlib>
+#include <map>
+
+#include "dense.hpp"
 
 namespace mpcare {
 
 enum { FLAG_NONE = 0, FLAG_CONVERGED = 1, FLAG_BREAKDOWN = 2, FLAG_NONFINITE = 3, FLAG_STAGNATED = 4, FLAG_DIVERGED = 5 };
 // a column stops when its residual norm has not dropped by 10 % for
-// STALL_MAX iterations (the attainable accuracy of the working precision is
-// reached), or when it exceeds 1e3 x the smallest residual met (divergence);
-// it then returns the best checkpointed iterate
-constexpr int STALL_MAX = 200;
+// max(STALL_MAX, iterations / 4) iterations (the attainable accuracy of the
+// working precision is reached, or BiCGStab stagnates; see the restarts),
+// or when it exceeds 1e3 x the smallest residual met (divergence); it then
+// returns the best checkpointed iterate
+constexpr int STALL_MAX = 150;
 constexpr double DIVERGE_RR = 1e6;
 enum { UPD_INIT = 0, UPD_XR = 1 };
 
@@ -113,14 +117,36 @@ __global__ void __launch_bounds__(256) k_bicg_elem(ElemArgs<T> a) {
 
 // sum of the row-block partials of (dot, real column c): one wavefront,
 // fixed order
+// (SCALAR_THREADS threads; four independent loads in flight per thread, then
+// a fixed-order tree: the result is the same on every thread)
+constexpr int SCALAR_THREADS = 256;
 __device__ __forceinline__ double wave_sum_partials(const double* __restrict__ part, int ncols, int nrb, int dot,
                                                     int c) {
   const double* p = part + ((int64_t)dot * ncols + c) * nrb;
-  double s = 0.0;
-  for (int rb = threadIdx.x; rb < nrb; rb += 64) s += p[rb];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const int t = threadIdx.x;
+  for (int rb = t; rb < nrb; rb += 4 * SCALAR_THREADS) {
+    const int r1 = rb + SCALAR_THREADS, r2 = rb + 2 * SCALAR_THREADS, r3 = rb + 3 * SCALAR_THREADS;
+    const double a0 = p[rb];
+    const double a1 = r1 < nrb ? p[r1] : 0.0;
+    const double a2 = r2 < nrb ? p[r2] : 0.0;
+    const double a3 = r3 < nrb ? p[r3] : 0.0;
+    s0 += a0;
+    s1 += a1;
+    s2 += a2;
+    s3 += a3;
+  }
+  double s = (s0 + s1) + (s2 + s3);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  return s;
+  __shared__ double wsum[SCALAR_THREADS / 64];
+  __syncthreads();
+  if ((t & 63) == 0) wsum[t >> 6] = s;
+  __syncthreads();
+  double tot = 0.0;
+#pragma unroll
+  for (int w = 0; w < SCALAR_THREADS / 64; ++w) tot += wsum[w];
+  return tot;
 }
 
 // (not written as v - v == 0: floating-point contraction may turn that into
@@ -143,7 +169,7 @@ __device__ __forceinline__ void cdiv(double ar, double ai, double br, double bi,
 
 // PHASE 0: init (bnrm2, rho); 1: alpha; 2: omega; 3: beta + convergence
 template <int PHASE, bool CPLX>
-__global__ void __launch_bounds__(64) k_bicg_scalar(double* __restrict__ scv, int* __restrict__ stv,
+__global__ void __launch_bounds__(SCALAR_THREADS) k_bicg_scalar(double* __restrict__ scv, int* __restrict__ stv,
                                                     const double* __restrict__ part, int ncols, int nrb, double tol2) {
   const int lc = blockIdx.x;
   const int cr = CPLX ? 2 * lc : lc;
@@ -161,6 +187,7 @@ __global__ void __launch_bounds__(64) k_bicg_scalar(double* __restrict__ scv, in
       sc[KS_RMIN] = bb;
       sc[KS_RREF] = bb;
       sc[KS_RCKPT] = bb;            // the checkpoint starts as x0 = 0
+      sc[KS_TOL2] = tol2;           // stop at ||r||^2 <= TOL2 ||b||^2
       st[KI_ITERS] = 0;
       st[KI_STALL] = 0;
       const bool ok = finite_d(bb);
@@ -223,7 +250,7 @@ __global__ void __launch_bounds__(64) k_bicg_scalar(double* __restrict__ scv, in
       st[KI_FLAG] = FLAG_NONFINITE;
       return;
     }
-    if (rr <= tol2 * sc[KS_BNRM2]) {
+    if (rr <= sc[KS_TOL2] * sc[KS_BNRM2]) {
       st[KI_ACTIVE] = 0;
       st[KI_FLAG] = FLAG_CONVERGED;
       return;
@@ -241,7 +268,7 @@ __global__ void __launch_bounds__(64) k_bicg_scalar(double* __restrict__ scv, in
       st[KI_FLAG] = FLAG_DIVERGED;
       return;
     }
-    if (st[KI_STALL] > STALL_MAX) {
+    if (st[KI_STALL] > STALL_MAX && st[KI_STALL] > st[KI_ITERS] / 4) {
       st[KI_ACTIVE] = 0;
       st[KI_FLAG] = FLAG_STAGNATED;
       return;
@@ -345,15 +372,16 @@ template <int PHASE>
 static void scalar(Ctx* ctx, bool cplx, double* sc, int* st, const double* part, int ncols, int nrb, double tol2) {
   const int nl = cplx ? ncols / 2 : ncols;
   if (cplx)
-    hipLaunchKernelGGL((k_bicg_scalar<PHASE, true>), dim3(nl), dim3(64), 0, ctx->stream, sc, st, part, ncols, nrb, tol2);
+    hipLaunchKernelGGL((k_bicg_scalar<PHASE, true>), dim3(nl), dim3(SCALAR_THREADS), 0, ctx->stream, sc, st, part, ncols, nrb, tol2);
   else
-    hipLaunchKernelGGL((k_bicg_scalar<PHASE, false>), dim3(nl), dim3(64), 0, ctx->stream, sc, st, part, ncols, nrb, tol2);
+    hipLaunchKernelGGL((k_bicg_scalar<PHASE, false>), dim3(nl), dim3(SCALAR_THREADS), 0, ctx->stream, sc, st, part, ncols, nrb, tol2);
   KERNEL_CHECK();
 }
 
 template <typename T>
-KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncols, const T* b, int64_t ldb, T* x,
-                      int64_t ldx, double tol, int maxit, int check_every) {
+static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double pi, int ncols, const T* b,
+                                  int64_t ldb, T* x, int64_t ldx, double tol, int maxit, int check_every,
+                                  const std::vector<int>* groups, const std::vector<double>* target2) {
   KrylovResult res;
   if (ncols <= 0) return res;
   const bool cplx = pi != 0.0;
@@ -404,6 +432,32 @@ KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncol
   };
   elem<T, UPD_INIT>(ctx, cplx, ea);
   scalar<0>(ctx, cplx, sc.get(), st.get(), part.get(), ncols, nrb, tol2);
+  if (groups || target2) {
+    // tolerance relative to the largest right-hand side of each group, or an
+    // absolute target ||r_c||^2 <= target2[c] (restarts)
+    if ((groups && (int)groups->size() != nl) || (target2 && (int)target2->size() != nl))
+      fail(CARE_ERR_ARG, "per-column tolerances do not match the columns");
+    std::vector<double> hs((size_t)nl * KS);
+    std::vector<int> hi((size_t)nl * KI);
+    d2h(ctx, hs.data(), sc.get(), hs.size() * sizeof(double));
+    d2h(ctx, hi.data(), st.get(), hi.size() * sizeof(int));
+    std::map<int, double> gmax;
+    if (groups)
+      for (int c = 0; c < nl; ++c)
+        gmax[(*groups)[c]] = std::max(gmax[(*groups)[c]], hs[(size_t)c * KS + KS_BNRM2]);
+    for (int c = 0; c < nl; ++c) {
+      const double bb = hs[(size_t)c * KS + KS_BNRM2];
+      if (bb <= 0.0 || !hi[(size_t)c * KI + KI_ACTIVE]) continue;
+      const double t2 = target2 ? (*target2)[c] / bb : tol2 * gmax[(*groups)[c]] / bb;
+      hs[(size_t)c * KS + KS_TOL2] = t2;
+      if (t2 >= 1.0) {                 // x = 0 already meets the group tolerance
+        hi[(size_t)c * KI + KI_ACTIVE] = 0;
+        hi[(size_t)c * KI + KI_FLAG] = FLAG_CONVERGED;
+      }
+    }
+    h2d(ctx, sc.get(), hs.data(), hs.size() * sizeof(double));
+    h2d(ctx, st.get(), hi.data(), hi.size() * sizeof(int));
+  }
   if (trace) dump("S0");
 
   std::vector<int> hst((size_t)nl * KI);
@@ -411,7 +465,7 @@ KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncol
   check_every = check_every > 0 ? check_every : 8;
   int next_check = 1;   // first poll right after one iteration (trivial columns)
   bool done = false;
-  while (it < maxit && !done) {
+  auto iteration = [&](int it) {
     SpmmArgs<T> a1;
     a1.ncols = ncols;
     a1.sr = pr;
@@ -446,16 +500,58 @@ KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncol
     elem<T, UPD_XR>(ctx, cplx, e3);
     scalar<3>(ctx, cplx, sc.get(), st.get(), part.get(), ncols, nrb, tol2);
     if (trace && it < 3) dump("S3");
+  };
+  auto poll = [&]() {
+    ckpt<T, false>(ctx, cplx, (int)n, ncols, x, ldx, Xb.get(), ld, sc.get(), st.get());
+    d2h(ctx, hst.data(), st.get(), hst.size() * sizeof(int));
+    int active = 0;
+    for (int c = 0; c < nl; ++c) active += hst[(size_t)c * KI + KI_ACTIVE];
+    done = active == 0;
+  };
+  // first check_every iterations (and everything when profiling) launched
+  // directly; the steady state replays a captured chunk of CHUNK iterations
+  // plus the checkpoint kernel as one HIP graph (no memset nodes: the loop
+  // holds kernels only), with a host poll after each replay.
+  const int CHUNK = 8;
+  const bool use_graph = !ctx->profile && !trace && maxit > 2 * CHUNK;
+  while (it < maxit && !done && (!use_graph || it < check_every)) {
+    iteration(it);
     ++it;
-
     if (it >= next_check || it >= maxit) {
-      ckpt<T, false>(ctx, cplx, (int)n, ncols, x, ldx, Xb.get(), ld, sc.get(), st.get());
+      poll();
+      next_check = it + check_every;
+    }
+  }
+  if (!done && it < maxit && use_graph) {
+    if (it % 2) {          // the ping-pong buffers repeat with period 2
+      iteration(it);
+      ++it;
+    }
+    const int64_t calls0 = ctx->spmm_calls;
+    const double bytes0 = ctx->spmm_bytes;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_CHECK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    for (int c = 0; c < CHUNK; ++c) iteration(it + c);
+    ckpt<T, false>(ctx, cplx, (int)n, ncols, x, ldx, Xb.get(), ld, sc.get(), st.get());
+    HIP_CHECK(hipStreamEndCapture(ctx->stream, &graph));
+    const int64_t dcalls = ctx->spmm_calls - calls0;
+    const double dbytes = ctx->spmm_bytes - bytes0;
+    ctx->spmm_calls = calls0;
+    ctx->spmm_bytes = bytes0;
+    HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    while (it < maxit && !done) {
+      HIP_CHECK(hipGraphLaunch(exec, ctx->stream));
+      it += CHUNK;
+      ctx->spmm_calls += dcalls;
+      ctx->spmm_bytes += dbytes;
       d2h(ctx, hst.data(), st.get(), hst.size() * sizeof(int));
       int active = 0;
       for (int c = 0; c < nl; ++c) active += hst[(size_t)c * KI + KI_ACTIVE];
       done = active == 0;
-      next_check = it + check_every;
     }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
   }
   // columns that stopped without converging fall back to their best checkpoint
   ckpt<T, true>(ctx, cplx, (int)n, ncols, x, ldx, Xb.get(), ld, sc.get(), st.get());
@@ -471,17 +567,87 @@ KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncol
     const double rel = v[KS_BNRM2] > 0 ? std::sqrt(rfin / v[KS_BNRM2]) : 0.0;
     res.worst_relres = std::max(res.worst_relres, rel);
     if (s[KI_FLAG] == FLAG_NONFINITE) fail(CARE_ERR_NONFINITE, "non-finite value in the Krylov iteration");
-    if (s[KI_FLAG] != FLAG_CONVERGED) {
-      if (rel > tol) res.unconverged += 1;
+    const bool ok = s[KI_FLAG] == FLAG_CONVERGED || rfin <= v[KS_TOL2] * v[KS_BNRM2];
+    res.col_ok.push_back(ok ? 1 : 0);
+    res.col_relres.push_back(rel);
+    res.col_bnorm.push_back(std::sqrt(std::max(v[KS_BNRM2], 0.0)));
+    if (!ok) {
+      res.unconverged += 1;
       if (s[KI_FLAG] == FLAG_BREAKDOWN) res.breakdown += 1;
     }
   }
   return res;
 }
 
+// Restarted solve: columns that stop above their tolerance (stagnation,
+// breakdown, divergence or the iteration cap) are solved again on their
+// true residual b - M x with a fresh shadow vector, up to MAX_RESTARTS
+// rounds, and the correction is added to x.
+constexpr int MAX_RESTARTS = 2;
+
+template <typename T>
+KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncols, const T* b, int64_t ldb, T* x,
+                      int64_t ldx, double tol, int maxit, int check_every, const std::vector<int>* groups) {
+  KrylovResult res = bicgstab_core<T>(ctx, op, pr, pi, ncols, b, ldb, x, ldx, tol, maxit, check_every, groups,
+                                      nullptr);
+  const bool cplx = pi != 0.0;
+  const int per = cplx ? 2 : 1;
+  const int nl = ncols / per;
+  const int64_t n = op.n, ld = pad_ld(n);
+  // absolute target of each column: ||r_c||^2 <= tgt2_c
+  std::vector<double> tgt2(nl);
+  std::map<int, double> gmax;
+  if (groups)
+    for (int c = 0; c < nl; ++c) gmax[(*groups)[c]] = std::max(gmax[(*groups)[c]], res.col_bnorm[c]);
+  for (int c = 0; c < nl; ++c) {
+    const double ref = groups ? gmax[(*groups)[c]] : res.col_bnorm[c];
+    tgt2[c] = tol * tol * ref * ref;
+  }
+  // a column that stopped within 1e4 unit roundoffs of its right-hand side
+  // sits at the attainable accuracy of the working precision: a restart
+  // cannot improve it (the true residual is that inaccurate itself)
+  const double floor_rel = 1e4 * (sizeof(T) == 8 ? 1.1102230246251565e-16 : 5.9604644775390625e-08);
+  for (int round = 0; round < MAX_RESTARTS; ++round) {
+    std::vector<int> cols;
+    for (int c = 0; c < nl; ++c)
+      if (!res.col_ok[c] && res.col_relres[c] > floor_rel) cols.push_back(c);
+    if (cols.empty()) break;
+    const int nc = (int)cols.size(), ncr = nc * per;
+    std::vector<int> map(ncr);
+    for (int j = 0; j < nc; ++j)
+      for (int e = 0; e < per; ++e) map[j * per + e] = cols[j] * per + e;
+    DBuf<T> Xc(ctx, (size_t)ld * ncr), Rc(ctx, (size_t)ld * ncr), Bc(ctx, (size_t)ld * ncr), D(ctx, (size_t)ld * ncr);
+    copy_cols<T, T>(ctx, n, ncr, x, ldx, Xc.get(), ld, map.data());
+    copy_cols<T, T>(ctx, n, ncr, b, ldb, Bc.get(), ld, map.data());
+    spmm_plain(ctx, op, pr, pi, Xc.get(), ld, ncr, Rc.get(), ld);
+    axpby<T>(ctx, n, ncr, 1.0, Bc.get(), ld, -1.0, Rc.get(), ld);    // Rc = b - M x
+    std::vector<double> ct2(nc);
+    for (int j = 0; j < nc; ++j) ct2[j] = tgt2[cols[j]];
+    KrylovResult r2 = bicgstab_core<T>(ctx, op, pr, pi, ncr, Rc.get(), ld, D.get(), ld, tol, maxit, check_every,
+                                       nullptr, &ct2);
+    for (int e = 0; e < ncr; ++e)
+      axpby<T>(ctx, n, 1, 1.0, D.get() + (int64_t)e * ld, ld, 1.0, x + (int64_t)map[e] * ldx, ldx);
+    res.max_iters += r2.max_iters;
+    res.restarts += 1;
+    for (int j = 0; j < nc; ++j) {
+      const int c = cols[j];
+      res.col_ok[c] = r2.col_ok[j];
+      const double rn = r2.col_relres[j] * r2.col_bnorm[j];
+      res.col_relres[c] = res.col_bnorm[c] > 0 ? rn / res.col_bnorm[c] : 0.0;
+    }
+  }
+  res.unconverged = 0;
+  res.worst_relres = 0;
+  for (int c = 0; c < nl; ++c) {
+    res.unconverged += res.col_ok[c] ? 0 : 1;
+    res.worst_relres = std::max(res.worst_relres, res.col_relres[c]);
+  }
+  return res;
+}
+
 template KrylovResult bicgstab<double>(Ctx*, const SellOp&, double, double, int, const double*, int64_t, double*,
-                                       int64_t, double, int, int);
+                                       int64_t, double, int, int, const std::vector<int>*);
 template KrylovResult bicgstab<float>(Ctx*, const SellOp&, double, double, int, const float*, int64_t, float*,
-                                      int64_t, double, int, int);
+                                      int64_t, double, int, int, const std::vector<int>*);
 
 }  // namespace mpcare

@@ -14,15 +14,25 @@ struct KrylovResult {
   int max_iters = 0;        // largest per-column iteration count
   int unconverged = 0;      // columns that stopped above tol
   int breakdown = 0;        // columns stopped by a breakdown
+  int restarts = 0;         // restart rounds performed
   double worst_relres = 0;  // largest ||r|| / ||b|| at exit (recursive residual)
+  std::vector<int> col_ok;          // per logical column: reached its tolerance
+  std::vector<double> col_relres;   // per logical column: ||r|| / ||b||
+  std::vector<double> col_bnorm;    // per logical column: ||b||
 };
 
 // Solve (A^T + p I) x_c = b_c for every column c.  T = double needs an FP64
 // operator, T = float an FP32 or BF16 operator.  Complex p (pi != 0): b and
 // x hold ncols_real/2 complex columns as interleaved (re, im) column pairs.
 // x is overwritten (zero initial guess).  Columns with b_c = 0 return 0.
+//
+// groups (optional, one id per logical column): the stopping test of column
+// c becomes ||r_c|| <= tol max_{c' in group(c)} ||b_c'||, i.e. accuracy
+// relative to the largest right-hand side of its group rather than to its
+// own norm (the block is used as a whole by LR-ADI).  NULL: ||r_c|| <= tol ||b_c||.
 template <typename T>
 KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncols_real, const T* b,
-                      int64_t ldb, T* x, int64_t ldx, double tol, int maxit, int check_every);
+                      int64_t ldb, T* x, int64_t ldx, double tol, int maxit, int check_every,
+                      const std::vector<int>* groups = nullptr);
 
 }  // namespace mpcare

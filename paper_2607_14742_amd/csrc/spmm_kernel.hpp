@@ -28,7 +28,7 @@ enum SpmmMode { MODE_PLAIN = 0, MODE_BICG_P = 1, MODE_BICG_S = 2 };
 // (RMIN: smallest ||r||^2 met; RCKPT: ||r||^2 of the checkpointed iterate)
 enum {
   KS_RHO = 0, KS_ALPHA = 2, KS_OMEGA = 4, KS_BETA = 6, KS_BNRM2 = 8, KS_RNRM2 = 9, KS_LAST_RHR = 10,
-  KS_RMIN = 11, KS_RCKPT = 12, KS_RREF = 13, KS = 16
+  KS_RMIN = 11, KS_RCKPT = 12, KS_RREF = 13, KS_TOL2 = 14, KS = 16
 };
 // per-logical-column status, KI ints per column (STALL: iterations since the
 // residual norm last dropped by 10 %)
