@@ -2,7 +2,8 @@
 mixed-precision refinement vs the all-FP64 path, at relative residual
 ||R||_F / ||C^T C||_F <= 1e-10, on the 500 x 500 2D convection-diffusion FDM
 problem (n = 250,000, 1,248,000 nonzeros, m = p = 5, Gaussian B and C from
-seed 1220, 16 log-spaced real shifts over the closed-form spectral interval).
+seed 1220, 16 log-spaced real shifts over the closed-form spectral interval,
+largest magnitude first).
 
 Prints ONE JSON line (see the keys below).  A step is one full care_solve
 (initial NLR-ADI solve + refinement) with inputs resident in HBM.
@@ -31,7 +32,7 @@ def parse():
     ap.add_argument("--N", type=int, default=500, help="grid size (500 -> n = 250000)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--cpu-sample-steps", type=int, default=12)
     return ap.parse_args()
 
 

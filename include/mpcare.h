@@ -92,14 +92,15 @@ typedef struct {
   double eta_r_rel;       /* Alg. 1 threshold, relative to max|lambda(H)| (1e-4)      */
   double eta_s_rel;       /* Alg. 2 threshold, relative to max|lambda(P)| (10 u_fp64)  */
   double tau_L;           /* inner LR-ADI stop ||W^T W||_F <= tau_L ||W0^T W0||_F;
-                             <= 0 selects 1e-12 (FP64) / 1e-5 (FP32) / 1e-2 (BF16)    */
+                             <= 0 selects 1e-12 (FP64) / 1e-5 (FP32) / 1e-3 (BF16)    */
   double tau_0;           /* initial NLR-ADI stop on the relative Riccati residual;
                              <= 0 selects max(tol / 10, 10 tau_L)                     */
   double stagnation;      /* stop when ||R_{k+1}|| / ||R_k|| > stagnation (0.999)     */
   int32_t krylov_maxit;   /* BiCGStab iteration cap per shifted solve (4000)          */
-  double krylov_tol;      /* per-column relative residual; <= 0 selects 1e-10 (FP64),
-                             1e-7 (FP32) or 1e-3 (BF16 products).  Columns that
-                             stagnate above it are restarted on their true residual */
+  double krylov_tol;      /* per-column relative residual; <= 0 selects
+                             max(1e-13, min(1e-10, tol / 10)) (FP64), 1e-7 (FP32) or
+                             1e-3 (BF16 products).  Columns that stagnate above it
+                             are restarted on their true residual                   */
   int32_t check_every;    /* host convergence poll period of the Krylov loop (8)      */
   int32_t penzl_l0;       /* auto shifts: number of shifts (16)                       */
   int32_t penzl_kp;       /* auto shifts: Arnoldi steps on A^T (20)                   */

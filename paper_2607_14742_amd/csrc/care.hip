@@ -20,10 +20,14 @@ Resolved resolve_opts(const care_opts* o, double tol) {
   if (!o) o = &d;
   r.prec = prec_from_abi(o->inner_prec);
   const double tl_def = r.prec == Prec::F64 ? 1e-12 : (r.prec == Prec::F32 ? 1e-5 : 1e-3);
-  // Krylov tolerance: 1e-10 (FP64) as in Sec. 5; FP32 uses 1e-7 instead of
-  // the paper's 1e-5 (unpreconditioned BiCGStab: the tighter inner solves
-  // leave a smaller, narrower residual and save refinement work)
-  const double kt_def = r.prec == Prec::F64 ? 1e-10 : (r.prec == Prec::F32 ? 1e-7 : 1e-3);
+  // Krylov tolerance: 1e-10 (FP64) as in Sec. 5, tightened to a tenth of the
+  // requested residual when that is smaller: the solves' own errors set the
+  // floor of the true Riccati residual near the Krylov tolerance, below the
+  // residual-identity estimate the initial stage stops on.  FP32 uses 1e-7
+  // instead of the paper's 1e-5 (unpreconditioned BiCGStab: the tighter inner
+  // solves leave a smaller, narrower residual and save refinement work).
+  const double kt_def = r.prec == Prec::F64 ? std::max(1e-13, std::min(1e-10, 0.1 * tol))
+                                            : (r.prec == Prec::F32 ? 1e-7 : 1e-3);
   r.tau_L = o->tau_L > 0 ? o->tau_L : tl_def;
   r.ktol = o->krylov_tol > 0 ? o->krylov_tol : kt_def;
   // the initial solve's residual estimate ignores the inner solves' own
@@ -152,10 +156,11 @@ static void stage0(Ctx* ctx, SolveState& S, TruncResult& Zout, care_stats* st, s
 }
 
 // one inner correction: LR-ADI on [C+, C-] with A_k = A - B (Z Z^T B)^T in
-// precision T; returns the combined factor promoted to FP64 with its signs
+// precision T; returns the factor promoted to FP64 with its columns grouped
+// by origin: Zpm = [Z+ (np columns), Z- (nm columns)]
 template <typename T>
 static void correction(Ctx* ctx, SolveState& S, const TruncResult& Zk, const ResidualFactor& rf, DBuf<double>& Zpm,
-                       int& zcols, std::vector<double>& sign, care_stats* st) {
+                       int& np, int& nm, care_stats* st) {
   const int64_t n = S.n, ld = S.ld;
   const int m = S.m;
   const int w = rf.rp + rf.rm;
@@ -186,11 +191,17 @@ static void correction(Ctx* ctx, SolveState& S, const TruncResult& Zk, const Res
   LradiOut lo = lradi_run<T>(ctx, *S.As, Bs.get(), (m > 0 && Zk.r > 0) ? Ks.get() : nullptr, m, W.get(), w,
                              S.shifts, lp, Zb.get(), zcap);
   st->iter_inner += lo.steps;
-  zcols = lo.zcols;
+  const int zcols = lo.zcols;
+  std::vector<int> map;
+  map.reserve(zcols);
+  for (int c = 0; c < zcols; ++c)
+    if (lo.zsrc[c] < rf.rp) map.push_back(c);
+  np = (int)map.size();
+  for (int c = 0; c < zcols; ++c)
+    if (lo.zsrc[c] >= rf.rp) map.push_back(c);
+  nm = zcols - np;
   Zpm.resize(ctx, (size_t)ld * std::max(zcols, 1));
-  copy_cols<T, double>(ctx, n, zcols, Zb.get(), ld, Zpm.get(), ld);
-  sign.assign(zcols, 1.0);
-  for (int c = 0; c < zcols; ++c) sign[c] = lo.zsrc[c] < rf.rp ? 1.0 : -1.0;
+  if (zcols) copy_cols<T, double>(ctx, n, zcols, Zb.get(), ld, Zpm.get(), ld, map.data());
 }
 
 static double fro_of_gram(Ctx* ctx, int64_t n, const double* X, int64_t ld, int k) {
@@ -266,6 +277,7 @@ void care_solve_impl(Ctx* ctx, const care_csr* A, const double* B, int m, const 
     copy_cols<double, double>(ctx, n, r0, opts->Z_init, opts->ldz_init, G.get(), S.ld);
     Z.Z = std::move(G);
     Z.r = r0;
+    Z.sig_max = factor_lam_max(ctx, n, Z.Z.get(), S.ld, r0);
   } else if (S.prm.prec == Prec::F64) {
     stage0<double>(ctx, S, Z, st, hist0);
   } else {
@@ -296,6 +308,7 @@ void care_solve_impl(Ctx* ctx, const care_csr* A, const double* B, int m, const 
       d2d(ctx, bestZ.Z.get(), Z.Z.get(), (size_t)S.ld * Z.r * sizeof(double));
       bestZ.r = Z.r;
       bestZ.eta_n = Z.eta_n;
+      bestZ.sig_max = Z.sig_max;
     }
     if (rel <= tol) {
       converged = true;
@@ -308,17 +321,33 @@ void care_solve_impl(Ctx* ctx, const care_csr* A, const double* B, int m, const 
     prev = rel;
     if (k == S.prm.k_max - 1) break;     // no correction whose residual would go unchecked
     DBuf<double> Zpm;
-    int zcols = 0;
-    std::vector<double> sgn;
-    if (S.prm.prec == Prec::F64) correction<double>(ctx, S, Z, rf, Zpm, zcols, sgn, st);
-    else correction<float>(ctx, S, Z, rf, Zpm, zcols, sgn, st);
-    // G = [Z, Z+-], Algorithm 2
-    const int s = Z.r + zcols;
+    int np = 0, nm = 0;
+    if (S.prm.prec == Prec::F64) correction<double>(ctx, S, Z, rf, Zpm, np, nm, st);
+    else correction<float>(ctx, S, Z, rf, Zpm, np, nm, st);
+    // Each of Z+ and Z- is a PSD factor: compressing it alone to the
+    // eigenvalues of Z+- Z+-^T above a quarter of Algorithm 2's own threshold
+    // (eta_s max|lambda(P)|, with max|lambda(P)| ~ ||Z Z^T||_2) changes
+    // G N G^T by at most that much, and shrinks G from the raw ADI width to
+    // the correction's numerical rank.
+    const double tau = 0.25 * S.prm.eta_s_rel * Z.sig_max;
+    const double* parts[2] = {Zpm.get(), Zpm.get() + (int64_t)np * S.ld};
+    int widths[2] = {np, nm};
+    DBuf<double> comp[2];
+    for (int g = 0; g < 2; ++g) {
+      int r = 0;
+      if (tau > 0.0 && widths[g] > 0 && psd_compress(ctx, n, parts[g], S.ld, widths[g], tau, comp[g], r)) {
+        parts[g] = comp[g].get();
+        widths[g] = r;
+      }
+    }
+    // G = [Z, Z+, Z-], Algorithm 2
+    const int s = Z.r + widths[0] + widths[1];
     DBuf<double> G(ctx, (size_t)S.ld * std::max(s, 1));
     d2d(ctx, G.get(), Z.Z.get(), (size_t)S.ld * Z.r * sizeof(double));
-    d2d(ctx, G.get() + (int64_t)Z.r * S.ld, Zpm.get(), (size_t)S.ld * zcols * sizeof(double));
+    d2d(ctx, G.get() + (int64_t)Z.r * S.ld, parts[0], (size_t)S.ld * widths[0] * sizeof(double));
+    d2d(ctx, G.get() + (int64_t)(Z.r + widths[0]) * S.ld, parts[1], (size_t)S.ld * widths[1] * sizeof(double));
     std::vector<double> sign(s, 1.0);
-    for (int c = 0; c < zcols; ++c) sign[Z.r + c] = sgn[c];
+    for (int c = Z.r + widths[0]; c < s; ++c) sign[c] = -1.0;
     TruncResult Zn;
     signed_truncate(ctx, n, G.get(), S.ld, s, sign, S.prm.eta_s_rel, Zn);
     st->eta_n = Zn.eta_n;

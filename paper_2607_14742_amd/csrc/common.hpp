@@ -99,6 +99,8 @@ struct Ctx {
   int profile = 0;
   int64_t spmm_calls = 0;
   double spmm_bytes = 0.0;
+  bool spmm_defer = false;          // bytes of sparse launches counted by the caller
+  int64_t spmm_pending[4] = {0, 0, 0, 0};   // deferred launches per mode
   double t_spmm = 0.0;
   int64_t krylov_iters = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_events;

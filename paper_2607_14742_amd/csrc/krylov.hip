@@ -501,11 +501,24 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
     scalar<3>(ctx, cplx, sc.get(), st.get(), part.get(), ncols, nrb, tol2);
     if (trace && it < 3) dump("S3");
   };
+  // Profiling: the bytes of the launches since the previous poll are counted
+  // for the columns still active at this poll, a lower bound for each of
+  // them (columns only ever leave the active set).
+  bool first_chunk = true;
+  auto account = [&](int active) {
+    if (!ctx->spmm_defer) return;
+    const int kr = active * (cplx ? 2 : 1);
+    ctx->spmm_bytes += double(ctx->spmm_pending[MODE_BICG_P]) * op.bytes(kr, spmm_vec_passes(MODE_BICG_P, first_chunk)) +
+                       double(ctx->spmm_pending[MODE_BICG_S]) * op.bytes(kr, spmm_vec_passes(MODE_BICG_S));
+    ctx->spmm_pending[MODE_BICG_P] = ctx->spmm_pending[MODE_BICG_S] = 0;
+    first_chunk = false;
+  };
   auto poll = [&]() {
     ckpt<T, false>(ctx, cplx, (int)n, ncols, x, ldx, Xb.get(), ld, sc.get(), st.get());
     d2h(ctx, hst.data(), st.get(), hst.size() * sizeof(int));
     int active = 0;
     for (int c = 0; c < nl; ++c) active += hst[(size_t)c * KI + KI_ACTIVE];
+    account(active);
     done = active == 0;
   };
   // first check_every iterations (and everything when profiling) launched
@@ -514,6 +527,8 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
   // holds kernels only), with a host poll after each replay.
   const int CHUNK = 8;
   const bool use_graph = !ctx->profile && !trace && maxit > 2 * CHUNK;
+  ctx->spmm_defer = ctx->profile != 0;
+  ctx->spmm_pending[MODE_BICG_P] = ctx->spmm_pending[MODE_BICG_S] = 0;
   while (it < maxit && !done && (!use_graph || it < check_every)) {
     iteration(it);
     ++it;
@@ -522,6 +537,8 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
       next_check = it + check_every;
     }
   }
+  account(0);
+  ctx->spmm_defer = false;
   if (!done && it < maxit && use_graph) {
     if (it % 2) {          // the ping-pong buffers repeat with period 2
       iteration(it);

@@ -1,7 +1,10 @@
 // Algorithms 1 and 2 (FP64).
 #include "lowrank.hpp"
 
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 namespace mpcare {
 
@@ -156,6 +159,52 @@ void signed_truncate(Ctx* ctx, int64_t n, const double* G, int64_t ldg, int s, c
     tsgemm(ctx, n, o.U.get(), o.ldu, k, coef.get(), k, out.r, 1.0, 0.0, out.Z.get(), ld);
   }
   ctx->sync();
+}
+
+bool psd_compress(Ctx* ctx, int64_t n, const double* Z, int64_t ldz, int w, double tau_abs, DBuf<double>& out,
+                  int& r) {
+  const int64_t ld = pad_ld(n);
+  r = 0;
+  if (w <= 0) {
+    out.resize(ctx, ld);
+    return true;
+  }
+  DBuf<double> G(ctx, (size_t)w * w);
+  gram(ctx, n, Z, ldz, w, Z, ldz, w, G.get(), w);
+  std::vector<double> lam;
+  dsyevd(ctx, w, G.get(), w, lam);
+  const double lmax = lam.back();
+  if (!(lmax > 0.0)) {
+    out.resize(ctx, ld);
+    return true;
+  }
+  if (!(tau_abs >= 1e-14 * lmax)) {
+    if (std::getenv("MPCARE_TRACE"))
+      std::fprintf(stderr, "[psd_compress] w %d kept whole: tau %.3e below 1e-14 lam_max %.3e\n", w, tau_abs, lmax);
+    return false;
+  }
+  std::vector<int> sel;
+  for (int i = w - 1; i >= 0; --i)
+    if (lam[i] > tau_abs) sel.push_back(i);
+  r = (int)sel.size();
+  out.resize(ctx, (size_t)ld * std::max(r, 1));
+  if (r) {
+    DBuf<double> coef(ctx, (size_t)w * r);
+    copy_cols<double, double>(ctx, w, r, G.get(), w, coef.get(), w, sel.data());
+    tsgemm(ctx, n, Z, ldz, w, coef.get(), w, r, 1.0, 0.0, out.get(), ld);
+  }
+  if (std::getenv("MPCARE_TRACE"))
+    std::fprintf(stderr, "[psd_compress] w %d -> %d  lam_max %.3e tau %.3e\n", w, r, lmax, tau_abs);
+  return true;
+}
+
+double factor_lam_max(Ctx* ctx, int64_t n, const double* Z, int64_t ldz, int r) {
+  if (r <= 0) return 0.0;
+  DBuf<double> G(ctx, (size_t)r * r);
+  gram(ctx, n, Z, ldz, r, Z, ldz, r, G.get(), r);
+  std::vector<double> lam;
+  dsyevd(ctx, r, G.get(), r, lam);
+  return std::max(lam.back(), 0.0);
 }
 
 }  // namespace mpcare

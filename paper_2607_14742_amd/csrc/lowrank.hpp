@@ -30,4 +30,18 @@ struct TruncResult {
 void signed_truncate(Ctx* ctx, int64_t n, const double* G, int64_t ldg, int s, const std::vector<double>& sign,
                      double eta_s_rel, TruncResult& out);
 
+// Compression of one positive semidefinite factor ahead of Algorithm 2:
+// Z Z^T = U diag(lam) U^T from the FP64 Gram Z^T Z = V diag(lam) V^T; keeps
+// lam > tau_abs and returns Zc = Z V_sel (n x r, ld pad_ld(n), orthogonal
+// columns), so that ||Z Z^T - Zc Zc^T||_2 <= tau_abs + O(u lam_max): the
+// dropped part is exactly the sum of the dropped eigen-terms, so only the
+// FP64 Gram's own rounding adds to it.  Returns false, and leaves out
+// untouched, when tau_abs lies below 1e-14 lam_max, where that rounding would
+// no longer be small next to it.
+bool psd_compress(Ctx* ctx, int64_t n, const double* Z, int64_t ldz, int w, double tau_abs, DBuf<double>& out,
+                  int& r);
+
+// largest eigenvalue of Z Z^T (0 for an empty factor)
+double factor_lam_max(Ctx* ctx, int64_t n, const double* Z, int64_t ldz, int r);
+
 }  // namespace mpcare

@@ -275,7 +275,7 @@ int launch_spmm(Ctx* ctx, const SellOp& op, int mode, bool cplx, SpmmArgs<T>& a)
   a.nrb = spmm_rowblocks(op.n);
   if (a.ncols <= 0) return a.nrb;
   if (cplx && (a.ncols % 2)) fail(CARE_ERR_ARG, "complex panel with an odd number of real columns");
-  SpmmTimer timer(ctx, op, a.ncols);
+  SpmmTimer timer(ctx, op, a.ncols, mode);
   if constexpr (sizeof(T) == 8) {
     if (op.prec != Prec::F64) fail(CARE_ERR_ARG, "FP64 vectors need the FP64 operator");
     launch_tv<double, double>(ctx->stream, op.n, mode, cplx, a);
@@ -291,9 +291,10 @@ int launch_spmm(Ctx* ctx, const SellOp& op, int mode, bool cplx, SpmmArgs<T>& a)
 template int launch_spmm<double>(Ctx*, const SellOp&, int, bool, SpmmArgs<double>&);
 template int launch_spmm<float>(Ctx*, const SellOp&, int, bool, SpmmArgs<float>&);
 
-SpmmTimer::SpmmTimer(Ctx* c, const SellOp& op, int k_real) : ctx(c) {
+SpmmTimer::SpmmTimer(Ctx* c, const SellOp& op, int k_real, int mode) : ctx(c) {
   ctx->spmm_calls += 1;
-  ctx->spmm_bytes += op.bytes(k_real);
+  if (ctx->spmm_defer) ctx->spmm_pending[mode & 3] += 1;
+  else ctx->spmm_bytes += op.bytes(k_real, spmm_vec_passes(mode));
   if (ctx->profile) {
     ev = ctx->event_pair();
     HIP_CHECK(hipEventRecord(ev.first, ctx->stream));

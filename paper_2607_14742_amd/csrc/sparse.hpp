@@ -30,10 +30,12 @@ struct SellOp {
   DBuf<uint8_t> vals;              // width_total * 64 * val_bytes
   DBuf<uint8_t> diag;              // n * vec_bytes
   double frob = 0.0;               // ||A||_F (FP64)
-  // algorithmic bytes of one product with k real columns (CSR formula)
-  double bytes(int k) const {
+  // algorithmic bytes of one product with k real columns: the CSR formula
+  // nnz (s_v + 4) + 4 (n + 1) plus `passes` n-vectors per column (2 for
+  // y = M x; the fused BiCGStab modes move more, see spmm_vec_passes)
+  double bytes(int k, int passes = 2) const {
     return double(nnz) * (double(val_bytes(prec)) + 4.0) + 4.0 * double(n + 1) +
-           2.0 * double(n) * double(k) * double(vec_bytes(prec));
+           double(passes) * double(n) * double(k) * double(vec_bytes(prec));
   }
 };
 
@@ -56,10 +58,19 @@ inline int spmm_rowblocks(int64_t n) { return (int)((n + 255) / 256); }
 
 // record the algorithmic traffic of a product (and bracket it with events
 // when profiling is on)
+// n-vector passes per real column of one launch in each mode: y = M x reads
+// x and writes y; MODE_BICG_P reads r, p, v, rhat and writes p, v (4 on a
+// column's first iteration, where p and v are not read); MODE_BICG_S reads
+// r, v and writes s, t.
+inline int spmm_vec_passes(int mode, bool first = false) { return mode == 0 ? 2 : (mode == 1 ? (first ? 4 : 6) : 4); }
+
+// Counts a launch and, when the context profiles, brackets it with HIP events
+// on the library stream.  While ctx->spmm_defer is set the launch's bytes are
+// left to the caller, which knows how many columns were still active.
 struct SpmmTimer {
   Ctx* ctx;
   std::pair<hipEvent_t, hipEvent_t> ev{};
-  SpmmTimer(Ctx* c, const SellOp& op, int k_real);
+  SpmmTimer(Ctx* c, const SellOp& op, int k_real, int mode);
   ~SpmmTimer();
 };
 
