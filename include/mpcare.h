@@ -114,6 +114,7 @@ typedef struct {
                              is negligible for the stopping test (default 1)       */
   int32_t krylov_block_tol; /* 1: Krylov accuracy relative to the largest column of
                              the right-hand side block instead of each column (0)  */
+  int32_t penzl_real;     /* auto shifts: 1 keeps the real parts of the Ritz values */
 } care_opts;
 
 /* Statistics written by the solvers (host struct). */
@@ -246,13 +247,34 @@ care_status care_solve(care_ctx* ctx, const care_csr* A, const double* B, int32_
                        const care_opts* opts, double* Z, int64_t ldz, int32_t rmax, int32_t* r_out,
                        care_stats* stats);
 
-/* Penzl-type heuristic shifts (the "shifts from Krylov subspaces" of Sec. 5):
- * Ritz values of kp Arnoldi steps with A^T and km steps with A^-T (FP64),
- * then the greedy min-max choice of l0 shifts.  shifts_out: HOST array with
- * room for l0 + 1 entries (a conjugate pair is never split); *count receives
- * the number written. */
+/* Penzl-type heuristic shifts (the "shifts from Krylov subspaces" of Sec. 5,
+ * read as Penzl's procedure): Ritz values of kp Arnoldi steps with A^T and
+ * of km steps with A^-T (inverted), FP64 on the GPU from ones / sqrt(n);
+ * those in the open left half-plane are the candidates of the greedy min-max
+ * choice of care_penzl_select.  real_only = 1 replaces each Ritz value by its
+ * real part first.  shifts_out: HOST array with room for l0 + 1 entries (a
+ * conjugate pair is never split); *count receives the number written.
+ * Errors: CARE_ERR_UNSTABLE if no Ritz value has a negative real part,
+ * CARE_ERR_BREAKDOWN if a solve with A^T fails. */
 care_status care_penzl_shifts(care_ctx* ctx, const care_csr* A, int32_t l0, int32_t kp, int32_t km,
-                              care_shift* shifts_out, int32_t* count);
+                              int32_t real_only, care_shift* shifts_out, int32_t* count);
+
+/* Host step of the shift heuristic: the eigenvalues (re[i], im[i]) of the
+ * k x k upper Hessenberg matrix H (HOST, column-major, ldh >= k; entries
+ * below the subdiagonal are ignored), i.e. the Ritz values of an Arnoldi
+ * run, by the Francis double-shift QR iteration.  Complex eigenvalues come
+ * in adjacent conjugate pairs.  No device work. */
+care_status care_ritz_values(const double* H, int32_t k, int64_t ldh, double* re, double* im);
+
+/* Host step of the shift heuristic: greedy min-max choice among nr candidate
+ * values (re[i], im[i]) (HOST; im may be NULL for real candidates).  Only
+ * candidates with Re < 0 take part, in ascending (Re, Im) order.  The first
+ * shift p minimises max_t |(t - p) / (t + p)|; then the candidate t that
+ * maximises prod_{p chosen} |(t - p) / (t + p)| is added until l0 shifts are
+ * chosen or every candidate is chosen.  A complex choice adds the pair
+ * (Im > 0 first).  out: HOST, room for l0 + 1.  No device work. */
+care_status care_penzl_select(const double* re, const double* im, int32_t nr, int32_t l0, care_shift* out,
+                              int32_t* count);
 
 #ifdef __cplusplus
 }

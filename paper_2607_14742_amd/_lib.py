@@ -36,7 +36,7 @@ class care_opts(C.Structure):
         ("stagnation", C.c_double), ("krylov_maxit", C.c_int32), ("krylov_tol", C.c_double),
         ("check_every", C.c_int32), ("penzl_l0", C.c_int32), ("penzl_kp", C.c_int32), ("penzl_km", C.c_int32),
         ("profile", C.c_int32), ("Z_init", C.c_void_p), ("ldz_init", C.c_int64), ("r_init", C.c_int32),
-        ("adi_deflate", C.c_int32), ("krylov_block_tol", C.c_int32),
+        ("adi_deflate", C.c_int32), ("krylov_block_tol", C.c_int32), ("penzl_real", C.c_int32),
     ]
 
 
@@ -79,7 +79,9 @@ SIGNATURES = {
     "lowrank_truncate": (I32, [P, I64, P, I64, I32, C.POINTER(C.c_int8), DBL, P, I64, I32, PI32, PDBL]),
     "care_solve": (I32, [P, C.POINTER(care_csr), P, I32, P, I32, DBL, C.POINTER(care_shift), I32,
                          C.POINTER(care_opts), P, I64, I32, PI32, C.POINTER(care_stats)]),
-    "care_penzl_shifts": (I32, [P, C.POINTER(care_csr), I32, I32, I32, C.POINTER(care_shift), PI32]),
+    "care_penzl_shifts": (I32, [P, C.POINTER(care_csr), I32, I32, I32, I32, C.POINTER(care_shift), PI32]),
+    "care_ritz_values": (I32, [PDBL, I32, I64, PDBL, PDBL]),
+    "care_penzl_select": (I32, [PDBL, PDBL, I32, I32, C.POINTER(care_shift), PI32]),
 }
 
 _lib = None

@@ -255,8 +255,36 @@ def care_solve(ctx, A, B, C_, tol=1e-10, shifts=None, prec="fp32", opts=None, rm
     return Z[:, :r.value], stats.to_dict(), st
 
 
-def penzl_shifts(ctx, A, l0=16, kp=20, km=10):
+def penzl_shifts(ctx, A, l0=16, kp=20, km=10, real_only=False):
+    """Heuristic shift set from Ritz values of A^T and A^-T (GPU Arnoldi)."""
     out = (care_shift * (l0 + 1))()
     cnt = C.c_int32(0)
-    _check(_lib().care_penzl_shifts(ctx.h, A.c, l0, kp, km, out, C.byref(cnt)))
+    _check(_lib().care_penzl_shifts(ctx.h, A.c, l0, kp, km, 1 if real_only else 0, out, C.byref(cnt)))
+    return np.array([complex(out[i].re, out[i].im) for i in range(cnt.value)])
+
+
+def ritz_values(H):
+    """Eigenvalues of a small upper Hessenberg matrix (host, no device work)."""
+    H = np.asfortranarray(np.asarray(H, dtype=np.float64))
+    k = H.shape[0]
+    if H.shape != (k, k):
+        raise ValueError("H must be square")
+    re = np.zeros(max(k, 1))
+    im = np.zeros(max(k, 1))
+    dp = C.POINTER(C.c_double)
+    _check(_lib().care_ritz_values(H.ctypes.data_as(dp), k, max(k, 1), re.ctypes.data_as(dp),
+                                   im.ctypes.data_as(dp)))
+    return (re + 1j * im)[:k]
+
+
+def penzl_select(candidates, l0):
+    """Greedy min-max choice of l0 shifts among candidate values (host)."""
+    R = np.asarray(candidates, dtype=np.complex128).ravel()
+    re = np.ascontiguousarray(R.real)
+    im = np.ascontiguousarray(R.imag)
+    out = (care_shift * (l0 + 1))()
+    cnt = C.c_int32(0)
+    dp = C.POINTER(C.c_double)
+    _check(_lib().care_penzl_select(re.ctypes.data_as(dp), im.ctypes.data_as(dp), R.size, l0, out,
+                                    C.byref(cnt)))
     return np.array([complex(out[i].re, out[i].im) for i in range(cnt.value)])

@@ -74,6 +74,7 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->penzl_l0 = 16;
   o->penzl_kp = 20;
   o->penzl_km = 10;
+  o->penzl_real = 0;
   o->profile = 0;
   o->Z_init = nullptr;
   o->ldz_init = 0;
@@ -388,14 +389,39 @@ care_status care_solve(care_ctx* cx, const care_csr* A, const double* B, int32_t
 }
 
 care_status care_penzl_shifts(care_ctx* cx, const care_csr* A, int32_t l0, int32_t kp, int32_t km,
-                              care_shift* out, int32_t* count) {
+                              int32_t real_only, care_shift* out, int32_t* count) {
   return guarded([&]() -> care_status {
     Ctx* ctx = unwrap(cx);
     check_csr_shape(A);
     if (!out || !count || l0 < 1 || kp < 1 || km < 0) fail(CARE_ERR_ARG, "invalid Penzl arguments");
     SellOp op;
     build_sell(ctx, A, Prec::F64, op);
-    std::vector<Shift> s = penzl_shifts(ctx, op, l0, kp, km);
+    std::vector<Shift> s = penzl_shifts(ctx, op, l0, kp, km, real_only != 0);
+    *count = (int)s.size();
+    for (size_t i = 0; i < s.size(); ++i) out[i] = care_shift{s[i].re, s[i].im};
+    return CARE_OK;
+  });
+}
+
+care_status care_ritz_values(const double* H, int32_t k, int64_t ldh, double* re, double* im) {
+  return guarded([&]() -> care_status {
+    if (k < 0 || (k > 0 && (!H || ldh < k || !re || !im))) fail(CARE_ERR_ARG, "invalid Hessenberg arguments");
+    std::vector<std::complex<double>> ev = hessenberg_eigvals(H, k, ldh);
+    for (int i = 0; i < k; ++i) {
+      re[i] = ev[i].real();
+      im[i] = ev[i].imag();
+    }
+    return CARE_OK;
+  });
+}
+
+care_status care_penzl_select(const double* re, const double* im, int32_t nr, int32_t l0, care_shift* out,
+                              int32_t* count) {
+  return guarded([&]() -> care_status {
+    if (nr < 1 || l0 < 1 || !re || !out || !count) fail(CARE_ERR_ARG, "invalid selection arguments");
+    std::vector<std::complex<double>> R(nr);
+    for (int i = 0; i < nr; ++i) R[i] = std::complex<double>(re[i], im ? im[i] : 0.0);
+    std::vector<Shift> s = penzl_select(R, l0);
     *count = (int)s.size();
     for (size_t i = 0; i < s.size(); ++i) out[i] = care_shift{s[i].re, s[i].im};
     return CARE_OK;

@@ -253,7 +253,9 @@ void care_solve_impl(Ctx* ctx, const care_csr* A, const double* B, int m, const 
     care_opts d;
     care_opts_default(&d, CARE_FP64);
     const care_opts* o = opts ? opts : &d;
-    S.shifts = penzl_shifts(ctx, A64, o->penzl_l0, o->penzl_kp, o->penzl_km);
+    S.shifts = penzl_shifts(ctx, A64, o->penzl_l0, o->penzl_kp, o->penzl_km, o->penzl_real != 0);
+    if (std::getenv("MPCARE_TRACE"))
+      for (const Shift& sh : S.shifts) std::fprintf(stderr, "[penzl] shift (%.6e, %.6e)\n", sh.re, sh.im);
   }
   // B and C^T in internal layout (ld = pad_ld(n)); C is p x n row-major = C^T col-major with ld n
   S.B64.resize(ctx, (size_t)S.ld * std::max(m, 1));

@@ -21,6 +21,11 @@ void care_solve_impl(Ctx* ctx, const care_csr* A, const double* B, int m, const 
                      const care_shift* shifts, int nshifts, const care_opts* opts, double* Z, int64_t ldz, int rmax,
                      int* r_out, care_stats* stats, care_status* warn);
 
-std::vector<Shift> penzl_shifts(Ctx* ctx, const SellOp& A64, int l0, int kp, int km);
+// Penzl's heuristic (penzl.hip): Ritz values of A^T and A^-T on the GPU, then
+// the greedy min-max choice of l0 shifts; real_only keeps real parts.
+std::vector<Shift> penzl_shifts(Ctx* ctx, const SellOp& A64, int l0, int kp, int km, bool real_only);
+// host steps of the heuristic
+std::vector<std::complex<double>> hessenberg_eigvals(const double* H, int k, int64_t ldh);
+std::vector<Shift> penzl_select(std::vector<std::complex<double>> R, int l0);
 
 }  // namespace mpcare

@@ -1,15 +1,241 @@
-// Heuristic ADI shifts from Ritz values (Penzl's procedure).
+// Heuristic ADI shifts from Ritz values: the "shifts generated from Krylov
+// subspaces" of Sec. 5, read as Penzl's procedure (Penzl 2000, Sec. 5):
+//   1. kp Arnoldi steps with F = A^T from b0 = ones / sqrt(n) -> Ritz values
+//   2. km Arnoldi steps with F^{-1} -> Ritz values, inverted
+//   3. candidates: the Ritz values in the open left half-plane
+//   4. greedy min-max: the first shift minimises max_t |(t - p)/(t + p)|, then
+//      the candidate where prod_{p in P} |(t - p)/(t + p)| is largest joins
+//      P until l0 shifts are chosen (a complex one brings its conjugate).
+// The Krylov steps run on the GPU (FP64 sparse products, or BiCGStab for
+// F^{-1}, classical Gram-Schmidt applied twice through the Gram/tall-skinny
+// kernels); the k x k Hessenberg eigenvalues and the greedy choice are small
+// host computations.
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <complex>
+
 #include "care.hpp"
+#include "dense.hpp"
 
 namespace mpcare {
 
-std::vector<Shift> penzl_shifts(Ctx* ctx, const SellOp& A64, int l0, int kp, int km) {
-  (void)ctx;
-  (void)A64;
-  (void)l0;
-  (void)kp;
-  (void)km;
-  fail(CARE_ERR_NOT_IMPLEMENTED, "automatic shift selection is not available yet; pass a shift set");
+using cplx = std::complex<double>;
+
+// Eigenvalues of a real upper Hessenberg matrix (column-major, leading
+// dimension ldh) by the Francis implicit double-shift QR iteration
+// (Golub & Van Loan, Sec. 7.5), eigenvalues only: every transformation is
+// confined to the active diagonal block [lo, hi].
+std::vector<cplx> hessenberg_eigvals(const double* Hin, int k, int64_t ldh) {
+  std::vector<double> a((size_t)k * k);
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i < k; ++i) a[(size_t)j * k + i] = (i <= j + 1) ? Hin[(size_t)j * ldh + i] : 0.0;
+  auto A = [&](int i, int j) -> double& { return a[(size_t)j * k + i]; };
+  std::vector<cplx> ev(k);
+  double anorm = 0.0;
+  for (double v : a) anorm += std::fabs(v);
+  const double eps = DBL_EPSILON;
+  int hi = k - 1, its = 0;
+  while (hi >= 0) {
+    int lo = hi;
+    while (lo > 0) {   // negligible subdiagonal entry splits the matrix
+      double s = std::fabs(A(lo - 1, lo - 1)) + std::fabs(A(lo, lo));
+      if (s == 0.0) s = anorm;
+      if (std::fabs(A(lo, lo - 1)) <= eps * s) {
+        A(lo, lo - 1) = 0.0;
+        break;
+      }
+      --lo;
+    }
+    if (lo == hi) {    // 1 x 1 block
+      ev[hi] = A(hi, hi);
+      --hi;
+      its = 0;
+      continue;
+    }
+    if (lo == hi - 1) {   // 2 x 2 block: roots of its characteristic polynomial
+      const double a11 = A(hi - 1, hi - 1), a12 = A(hi - 1, hi), a21 = A(hi, hi - 1), a22 = A(hi, hi);
+      const double half = 0.5 * (a11 - a22), disc = half * half + a12 * a21;
+      const double mid = 0.5 * (a11 + a22);
+      if (disc >= 0.0) {
+        const double r = std::sqrt(disc);
+        const double big = mid + (mid >= 0 ? r : -r);    // the root free of cancellation
+        const double det = a11 * a22 - a12 * a21;        // product of the two roots
+        ev[hi - 1] = big;
+        ev[hi] = big != 0.0 ? det / big : 0.0;
+      } else {
+        const double r = std::sqrt(-disc);
+        ev[hi - 1] = cplx(mid, r);
+        ev[hi] = cplx(mid, -r);
+      }
+      hi -= 2;
+      its = 0;
+      continue;
+    }
+    if (++its > 100) fail(CARE_ERR_BREAKDOWN, "Hessenberg QR iteration did not converge");
+    // shifts: the eigenvalues of the trailing 2 x 2 block (sum s, product t),
+    // replaced by an ad hoc pair every tenth iteration
+    double s, t;
+    if (its % 10 == 0) {
+      const double w = std::fabs(A(hi, hi - 1)) + std::fabs(A(hi - 1, hi - 2));
+      s = 1.5 * w;
+      t = w * w;
+    } else {
+      s = A(hi - 1, hi - 1) + A(hi, hi);
+      t = A(hi - 1, hi - 1) * A(hi, hi) - A(hi - 1, hi) * A(hi, hi - 1);
+    }
+    // first column of (H - s1 I)(H - s2 I) = H^2 - s H + t I, rows lo..lo+2
+    double x = A(lo, lo) * A(lo, lo) + A(lo, lo + 1) * A(lo + 1, lo) - s * A(lo, lo) + t;
+    double y = A(lo + 1, lo) * (A(lo, lo) + A(lo + 1, lo + 1) - s);
+    double z = A(lo + 1, lo) * A(lo + 2, lo + 1);
+    for (int c = lo; c <= hi - 1; ++c) {
+      const int nr = c < hi - 1 ? 3 : 2;
+      if (c > lo) {
+        x = A(c, c - 1);
+        y = A(c + 1, c - 1);
+        z = nr == 3 ? A(c + 2, c - 1) : 0.0;
+      }
+      // Householder reflector I - beta v v^T with v = u - alpha e1, u = (x, y, z)
+      const double nu = std::sqrt(x * x + y * y + z * z);
+      if (nu == 0.0) continue;
+      const double alpha = x > 0 ? -nu : nu;
+      const double v0 = x - alpha, v1 = y, v2 = z;
+      const double beta = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
+      for (int j = std::max(lo, c - 1); j <= hi; ++j) {   // from the left
+        const double d = beta * (v0 * A(c, j) + v1 * A(c + 1, j) + (nr == 3 ? v2 * A(c + 2, j) : 0.0));
+        A(c, j) -= d * v0;
+        A(c + 1, j) -= d * v1;
+        if (nr == 3) A(c + 2, j) -= d * v2;
+      }
+      if (c > lo) {
+        A(c, c - 1) = alpha;
+        A(c + 1, c - 1) = 0.0;
+        if (nr == 3) A(c + 2, c - 1) = 0.0;
+      }
+      const int imax = std::min(c + 3, hi);
+      for (int i = lo; i <= imax; ++i) {                  // from the right
+        const double d = beta * (A(i, c) * v0 + A(i, c + 1) * v1 + (nr == 3 ? A(i, c + 2) * v2 : 0.0));
+        A(i, c) -= d * v0;
+        A(i, c + 1) -= d * v1;
+        if (nr == 3) A(i, c + 2) -= d * v2;
+      }
+    }
+  }
+  return ev;
+}
+
+std::vector<Shift> penzl_select(std::vector<cplx> R, int l0) {
+  std::vector<cplx> cand;
+  for (const cplx& t : R)
+    if (t.real() < 0.0 && std::isfinite(t.real()) && std::isfinite(t.imag())) cand.push_back(t);
+  if (cand.empty()) fail(CARE_ERR_UNSTABLE, "no Ritz value in the open left half-plane");
+  std::stable_sort(cand.begin(), cand.end(), [](const cplx& a, const cplx& b) {
+    return a.real() < b.real() || (a.real() == b.real() && a.imag() < b.imag());
+  });
+  auto ratio = [](const cplx& t, const cplx& p) { return std::abs((t - p) / (t + p)); };
+  int first = 0;
+  double best = INFINITY;
+  for (size_t ip = 0; ip < cand.size(); ++ip) {
+    double worst = 0.0;
+    for (const cplx& t : cand) worst = std::max(worst, ratio(t, cand[ip]));
+    if (worst < best) {
+      best = worst;
+      first = (int)ip;
+    }
+  }
+  std::vector<cplx> P;
+  auto add = [&](const cplx& p) {
+    if (p.imag() != 0.0) {
+      P.emplace_back(p.real(), std::fabs(p.imag()));
+      P.emplace_back(p.real(), -std::fabs(p.imag()));
+    } else {
+      P.emplace_back(p.real(), 0.0);
+    }
+  };
+  add(cand[first]);
+  while ((int)P.size() < l0) {
+    int imax = 0;
+    double smax = -1.0;
+    for (size_t it = 0; it < cand.size(); ++it) {
+      double s = 1.0;
+      for (const cplx& p : P) s *= ratio(cand[it], p);
+      if (s > smax) {
+        smax = s;
+        imax = (int)it;
+      }
+    }
+    if (smax == 0.0) break;   // every candidate is already a shift
+    add(cand[imax]);
+  }
+  std::vector<Shift> out;
+  for (const cplx& p : P) out.push_back(Shift{p.real(), p.imag()});
+  return out;
+}
+
+// Ritz values of k Arnoldi steps with F = A^T (inverse: F^{-1}, applied by
+// BiCGStab to relative residual 1e-12) from ones / sqrt(n).
+static std::vector<cplx> arnoldi_ritz(Ctx* ctx, const SellOp& op, int k, bool inverse) {
+  const int64_t n = op.n, ld = pad_ld(n);
+  DBuf<double> V(ctx, (size_t)ld * (k + 1)), w(ctx, ld), h1(ctx, k + 1), h2(ctx, k + 1), nn(ctx, 1);
+  {
+    std::vector<double> b0(n, 1.0 / std::sqrt((double)n));
+    h2d(ctx, V.get(), b0.data(), n * sizeof(double));
+  }
+  std::vector<double> H((size_t)(k + 1) * k, 0.0);   // (k+1) x k, ld k+1
+  int steps = k;
+  for (int j = 0; j < k; ++j) {
+    const double* vj = V.get() + (int64_t)j * ld;
+    if (!inverse) {
+      spmm_plain(ctx, op, 0.0, 0.0, vj, ld, 1, w.get(), ld);
+    } else {
+      KrylovResult kr = bicgstab<double>(ctx, op, 0.0, 0.0, 1, vj, ld, w.get(), ld, 1e-12, 20000, 8);
+      if (!(kr.worst_relres < 1e-6))
+        fail(CARE_ERR_BREAKDOWN, "inverse Arnoldi solve with A^T did not converge");
+    }
+    // classical Gram-Schmidt, twice
+    std::vector<double> hc(j + 1, 0.0), tmp(j + 1);
+    for (int rep = 0; rep < 2; ++rep) {
+      gram(ctx, n, V.get(), ld, j + 1, w.get(), ld, 1, h1.get(), j + 1);
+      tsgemm(ctx, n, V.get(), ld, j + 1, h1.get(), j + 1, 1, -1.0, 1.0, w.get(), ld);
+      d2h(ctx, tmp.data(), h1.get(), (j + 1) * sizeof(double));
+      for (int i = 0; i <= j; ++i) hc[i] += tmp[i];
+    }
+    gram(ctx, n, w.get(), ld, 1, w.get(), ld, 1, nn.get(), 1);
+    double nrm2 = 0.0;
+    d2h(ctx, &nrm2, nn.get(), sizeof(double));
+    const double hn = std::sqrt(std::max(nrm2, 0.0));
+    if (!std::isfinite(hn)) fail(CARE_ERR_NONFINITE, "non-finite Arnoldi vector");
+    double colnorm = hn * hn;
+    for (int i = 0; i <= j; ++i) {
+      H[(size_t)j * (k + 1) + i] = hc[i];
+      colnorm += hc[i] * hc[i];
+    }
+    H[(size_t)j * (k + 1) + j + 1] = hn;
+    if (hn <= 1e-12 * std::sqrt(colnorm)) {   // invariant subspace: the Ritz values are exact
+      steps = j + 1;
+      break;
+    }
+    axpby<double>(ctx, n, 1, 1.0 / hn, w.get(), ld, 0.0, V.get() + (int64_t)(j + 1) * ld, ld);
+  }
+  std::vector<cplx> ev = hessenberg_eigvals(H.data(), steps, k + 1);
+  if (inverse)
+    for (cplx& t : ev) t = 1.0 / t;
+  return ev;
+}
+
+std::vector<Shift> penzl_shifts(Ctx* ctx, const SellOp& A64, int l0, int kp, int km, bool real_only) {
+  if (A64.prec != Prec::F64) fail(CARE_ERR_ARG, "Ritz values need the FP64 operator");
+  if (l0 < 1 || kp < 1 || km < 0) fail(CARE_ERR_ARG, "need l0 >= 1, kp >= 1, km >= 0");
+  const int kcap = (int)std::min<int64_t>(A64.n, 1000);
+  std::vector<cplx> R = arnoldi_ritz(ctx, A64, std::min(kp, kcap), false);
+  if (km > 0) {
+    std::vector<cplx> Ri = arnoldi_ritz(ctx, A64, std::min(km, kcap), true);
+    R.insert(R.end(), Ri.begin(), Ri.end());
+  }
+  if (real_only)
+    for (cplx& t : R) t = cplx(t.real(), 0.0);
+  ctx->sync();
+  return penzl_select(R, l0);
 }
 
 }  // namespace mpcare
