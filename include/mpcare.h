@@ -247,6 +247,41 @@ care_status care_solve(care_ctx* ctx, const care_csr* A, const double* B, int32_
                        const care_opts* opts, double* Z, int64_t ldz, int32_t rmax, int32_t* r_out,
                        care_stats* stats);
 
+/* One CARE instance of a batch: the arguments care_solve takes for it. */
+typedef struct {
+  const care_csr* A;            /* device CSR of A (n x n)                        */
+  const double* B;              /* device, n x m column-major (ld n)              */
+  int32_t m;
+  const double* C;              /* device, p x n row-major                        */
+  int32_t p;
+  const care_shift* shifts;     /* host; nshifts = 0 selects the heuristic shifts */
+  int32_t nshifts;
+  double* Z;                    /* device output, n x rmax, ld ldz >= n           */
+  int64_t ldz;
+  int32_t rmax;
+} care_instance;
+
+/* Outcome of one instance of care_solve_batch (host). */
+typedef struct {
+  int32_t status;               /* what care_solve returns for this instance      */
+  int32_t r;                    /* columns of Z (CARE_ERR_CAPACITY: needed)       */
+  care_stats stats;
+  char message[128];            /* error text of a failed instance, else ""       */
+} care_instance_result;
+
+/* Batched Framework 1 over `count` independent CAREs of uneven sizes (the
+ * paper solves one instance at a time): every instance is solved exactly as
+ * care_solve would, with the same tol and opts; `workers` concurrent solves
+ * (<= 0: min(count, 8)), each on its own non-blocking stream of the ctx's
+ * device with its own host thread, pick instances largest n first, so that
+ * the kernels of small instances fill the GPU together.  results: HOST array
+ * of count entries.  Returns CARE_OK when every instance returned a status
+ * >= 0, else the error of the first failed instance in input order (the
+ * other instances are still solved).  Each instance's Z must be its own
+ * buffer. */
+care_status care_solve_batch(care_ctx* ctx, int32_t count, const care_instance* instances, double tol,
+                             const care_opts* opts, int32_t workers, care_instance_result* results);
+
 /* Penzl-type heuristic shifts (the "shifts from Krylov subspaces" of Sec. 5,
  * read as Penzl's procedure): Ritz values of kp Arnoldi steps with A^T and
  * of km steps with A^-T (inverted), FP64 on the GPU from ones / sqrt(n);

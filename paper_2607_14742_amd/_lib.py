@@ -56,6 +56,16 @@ class care_stats(C.Structure):
         return d
 
 
+class care_instance(C.Structure):
+    _fields_ = [("A", C.POINTER(care_csr)), ("B", C.c_void_p), ("m", C.c_int32), ("C", C.c_void_p),
+                ("p", C.c_int32), ("shifts", C.POINTER(care_shift)), ("nshifts", C.c_int32),
+                ("Z", C.c_void_p), ("ldz", C.c_int64), ("rmax", C.c_int32)]
+
+
+class care_instance_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("r", C.c_int32), ("stats", care_stats), ("message", C.c_char * 128)]
+
+
 P = C.c_void_p
 I32, I64, DBL = C.c_int32, C.c_int64, C.c_double
 PI32 = C.POINTER(C.c_int32)
@@ -80,6 +90,8 @@ SIGNATURES = {
     "care_solve": (I32, [P, C.POINTER(care_csr), P, I32, P, I32, DBL, C.POINTER(care_shift), I32,
                          C.POINTER(care_opts), P, I64, I32, PI32, C.POINTER(care_stats)]),
     "care_penzl_shifts": (I32, [P, C.POINTER(care_csr), I32, I32, I32, I32, C.POINTER(care_shift), PI32]),
+    "care_solve_batch": (I32, [P, I32, C.POINTER(care_instance), DBL, C.POINTER(care_opts), I32,
+                               C.POINTER(care_instance_result)]),
     "care_ritz_values": (I32, [PDBL, I32, I64, PDBL, PDBL]),
     "care_penzl_select": (I32, [PDBL, PDBL, I32, I32, C.POINTER(care_shift), PI32]),
 }

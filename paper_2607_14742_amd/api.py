@@ -255,6 +255,41 @@ def care_solve(ctx, A, B, C_, tol=1e-10, shifts=None, prec="fp32", opts=None, rm
     return Z[:, :r.value], stats.to_dict(), st
 
 
+def care_solve_batch(ctx, problems, tol=1e-10, prec="fp32", opts=None, rmax=None, workers=0, **kw):
+    """Batched Framework 1.  problems: list of (A DeviceCSR, B n x m tensor,
+    C p x n tensor, shifts or None).  Returns a list of
+    (Z, stats dict, status, message), one per problem; raises CareError only
+    for a batch-level failure (use the per-instance status otherwise)."""
+    from ._lib import care_instance, care_instance_result
+    opts = opts or default_opts(prec, **kw)
+    count = len(problems)
+    inst = (care_instance * max(count, 1))()
+    res = (care_instance_result * max(count, 1))()
+    keep = []
+    for k, (A, B, Cm, shifts) in enumerate(problems):
+        B = tight(B)
+        Cr = Cm.contiguous()
+        n, m = B.shape
+        rk = rmax or min(n, 4096)
+        Z = empty_colmajor(n, rk, B.device)
+        arr, ns = _shift_array(shifts if shifts is not None else [])
+        keep.append((A, B, Cr, Z, arr))
+        inst[k].A = C.pointer(A._c)
+        inst[k].B, inst[k].m = (B.data_ptr() if m > 0 else None), m
+        inst[k].C, inst[k].p = Cr.data_ptr(), Cr.shape[0]
+        inst[k].shifts, inst[k].nshifts = (C.cast(arr, C.POINTER(care_shift)) if ns else None), ns
+        inst[k].Z, inst[k].ldz, inst[k].rmax = Z.data_ptr(), _ld(Z), rk
+    st = _lib().care_solve_batch(ctx.h, count, inst, tol, C.byref(opts), workers, res)
+    if st < 0 and all(res[k].status >= 0 for k in range(count)):
+        raise CareError(st, _lib().care_last_error().decode())
+    out = []
+    for k in range(count):
+        Z = keep[k][3]
+        r = res[k].r if res[k].status >= 0 else 0
+        out.append((Z[:, :r], res[k].stats.to_dict(), res[k].status, res[k].message.decode()))
+    return out
+
+
 def penzl_shifts(ctx, A, l0=16, kp=20, km=10, real_only=False):
     """Heuristic shift set from Ritz values of A^T and A^-T (GPU Arnoldi)."""
     out = (care_shift * (l0 + 1))()

@@ -90,22 +90,13 @@ care_status care_ctx_create(care_ctx** out, int32_t device, void* stream) {
     int count = 0;
     HIP_CHECK(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) fail(CARE_ERR_ARG, "device index out of range");
-    HIP_CHECK(hipSetDevice(device));
     care_ctx* c = new care_ctx();
-    c->c.device = device;
-    c->c.user_stream = (hipStream_t)stream;
-    HIP_CHECK(hipStreamCreateWithFlags(&c->c.stream, hipStreamNonBlocking));   // default priority
-    HIP_CHECK(hipEventCreateWithFlags(&c->c.order_event, hipEventDisableTiming));
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
-      c->c.num_cu = prop.multiProcessorCount;
-    c->c.arena = new Arena(c->c.stream);
-    if (rocblas_create_handle(&c->c.blas) != rocblas_status_success) {
-      delete c->c.arena;
+    try {
+      ctx_init(c->c, device, (hipStream_t)stream);
+    } catch (...) {
       delete c;
-      fail(CARE_ERR_DEVICE, "rocblas_create_handle failed");
+      throw;
     }
-    rocblas_set_stream(c->c.blas, c->c.stream);
     *out = c;
     return CARE_OK;
   });
@@ -113,21 +104,7 @@ care_status care_ctx_create(care_ctx** out, int32_t device, void* stream) {
 
 void care_ctx_destroy(care_ctx* c) {
   if (!c) return;
-  (void)hipSetDevice(c->c.device);
-  (void)hipStreamSynchronize(c->c.stream);
-  for (auto& e : c->c.event_pool) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
-  }
-  for (auto& e : c->c.pending_events) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
-  }
-  if (c->c.blas) rocblas_destroy_handle(c->c.blas);
-  delete c->c.arena;
-  if (c->c.pinned) (void)hipHostFree(c->c.pinned);
-  if (c->c.order_event) (void)hipEventDestroy(c->c.order_event);
-  if (c->c.stream) (void)hipStreamDestroy(c->c.stream);
+  ctx_release(c->c);
   delete c;
 }
 
@@ -399,6 +376,19 @@ care_status care_penzl_shifts(care_ctx* cx, const care_csr* A, int32_t l0, int32
     std::vector<Shift> s = penzl_shifts(ctx, op, l0, kp, km, real_only != 0);
     *count = (int)s.size();
     for (size_t i = 0; i < s.size(); ++i) out[i] = care_shift{s[i].re, s[i].im};
+    return CARE_OK;
+  });
+}
+
+care_status care_solve_batch(care_ctx* cx, int32_t count, const care_instance* instances, double tol,
+                             const care_opts* opts, int32_t workers, care_instance_result* results) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    if (!(tol > 0)) fail(CARE_ERR_ARG, "tol must be positive");
+    solve_batch(ctx, count, instances, tol, opts, workers, results);
+    for (int k = 0; k < count; ++k)
+      if (results[k].status < 0)
+        fail((care_status)results[k].status, "instance " + std::to_string(k) + ": " + results[k].message);
     return CARE_OK;
   });
 }

@@ -1,0 +1,92 @@
+// Batched Framework 1 over independent CARE instances of uneven sizes.
+//
+// Each instance runs the single-instance solver unchanged.  Concurrency comes
+// from W worker threads, each owning a context (non-blocking stream, rocBLAS
+// handle, workspace arena) on the same device: the host-side decisions of one
+// instance (Krylov polls, eigen-splits) never stall the kernels of another,
+// and the sparse products of small instances, which alone cannot fill 256
+// CUs, overlap on the device.  Instances are taken largest first from a
+// shared counter (longest-processing-time order), so the big ones do not
+// start last.
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <thread>
+
+#include "care.hpp"
+
+namespace mpcare {
+
+void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, const care_opts* opts, int workers,
+                 care_instance_result* res) {
+  if (count < 0) fail(CARE_ERR_ARG, "negative instance count");
+  if (count == 0) return;
+  if (!inst || !res) fail(CARE_ERR_ARG, "instances or results is NULL");
+  const int nw = workers > 0 ? std::min(workers, count) : std::min(count, 8);
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  auto size_of = [&](int k) -> int64_t { return inst[k].A ? inst[k].A->n : 0; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return size_of(a) > size_of(b); });
+  for (int k = 0; k < count; ++k) {
+    std::memset(&res[k], 0, sizeof(res[k]));
+    res[k].status = CARE_ERR_DEVICE;   // until a worker has run the instance
+    std::strncpy(res[k].message, "not run", sizeof(res[k].message) - 1);
+  }
+
+  std::atomic<int> next{0};
+  std::vector<std::string> setup_err(nw);
+  auto work = [&](int w) {
+    Ctx wc;
+    try {
+      ctx_init(wc, ctx->device, ctx->stream);
+      // ordered after everything the caller queued (ctx->stream waits on it)
+      HIP_CHECK(hipEventRecord(wc.order_event, wc.user_stream));
+      HIP_CHECK(hipStreamWaitEvent(wc.stream, wc.order_event, 0));
+    } catch (const CareError& e) {
+      setup_err[w] = e.msg;
+      return;
+    } catch (...) {
+      setup_err[w] = "worker context setup failed";
+      return;
+    }
+    for (int i; (i = next.fetch_add(1)) < count;) {
+      const int k = order[i];
+      const care_instance& I = inst[k];
+      care_instance_result& R = res[k];
+      int r = 0;
+      care_status warn = CARE_OK;
+      R.message[0] = '\0';
+      try {
+        if (!I.A || I.A->n < 1) fail(CARE_ERR_ARG, "instance A is NULL or empty");
+        care_solve_impl(&wc, I.A, I.B, I.m, I.C, I.p, tol, I.shifts, I.nshifts, opts, I.Z, I.ldz, I.rmax, &r,
+                        &R.stats, &warn);
+        R.status = warn;
+      } catch (const CareError& e) {
+        R.status = e.status;
+        std::strncpy(R.message, e.msg.c_str(), sizeof(R.message) - 1);
+      } catch (const std::bad_alloc&) {
+        R.status = CARE_ERR_NOMEM;
+        std::strncpy(R.message, "host allocation failed", sizeof(R.message) - 1);
+      } catch (...) {
+        R.status = CARE_ERR_DEVICE;
+        std::strncpy(R.message, "internal error", sizeof(R.message) - 1);
+      }
+      R.r = r;
+      try {
+        wc.sync();   // a failed instance may leave work queued
+      } catch (...) {
+      }
+    }
+    ctx_release(wc);
+  };
+  std::vector<std::thread> th;
+  th.reserve(nw);
+  for (int w = 0; w < nw; ++w) th.emplace_back(work, w);
+  for (auto& t : th) t.join();
+  for (int w = 0; w < nw; ++w)
+    if (!setup_err[w].empty()) fail(CARE_ERR_DEVICE, "batch worker: " + setup_err[w]);
+}
+
+}  // namespace mpcare

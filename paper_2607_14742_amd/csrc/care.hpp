@@ -21,6 +21,11 @@ void care_solve_impl(Ctx* ctx, const care_csr* A, const double* B, int m, const 
                      const care_shift* shifts, int nshifts, const care_opts* opts, double* Z, int64_t ldz, int rmax,
                      int* r_out, care_stats* stats, care_status* warn);
 
+// Batched solve of independent instances on concurrent worker streams
+// (batch.hip); per-instance outcomes in res.
+void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, const care_opts* opts, int workers,
+                 care_instance_result* res);
+
 // Penzl's heuristic (penzl.hip): Ritz values of A^T and A^-T on the GPU, then
 // the greedy min-max choice of l0 shifts; real_only keeps real parts.
 std::vector<Shift> penzl_shifts(Ctx* ctx, const SellOp& A64, int l0, int kp, int km, bool real_only);

@@ -116,6 +116,14 @@ struct Ctx {
   std::pair<hipEvent_t, hipEvent_t> event_pair();
 };
 
+// Set up a context on `device`: its own non-blocking stream (default
+// priority), the ordering event, a rocBLAS handle and the workspace arena.
+// `user_stream` is the caller's stream the context's work is ordered after.
+void ctx_init(Ctx& c, int device, hipStream_t user_stream);
+// Release everything ctx_init acquired (waits for the stream first).
+void ctx_release(Ctx& c);
+
+
 // RAII device buffer from the context arena
 template <typename T>
 struct DBuf {

@@ -150,4 +150,47 @@ void dzero(Ctx* ctx, void* dst, size_t bytes) {
   }
 }
 
+void ctx_init(Ctx& c, int device, hipStream_t user_stream) {
+  HIP_CHECK(hipSetDevice(device));
+  c.device = device;
+  c.user_stream = user_stream;
+  HIP_CHECK(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));   // default priority
+  HIP_CHECK(hipEventCreateWithFlags(&c.order_event, hipEventDisableTiming));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c.num_cu = prop.multiProcessorCount;
+  c.arena = new Arena(c.stream);
+  if (rocblas_create_handle(&c.blas) != rocblas_status_success) {
+    c.blas = nullptr;
+    ctx_release(c);
+    fail(CARE_ERR_DEVICE, "rocblas_create_handle failed");
+  }
+  rocblas_set_stream(c.blas, c.stream);
+}
+
+void ctx_release(Ctx& c) {
+  (void)hipSetDevice(c.device);
+  if (c.stream) (void)hipStreamSynchronize(c.stream);
+  for (auto& e : c.event_pool) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (auto& e : c.pending_events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  c.event_pool.clear();
+  c.pending_events.clear();
+  if (c.blas) rocblas_destroy_handle(c.blas);
+  c.blas = nullptr;
+  delete c.arena;
+  c.arena = nullptr;
+  if (c.pinned) (void)hipHostFree(c.pinned);
+  c.pinned = nullptr;
+  if (c.order_event) (void)hipEventDestroy(c.order_event);
+  c.order_event = nullptr;
+  if (c.stream) (void)hipStreamDestroy(c.stream);
+  c.stream = nullptr;
+}
+
 }  // namespace mpcare

@@ -249,3 +249,10 @@ def fdm_batch_sizes(count: int = 32, seed: int = DEFAULT_SEED):
     ms = rng.integers(1, 9, size=count)
     ps = rng.integers(1, 9, size=count)
     return Ns, [int(v) for v in ms], [int(v) for v in ps]
+
+
+def fdm_batch_problem(i: int, count: int = 32, seed: int = DEFAULT_SEED) -> Problem:
+    """Instance i of the uneven FDM batch: grid N_i, (m_i, p_i) from
+    ``fdm_batch_sizes``, Gaussian factors from seed + i, 16 shifts."""
+    Ns, ms, ps = fdm_batch_sizes(count, seed)
+    return fdm2d_problem(Ns[i], ms[i], ps[i], seed=seed + i, name=f"batch{i}_fdm2d_{Ns[i]}")
