@@ -115,6 +115,8 @@ typedef struct {
   int32_t krylov_block_tol; /* 1: Krylov accuracy relative to the largest column of
                              the right-hand side block instead of each column (0)  */
   int32_t penzl_real;     /* auto shifts: 1 keeps the real parts of the Ritz values */
+  int32_t spmm_split;     /* BiCGStab products: 0 chooses by the L2 footprint of the
+                             fused gathers, 1 fused, 2 split (update pass + product) */
 } care_opts;
 
 /* Statistics written by the solvers (host struct). */
@@ -249,7 +251,9 @@ care_status care_solve(care_ctx* ctx, const care_csr* A, const double* B, int32_
 
 /* One CARE instance of a batch: the arguments care_solve takes for it. */
 typedef struct {
-  const care_csr* A;            /* device CSR of A (n x n)                        */
+  const care_csr* A;            /* device CSR of A (n x n), or NULL for a dense A  */
+  const double* A_dense;        /* dense A (device, column-major) when A is NULL   */
+  int64_t n_dense, lda_dense;
   const double* B;              /* device, n x m column-major (ld n)              */
   int32_t m;
   const double* C;              /* device, p x n row-major                        */
@@ -281,6 +285,18 @@ typedef struct {
  * buffer. */
 care_status care_solve_batch(care_ctx* ctx, int32_t count, const care_instance* instances, double tol,
                              const care_opts* opts, int32_t workers, care_instance_result* results);
+
+/* care_solve for a dense A (device, n x n column-major, leading dimension
+ * lda >= n), e.g. the dense test CAREs of Sec. 5.1.  The shifted solves
+ * factor A^T + p I once per real shift (partially pivoted LU in the inner
+ * precision, rocSOLVER getrf) and reuse the factors for every right-hand
+ * side block; products with A^T are GEMMs.  Real shifts only
+ * (CARE_ERR_NOT_IMPLEMENTED for complex ones) and inner precision FP64 or
+ * FP32.  Other arguments, outputs and statuses as care_solve. */
+care_status care_solve_dense(care_ctx* ctx, const double* A, int64_t n, int64_t lda, const double* B, int32_t m,
+                             const double* C, int32_t p, double tol, const care_shift* shifts, int32_t nshifts,
+                             const care_opts* opts, double* Z, int64_t ldz, int32_t rmax, int32_t* r_out,
+                             care_stats* stats);
 
 /* Penzl-type heuristic shifts (the "shifts from Krylov subspaces" of Sec. 5,
  * read as Penzl's procedure): Ritz values of kp Arnoldi steps with A^T and

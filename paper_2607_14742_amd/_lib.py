@@ -37,6 +37,7 @@ class care_opts(C.Structure):
         ("check_every", C.c_int32), ("penzl_l0", C.c_int32), ("penzl_kp", C.c_int32), ("penzl_km", C.c_int32),
         ("profile", C.c_int32), ("Z_init", C.c_void_p), ("ldz_init", C.c_int64), ("r_init", C.c_int32),
         ("adi_deflate", C.c_int32), ("krylov_block_tol", C.c_int32), ("penzl_real", C.c_int32),
+        ("spmm_split", C.c_int32),
     ]
 
 
@@ -57,7 +58,8 @@ class care_stats(C.Structure):
 
 
 class care_instance(C.Structure):
-    _fields_ = [("A", C.POINTER(care_csr)), ("B", C.c_void_p), ("m", C.c_int32), ("C", C.c_void_p),
+    _fields_ = [("A", C.POINTER(care_csr)), ("A_dense", C.c_void_p), ("n_dense", C.c_int64),
+                ("lda_dense", C.c_int64), ("B", C.c_void_p), ("m", C.c_int32), ("C", C.c_void_p),
                 ("p", C.c_int32), ("shifts", C.POINTER(care_shift)), ("nshifts", C.c_int32),
                 ("Z", C.c_void_p), ("ldz", C.c_int64), ("rmax", C.c_int32)]
 
@@ -90,6 +92,8 @@ SIGNATURES = {
     "care_solve": (I32, [P, C.POINTER(care_csr), P, I32, P, I32, DBL, C.POINTER(care_shift), I32,
                          C.POINTER(care_opts), P, I64, I32, PI32, C.POINTER(care_stats)]),
     "care_penzl_shifts": (I32, [P, C.POINTER(care_csr), I32, I32, I32, I32, C.POINTER(care_shift), PI32]),
+    "care_solve_dense": (I32, [P, P, I64, I64, P, I32, P, I32, DBL, C.POINTER(care_shift), I32,
+                               C.POINTER(care_opts), P, I64, I32, PI32, C.POINTER(care_stats)]),
     "care_solve_batch": (I32, [P, I32, C.POINTER(care_instance), DBL, C.POINTER(care_opts), I32,
                                C.POINTER(care_instance_result)]),
     "care_ritz_values": (I32, [PDBL, I32, I64, PDBL, PDBL]),

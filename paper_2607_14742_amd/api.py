@@ -255,9 +255,29 @@ def care_solve(ctx, A, B, C_, tol=1e-10, shifts=None, prec="fp32", opts=None, rm
     return Z[:, :r.value], stats.to_dict(), st
 
 
+def care_solve_dense(ctx, A, B, C_, tol=1e-10, shifts=None, prec="fp32", opts=None, rmax=None, **kw):
+    """Framework 1 for a dense A (n x n device tensor, FP64).  Returns
+    (Z, stats dict, status)."""
+    A = colmajor(A.to(torch.float64))
+    B = tight(B)
+    Cr = C_.contiguous()
+    n, m = B.shape
+    p = Cr.shape[0]
+    opts = opts or default_opts(prec, **kw)
+    rmax = rmax or min(n, 4096)
+    Z = empty_colmajor(n, rmax, B.device)
+    r = C.c_int32(0)
+    stats = care_stats()
+    arr, ns = _shift_array(shifts if shifts is not None else [])
+    st = _check(_lib().care_solve_dense(ctx.h, _ptr(A), n, _ld(A), _ptr(B), m, _ptr(Cr), p, tol, arr, ns,
+                                        C.byref(opts), _ptr(Z), _ld(Z), rmax, C.byref(r), C.byref(stats)))
+    return Z[:, :r.value], stats.to_dict(), st
+
+
 def care_solve_batch(ctx, problems, tol=1e-10, prec="fp32", opts=None, rmax=None, workers=0, **kw):
-    """Batched Framework 1.  problems: list of (A DeviceCSR, B n x m tensor,
-    C p x n tensor, shifts or None).  Returns a list of
+    """Batched Framework 1.  problems: list of (A, B n x m tensor, C p x n
+    tensor, shifts or None) with A a DeviceCSR or a dense n x n FP64 device
+    tensor.  Returns a list of
     (Z, stats dict, status, message), one per problem; raises CareError only
     for a batch-level failure (use the per-instance status otherwise)."""
     from ._lib import care_instance, care_instance_result
@@ -273,8 +293,12 @@ def care_solve_batch(ctx, problems, tol=1e-10, prec="fp32", opts=None, rmax=None
         rk = rmax or min(n, 4096)
         Z = empty_colmajor(n, rk, B.device)
         arr, ns = _shift_array(shifts if shifts is not None else [])
+        if isinstance(A, DeviceCSR):
+            inst[k].A = C.pointer(A._c)
+        else:
+            A = colmajor(A.to(torch.float64))
+            inst[k].A_dense, inst[k].n_dense, inst[k].lda_dense = A.data_ptr(), A.shape[0], _ld(A)
         keep.append((A, B, Cr, Z, arr))
-        inst[k].A = C.pointer(A._c)
         inst[k].B, inst[k].m = (B.data_ptr() if m > 0 else None), m
         inst[k].C, inst[k].p = Cr.data_ptr(), Cr.shape[0]
         inst[k].shifts, inst[k].nshifts = (C.cast(arr, C.POINTER(care_shift)) if ns else None), ns

@@ -75,6 +75,7 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->penzl_kp = 20;
   o->penzl_km = 10;
   o->penzl_real = 0;
+  o->spmm_split = 0;
   o->profile = 0;
   o->Z_init = nullptr;
   o->ldz_init = 0;
@@ -250,6 +251,7 @@ care_status lyap_lradi(care_ctx* cx, const care_csr* A, const double* B, const d
     lp.deflate = false;      // keep the documented block layout of Z
     ctx->reset_counters();
     ctx->profile = o->profile;
+    ctx->spmm_split = o->spmm_split;
     const double t0 = now_s();
     SellOp op;
     build_sell(ctx, A, r.prec, op);
@@ -258,14 +260,15 @@ care_status lyap_lradi(care_ctx* cx, const care_csr* A, const double* B, const d
     auto run = [&](auto tag) {
       using T = decltype(tag);
       DBuf<T> Bs(ctx, (size_t)ld * std::max(m, 1)), Ks(ctx, (size_t)ld * std::max(m, 1)),
-          Ws(ctx, (size_t)ld * std::max(w, 1)), Zs(ctx, (size_t)ld * std::max(zcap, 1));
+          Ws(ctx, (size_t)ld * std::max(w, 1));
+      ZBuffer<T> Zs;
+      Zs.init(ctx, n, std::min(zcap, 16 * std::max(w, 1)));
       if (smw) {
         copy_cols<double, T>(ctx, n, m, B, n, Bs.get(), ld);
         copy_cols<double, T>(ctx, n, m, K, n, Ks.get(), ld);
       }
       copy_cols<double, T>(ctx, n, w, W, ldw, Ws.get(), ld);
-      lo = lradi_run<T>(ctx, op, Bs.get(), smw ? Ks.get() : nullptr, smw ? m : 0, Ws.get(), w, sh, lp, Zs.get(),
-                        zcap);
+      lo = lradi_run<T>(ctx, op, Bs.get(), smw ? Ks.get() : nullptr, smw ? m : 0, Ws.get(), w, sh, lp, Zs, zcap);
       *r_out = lo.zcols;
       if (lo.zcols > rmax) fail(CARE_ERR_CAPACITY, "Z needs " + std::to_string(lo.zcols) + " columns");
       copy_cols<T, double>(ctx, n, lo.zcols, Zs.get(), ld, Z, ldz);
@@ -359,8 +362,24 @@ care_status care_solve(care_ctx* cx, const care_csr* A, const double* B, int32_t
     check_csr_shape(A);
     care_stats local;
     care_status warn = CARE_OK;
-    care_solve_impl(ctx, A, B, m, C, p, tol, shifts, nshifts, opts, Z, ldz, rmax, r_out, stats ? stats : &local,
+    care_solve_impl(ctx, sparse_spec(A), B, m, C, p, tol, shifts, nshifts, opts, Z, ldz, rmax, r_out,
+                    stats ? stats : &local,
                     &warn);
+    return warn;
+  });
+}
+
+care_status care_solve_dense(care_ctx* cx, const double* A, int64_t n, int64_t lda, const double* B, int32_t m,
+                             const double* C, int32_t p, double tol, const care_shift* shifts, int32_t nshifts,
+                             const care_opts* opts, double* Z, int64_t ldz, int32_t rmax, int32_t* r_out,
+                             care_stats* stats) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    if (!A || n < 1 || lda < n) fail(CARE_ERR_ARG, "invalid dense A");
+    care_stats local;
+    care_status warn = CARE_OK;
+    care_solve_impl(ctx, dense_spec(A, n, lda), B, m, C, p, tol, shifts, nshifts, opts, Z, ldz, rmax, r_out,
+                    stats ? stats : &local, &warn);
     return warn;
   });
 }

@@ -193,7 +193,7 @@ static KrylovResult smw_step(Ctx* ctx, const SellOp& op, const T* B, const T* K,
 
 template <typename T>
 LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T* W, int w,
-                   const std::vector<Shift>& shifts, const LradiParams& prm, T* Z, int zcap) {
+                   const std::vector<Shift>& shifts, const LradiParams& prm, ZBuffer<T>& Z, int zmax) {
   LradiOut out;
   const int64_t n = op.n;
   const int64_t ld = pad_ld(n);
@@ -228,7 +228,8 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
     ShiftCache& sc = cache[idx % shifts.size()];
     const bool cp = p.im != 0.0;
     const int width = (cp ? 2 : 1) * wa;
-    if (out.zcols + width > zcap) fail(CARE_ERR_CAPACITY, "LR-ADI factor buffer too small");
+    if (out.zcols + width > zmax) fail(CARE_ERR_CAPACITY, "LR-ADI factor buffer too small");
+    Z.reserve(ctx, out.zcols, out.zcols + width);
     KrylovResult kr = smw_step<T>(ctx, op, B, K, m, W, wa, p, sc, prm, rhs.get(), sol.get(), yr, yi);
     out.krylov_unconverged += kr.unconverged;
     out.krylov_max_iters = std::max(out.krylov_max_iters, kr.max_iters);
@@ -236,7 +237,7 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
       h2d(ctx, dYr.get(), yr.data(), (size_t)m * wa * sizeof(double));
       if (cp) h2d(ctx, dYi.get(), yi.data(), (size_t)m * wa * sizeof(double));
     }
-    T* Zb = Z + (int64_t)out.zcols * ld;
+    T* Zb = Z.get() + (int64_t)out.zcols * ld;
     dim3 g(ceil_div(n, 256), wa);
     const T* Sp = smw ? (const T*)sc.S.get() : nullptr;
     if (!cp) {
@@ -344,8 +345,8 @@ template KrylovResult shifted_solve<float>(Ctx*, const SellOp&, const float*, co
                                            Shift, const LradiParams&, float*);
 
 template LradiOut lradi_run<double>(Ctx*, const SellOp&, const double*, const double*, int, double*, int,
-                                    const std::vector<Shift>&, const LradiParams&, double*, int);
+                                    const std::vector<Shift>&, const LradiParams&, ZBuffer<double>&, int);
 template LradiOut lradi_run<float>(Ctx*, const SellOp&, const float*, const float*, int, float*, int,
-                                   const std::vector<Shift>&, const LradiParams&, float*, int);
+                                   const std::vector<Shift>&, const LradiParams&, ZBuffer<float>&, int);
 
 }  // namespace mpcare

@@ -12,6 +12,7 @@
 // where S = M^{-1} K and T^{-1} are cached per shift for the whole solve.
 #pragma once
 
+#include <algorithm>
 #include <complex>
 
 #include "krylov.hpp"
@@ -46,13 +47,38 @@ struct LradiOut {
 // shift list checks: Re < 0, complex shifts as (p, conj p) with Im p > 0 first
 std::vector<Shift> check_shifts(const care_shift* s, int count);
 
+// Growable n x cap column buffer (ld pad_ld(n)) for the LR-ADI factor: the
+// factor's final width is known only at the end (column deflation), so the
+// buffer starts small and grows by half again when full, keeping the columns
+// already written.
+template <typename T>
+struct ZBuffer {
+  DBuf<T> buf;
+  int64_t ld = 0;
+  int cap = 0;
+  void init(Ctx* ctx, int64_t n, int cap0) {
+    ld = pad_ld(n);
+    cap = std::max(cap0, 1);
+    buf = DBuf<T>(ctx, (size_t)ld * cap);
+  }
+  void reserve(Ctx* ctx, int used, int need) {
+    if (need <= cap) return;
+    const int nc = std::max(need, cap + cap / 2);
+    DBuf<T> nb(ctx, (size_t)ld * nc);
+    if (used > 0) d2d(ctx, nb.get(), buf.get(), (size_t)ld * used * sizeof(T));
+    buf = std::move(nb);
+    cap = nc;
+  }
+  T* get() const { return buf.get(); }
+};
+
 // Run LR-ADI in vector precision T (double or float) on the prepared
 // operator.  B, K: n x m (K may be NULL), W: n x w, all with leading
 // dimension pad_ld(n); W is overwritten by the final residual factor.  Z
-// (ld pad_ld(n), capacity zcap columns) receives the factor blocks.
+// receives the factor blocks (growing as needed up to zmax columns).
 template <typename T>
 LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T* W, int w,
-                   const std::vector<Shift>& shifts, const LradiParams& prm, T* Z, int zcap);
+                   const std::vector<Shift>& shifts, const LradiParams& prm, ZBuffer<T>& Z, int zmax);
 
 // One SMW shifted solve (A_k^T + p I) V = W (the building block of
 // lradi_run), V explicit: n x w real, or n x 2w interleaved for complex p.

@@ -27,7 +27,13 @@ void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, con
   const int nw = workers > 0 ? std::min(workers, count) : std::min(count, 8);
   std::vector<int> order(count);
   std::iota(order.begin(), order.end(), 0);
-  auto size_of = [&](int k) -> int64_t { return inst[k].A ? inst[k].A->n : 0; };
+  auto spec_of = [&](int k) -> OpSpec {
+    return inst[k].A ? sparse_spec(inst[k].A) : dense_spec(inst[k].A_dense, inst[k].n_dense, inst[k].lda_dense);
+  };
+  auto size_of = [&](int k) -> int64_t {
+    const OpSpec s = spec_of(k);
+    return (s.csr || s.dense) ? s.size() : 0;
+  };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return size_of(a) > size_of(b); });
   for (int k = 0; k < count; ++k) {
     std::memset(&res[k], 0, sizeof(res[k]));
@@ -59,8 +65,10 @@ void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, con
       care_status warn = CARE_OK;
       R.message[0] = '\0';
       try {
-        if (!I.A || I.A->n < 1) fail(CARE_ERR_ARG, "instance A is NULL or empty");
-        care_solve_impl(&wc, I.A, I.B, I.m, I.C, I.p, tol, I.shifts, I.nshifts, opts, I.Z, I.ldz, I.rmax, &r,
+        const OpSpec spec = spec_of(k);
+        if (!spec.csr && !spec.dense) fail(CARE_ERR_ARG, "instance A is NULL");
+        if (spec.size() < 1 || (spec.dense && spec.lda < spec.n)) fail(CARE_ERR_ARG, "instance A is empty or invalid");
+        care_solve_impl(&wc, spec, I.B, I.m, I.C, I.p, tol, I.shifts, I.nshifts, opts, I.Z, I.ldz, I.rmax, &r,
                         &R.stats, &warn);
         R.status = warn;
       } catch (const CareError& e) {
@@ -78,6 +86,9 @@ void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, con
         wc.sync();   // a failed instance may leave work queued
       } catch (...) {
       }
+      // concurrent workers share the device memory: hand this instance's
+      // cached workspace back before the next one
+      wc.arena->trim();
     }
     ctx_release(wc);
   };

@@ -103,8 +103,10 @@ static void stage0(Ctx* ctx, SolveState& S, TruncResult& Zout, care_stats* st, s
   const int zcap = lradi_capacity(wmax, S.prm.j_max);
   DBuf<T> K(ctx, (size_t)ld * std::max(m, 1)), Kn(ctx, (size_t)ld * std::max(m, 1)),
       dK(ctx, (size_t)ld * std::max(m, 1));
-  DBuf<T> W(ctx, (size_t)ld * wmax), Zb(ctx, (size_t)ld * zcap);
-  DBuf<double> Y(ctx, (size_t)zcap * std::max(m, 1));
+  DBuf<T> W(ctx, (size_t)ld * wmax);
+  ZBuffer<T> Zb;
+  Zb.init(ctx, n, std::min(zcap, 16 * wmax));
+  DBuf<double> Y;
   LradiParams lp;
   lp.tol = S.prm.tau_L;
   lp.jmax = S.prm.j_max;
@@ -120,13 +122,14 @@ static void stage0(Ctx* ctx, SolveState& S, TruncResult& Zout, care_stats* st, s
     d2d(ctx, W.get(), Cts.get(), (size_t)ld * p * sizeof(T));
     if (w > p) d2d(ctx, W.get() + (int64_t)p * ld, K.get(), (size_t)ld * m * sizeof(T));
     LradiOut lo = lradi_run<T>(ctx, *S.As, Bs.get(), (i > 0 && m > 0) ? K.get() : nullptr, m, W.get(), w, S.shifts,
-                               lp, Zb.get(), zcap);
+                               lp, Zb, zcap);
     st->iter0_outer += 1;
     st->iter0_inner += lo.steps;
     zcols = lo.zcols;
     double rel;
     if (m > 0) {
       // K_{i+1} = Z (Z^T B)
+      Y.resize(ctx, (size_t)std::max(zcols, 1) * m);
       gram(ctx, n, Zb.get(), ld, zcols, Bs.get(), ld, m, Y.get(), zcols);
       tsgemm<T, T>(ctx, n, Zb.get(), ld, zcols, Y.get(), zcols, m, 1.0, 0.0, Kn.get(), ld);
       d2d(ctx, dK.get(), Kn.get(), (size_t)ld * m * sizeof(T));
@@ -179,7 +182,8 @@ static void correction(Ctx* ctx, SolveState& S, const TruncResult& Zk, const Res
   if (rf.rp) copy_cols<double, T>(ctx, n, rf.rp, rf.Cp.get(), ld, W.get(), ld);
   if (rf.rm) copy_cols<double, T>(ctx, n, rf.rm, rf.Cm.get(), ld, W.get() + (int64_t)rf.rp * ld, ld);
   const int zcap = lradi_capacity(w, S.prm.j_max);
-  DBuf<T> Zb(ctx, (size_t)ld * zcap);
+  ZBuffer<T> Zb;
+  Zb.init(ctx, n, std::min(zcap, 16 * std::max(w, 1)));
   LradiParams lp;
   lp.tol = S.prm.tau_L;
   lp.jmax = S.prm.j_max;
@@ -189,7 +193,7 @@ static void correction(Ctx* ctx, SolveState& S, const TruncResult& Zk, const Res
   lp.deflate = S.prm.deflate;
   lp.group_tol = S.prm.block_tol;
   LradiOut lo = lradi_run<T>(ctx, *S.As, Bs.get(), (m > 0 && Zk.r > 0) ? Ks.get() : nullptr, m, W.get(), w,
-                             S.shifts, lp, Zb.get(), zcap);
+                             S.shifts, lp, Zb, zcap);
   st->iter_inner += lo.steps;
   const int zcols = lo.zcols;
   std::vector<int> map;
@@ -215,14 +219,34 @@ static double fro_of_gram(Ctx* ctx, int64_t n, const double* X, int64_t ld, int 
   return std::sqrt(s);
 }
 
-void care_solve_impl(Ctx* ctx, const care_csr* A, const double* B, int m, const double* C, int p, double tol,
+OpSpec sparse_spec(const care_csr* A) {
+  OpSpec s;
+  s.csr = A;
+  return s;
+}
+
+OpSpec dense_spec(const double* A, int64_t n, int64_t lda) {
+  OpSpec s;
+  s.dense = A;
+  s.n = n;
+  s.lda = lda;
+  return s;
+}
+
+void build_op(Ctx* ctx, const OpSpec& A, Prec prec, SellOp& op) {
+  if (A.csr) build_sell(ctx, A.csr, prec, op);
+  else build_dense(ctx, A.dense, A.lda, A.n, prec, op);
+}
+
+void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const double* C, int p, double tol,
                      const care_shift* shifts, int nshifts, const care_opts* opts, double* Zout, int64_t ldz,
                      int rmax, int* r_out, care_stats* st, care_status* warn) {
   const double t0 = now_s();
   *warn = CARE_OK;
   std::memset(st, 0, sizeof(*st));
-  if (!A) fail(CARE_ERR_ARG, "A is NULL");
-  const int64_t n = A->n;
+  if (!A.csr && !A.dense) fail(CARE_ERR_ARG, "A is NULL");
+  const int64_t n = A.size();
+  if (n < 1) fail(CARE_ERR_ARG, "A must have n >= 1");
   if (m < 0 || p < 1) fail(CARE_ERR_ARG, "need m >= 0 and p >= 1");
   if (m > 0 && !B) fail(CARE_ERR_ARG, "B is NULL");
   if (!C) fail(CARE_ERR_ARG, "C is NULL");
@@ -237,14 +261,15 @@ void care_solve_impl(Ctx* ctx, const care_csr* A, const double* B, int m, const 
   S.p = p;
   ctx->reset_counters();
   ctx->profile = opts ? opts->profile : 0;
+  ctx->spmm_split = opts ? opts->spmm_split : 0;
 
   SellOp A64, As;
-  build_sell(ctx, A, Prec::F64, A64);
+  build_op(ctx, A, Prec::F64, A64);
   S.A64 = &A64;
   if (S.prm.prec == Prec::F64) {
     S.As = &A64;
   } else {
-    build_sell(ctx, A, S.prm.prec, As);
+    build_op(ctx, A, S.prm.prec, As);
     S.As = &As;
   }
   if (nshifts > 0) {

@@ -17,7 +17,18 @@ struct Resolved {
 
 Resolved resolve_opts(const care_opts* o, double tol);
 
-void care_solve_impl(Ctx* ctx, const care_csr* A, const double* B, int m, const double* C, int p, double tol,
+// The operator of one solve: a sparse CSR of A, or a dense column-major A.
+struct OpSpec {
+  const care_csr* csr = nullptr;
+  const double* dense = nullptr;   // device, n x n, leading dimension lda
+  int64_t n = 0, lda = 0;
+  int64_t size() const { return csr ? csr->n : n; }
+};
+OpSpec sparse_spec(const care_csr* A);
+OpSpec dense_spec(const double* A, int64_t n, int64_t lda);
+void build_op(Ctx* ctx, const OpSpec& A, Prec prec, SellOp& op);
+
+void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const double* C, int p, double tol,
                      const care_shift* shifts, int nshifts, const care_opts* opts, double* Z, int64_t ldz, int rmax,
                      int* r_out, care_stats* stats, care_status* warn);
 

@@ -73,6 +73,7 @@ class Arena {
   ~Arena();
   void* get(size_t bytes);
   void put(void* p);
+  void trim();   // return every cached block to the device (after a stream sync)
   size_t in_use() const { return in_use_; }
 
  private:
@@ -100,7 +101,8 @@ struct Ctx {
   int64_t spmm_calls = 0;
   double spmm_bytes = 0.0;
   bool spmm_defer = false;          // bytes of sparse launches counted by the caller
-  int64_t spmm_pending[4] = {0, 0, 0, 0};   // deferred launches per mode
+  int64_t spmm_pending[5] = {0, 0, 0, 0, 0};   // deferred launches per mode
+  int spmm_split = 0;               // BiCGStab products: 0 auto, 1 fused, 2 split
   double t_spmm = 0.0;
   int64_t krylov_iters = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_events;

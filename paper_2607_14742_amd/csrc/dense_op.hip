@@ -1,0 +1,125 @@
+// Dense operator for the dense CARE instances: A^T stored as an n x n
+// column-major matrix in the inner precision.  Products y = (A^T + p I) x
+// are rocBLAS GEMMs (MFMA) plus a shift; shifted solves factor A^T + p I
+// once per real shift with a partially pivoted LU (rocSOLVER getrf, FP32 for
+// the FP32 inner precision) and reuse the factors for every right-hand side
+// block of every Newton step, since with the SMW form the base matrix does
+// not change (Sec. 4).
+#include <rocsolver/rocsolver.h>
+
+#include <cmath>
+
+#include "dense.hpp"
+#include "krylov.hpp"
+
+namespace mpcare {
+
+template <typename T>
+__global__ void k_add_diag(int64_t n, T* a, int64_t lda, T p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i * lda + i] += p;
+}
+
+void build_dense(Ctx* ctx, const double* A, int64_t lda, int64_t n, Prec prec, SellOp& op) {
+  if (!A || n < 1 || lda < n) fail(CARE_ERR_ARG, "invalid dense A");
+  if (n > 46340) fail(CARE_ERR_ARG, "dense A larger than 46340 x 46340");
+  if (prec == Prec::BF16) fail(CARE_ERR_NOT_IMPLEMENTED, "the bf16 variant applies to sparse operators only");
+  op = SellOp();
+  op.n = n;
+  op.nnz = n * n;
+  op.prec = prec;
+  op.dense = true;
+  DBuf<double> t(ctx, (size_t)n * n);
+  const double one = 1.0, zero = 0.0;
+  // A^T, leading dimension n
+  ROCBLAS_CHECK(rocblas_dgeam(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, (int)n, (int)n, &one, A,
+                              (int)lda, &zero, A, (int)lda, t.get(), (int)n));
+  double nrm = 0.0;
+  ROCBLAS_CHECK(rocblas_dnrm2(ctx->blas, (int)(n * n), t.get(), 1, &nrm));
+  op.frob = nrm;
+  if (!std::isfinite(nrm)) fail(CARE_ERR_NONFINITE, "A has non-finite entries");
+  if (prec == Prec::F64) {
+    op.dmat.resize(ctx, (size_t)n * n * sizeof(double));
+    d2d(ctx, op.dmat.get(), t.get(), (size_t)n * n * sizeof(double));
+  } else {
+    op.dmat.resize(ctx, (size_t)n * n * sizeof(float));
+    copy_cols<double, float>(ctx, n, (int)n, t.get(), n, (float*)op.dmat.get(), n);
+  }
+  ctx->sync();
+}
+
+void dense_apply(Ctx* ctx, const SellOp& op, double pr, double pi, const void* X, int64_t ldx, int k, void* Y,
+                 int64_t ldy) {
+  if (pi != 0.0) fail(CARE_ERR_NOT_IMPLEMENTED, "complex shifts with a dense operator");
+  if (k <= 0) return;
+  const int n = (int)op.n;
+  if (op.prec == Prec::F64) {
+    const double one = 1.0, zero = 0.0;
+    ROCBLAS_CHECK(rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, n, k, n, &one,
+                                (const double*)op.dmat.get(), n, (const double*)X, (int)ldx, &zero, (double*)Y,
+                                (int)ldy));
+    if (pr != 0.0) axpby<double>(ctx, n, k, pr, (const double*)X, ldx, 1.0, (double*)Y, ldy);
+  } else {
+    const float one = 1.0f, zero = 0.0f;
+    ROCBLAS_CHECK(rocblas_sgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, n, k, n, &one,
+                                (const float*)op.dmat.get(), n, (const float*)X, (int)ldx, &zero, (float*)Y,
+                                (int)ldy));
+    if (pr != 0.0) axpby<float>(ctx, n, k, pr, (const float*)X, ldx, 1.0, (float*)Y, ldy);
+  }
+}
+
+static rocblas_status getrf(rocblas_handle h, int n, double* a, int* ipiv, int* info) {
+  return rocsolver_dgetrf(h, n, n, a, n, ipiv, info);
+}
+static rocblas_status getrf(rocblas_handle h, int n, float* a, int* ipiv, int* info) {
+  return rocsolver_sgetrf(h, n, n, a, n, ipiv, info);
+}
+static rocblas_status getrs(rocblas_handle h, int n, int k, double* a, const int* ipiv, double* x, int ldx) {
+  return rocsolver_dgetrs(h, rocblas_operation_none, n, k, a, n, ipiv, x, ldx);
+}
+static rocblas_status getrs(rocblas_handle h, int n, int k, float* a, const int* ipiv, float* x, int ldx) {
+  return rocsolver_sgetrs(h, rocblas_operation_none, n, k, a, n, ipiv, x, ldx);
+}
+
+template <typename T>
+KrylovResult dense_solve(Ctx* ctx, const SellOp& op, double pr, double pi, int ncols, const T* b, int64_t ldb, T* x,
+                         int64_t ldx) {
+  KrylovResult res;
+  if (ncols <= 0) return res;
+  if (pi != 0.0) fail(CARE_ERR_NOT_IMPLEMENTED, "complex shifts with a dense operator");
+  if ((op.prec == Prec::F64) != (sizeof(T) == 8)) fail(CARE_ERR_ARG, "dense solve precision mismatch");
+  const int n = (int)op.n;
+  std::shared_ptr<SellOp::DenseLU> f;
+  auto it = op.lu.find(pr);
+  if (it != op.lu.end()) {
+    f = it->second;
+  } else {
+    f = std::make_shared<SellOp::DenseLU>();
+    f->a.resize(ctx, (size_t)n * n * sizeof(T));
+    f->ipiv.resize(ctx, n);
+    d2d(ctx, f->a.get(), op.dmat.get(), (size_t)n * n * sizeof(T));
+    // the shift is added in the operator precision (I is kept in A's type)
+    hipLaunchKernelGGL(k_add_diag<T>, dim3(ceil_div(n, 256)), dim3(256), 0, ctx->stream, (int64_t)n,
+                       (T*)f->a.get(), (int64_t)n, (T)pr);
+    KERNEL_CHECK();
+    DBuf<int> info(ctx, 1);
+    ROCBLAS_CHECK(getrf(ctx->blas, n, (T*)f->a.get(), f->ipiv.get(), info.get()));
+    int hinfo = 0;
+    d2h(ctx, &hinfo, info.get(), sizeof(int));
+    if (hinfo > 0) fail(CARE_ERR_BREAKDOWN, "A^T + p I is singular in the inner precision");
+    op.lu[pr] = f;
+  }
+  copy_cols<T, T>(ctx, n, ncols, b, ldb, x, ldx);
+  ROCBLAS_CHECK(getrs(ctx->blas, n, ncols, (T*)f->a.get(), f->ipiv.get(), x, (int)ldx));
+  res.col_ok.assign(ncols, 1);
+  res.col_relres.assign(ncols, 0.0);
+  res.col_bnorm.assign(ncols, 0.0);
+  return res;
+}
+
+template KrylovResult dense_solve<double>(Ctx*, const SellOp&, double, double, int, const double*, int64_t, double*,
+                                          int64_t);
+template KrylovResult dense_solve<float>(Ctx*, const SellOp&, double, double, int, const float*, int64_t, float*,
+                                         int64_t);
+
+}  // namespace mpcare

@@ -346,6 +346,93 @@ static void ckpt(Ctx* ctx, bool cplx, int n, int ncols, T* x, int64_t ldx, T* xb
   KERNEL_CHECK();
 }
 
+// First half of a split MODE_BICG_P / MODE_BICG_S (see spmm_kernel.hpp): the
+// input of the sparse product formed once per row, with the fused modes'
+// formulas: p_new = r + beta (p - omega v) (r on a column's first iteration),
+// or s = r - alpha v.
+template <typename T, int CP, int WHICH, bool CPLX>
+__global__ void __launch_bounds__(256) k_bicg_pre(SpmmArgs<T> a) {
+  constexpr int NL = CPLX ? CP / 2 : CP;
+  const int rb = (int)xcd_remap(blockIdx.x, gridDim.x);
+  const int i = rb * 256 + threadIdx.x;
+  const int c0 = blockIdx.y * CP;
+  if (i >= a.n) return;
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int cr = c0 + (CPLX ? 2 * q : q);
+    if (cr >= a.ncols) continue;
+    const int lc = CPLX ? cr / 2 : cr;
+    const int* st = a.st + (int64_t)lc * KI;
+    if (st[KI_ACTIVE] == 0) continue;
+    const double* sc = a.sc + (int64_t)lc * KS;
+    const int64_t o = (int64_t)cr * a.ld + i;
+    if (WHICH == MODE_BICG_P) {
+      const bool first = st[KI_ITERS] == 0;
+      const T br = (T)sc[KS_BETA], bi = (T)sc[KS_BETA + 1];
+      const T wr = (T)sc[KS_OMEGA], wi = (T)sc[KS_OMEGA + 1];
+      if (!CPLX) {
+        const T rv = a.r[o];
+        a.pnew[o] = first ? rv : rv + br * (a.pold[o] - wr * a.vold[o]);
+      } else {
+        const T rr = a.r[o], ri = a.r[o + a.ld];
+        if (first) {
+          a.pnew[o] = rr;
+          a.pnew[o + a.ld] = ri;
+        } else {
+          const T pr = a.pold[o], pi = a.pold[o + a.ld];
+          const T vr = a.vold[o], vi = a.vold[o + a.ld];
+          const T ur = pr - (wr * vr - wi * vi);
+          const T ui = pi - (wr * vi + wi * vr);
+          a.pnew[o] = rr + (br * ur - bi * ui);
+          a.pnew[o + a.ld] = ri + (br * ui + bi * ur);
+        }
+      }
+    } else {
+      const T ar = (T)sc[KS_ALPHA], ai = (T)sc[KS_ALPHA + 1];
+      if (!CPLX) {
+        a.s[o] = a.r[o] - ar * a.vold[o];
+      } else {
+        const T vr = a.vold[o], vi = a.vold[o + a.ld];
+        a.s[o] = a.r[o] - (ar * vr - ai * vi);
+        a.s[o + a.ld] = a.r[o + a.ld] - (ar * vi + ai * vr);
+      }
+    }
+  }
+}
+
+template <typename T, int WHICH>
+static void launch_pre(Ctx* ctx, const SellOp& op, bool cplx, SpmmArgs<T> a) {
+  a.n = (int)op.n;
+  const int k = a.ncols;
+  if (k <= 0 || a.n <= 0) return;
+  const int cp = k <= 2 ? 2 : (k <= 4 ? 4 : 8);
+  dim3 g(spmm_rowblocks(a.n), ceil_div(k, cp));
+  if (cplx) {
+    if (cp == 2) hipLaunchKernelGGL((k_bicg_pre<T, 2, WHICH, true>), g, dim3(256), 0, ctx->stream, a);
+    else if (cp == 4) hipLaunchKernelGGL((k_bicg_pre<T, 4, WHICH, true>), g, dim3(256), 0, ctx->stream, a);
+    else hipLaunchKernelGGL((k_bicg_pre<T, 8, WHICH, true>), g, dim3(256), 0, ctx->stream, a);
+  } else {
+    if (cp == 2) hipLaunchKernelGGL((k_bicg_pre<T, 2, WHICH, false>), g, dim3(256), 0, ctx->stream, a);
+    else if (cp == 4) hipLaunchKernelGGL((k_bicg_pre<T, 4, WHICH, false>), g, dim3(256), 0, ctx->stream, a);
+    else hipLaunchKernelGGL((k_bicg_pre<T, 8, WHICH, false>), g, dim3(256), 0, ctx->stream, a);
+  }
+  KERNEL_CHECK();
+}
+
+// Split or fused BiCGStab products: split when the fused kernel's gathered
+// vectors (3 for the p step) for the rows of one panel that a single XCD holds
+// would fill more than half of that XCD's 4 MB L2.
+static bool use_split(const Ctx* ctx, const SellOp& op, int ncols, bool cplx) {
+  if (ctx->spmm_split == 1) return false;
+  if (ctx->spmm_split == 2) return true;
+  const int k = ncols;
+  int cp = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
+  if (cplx && cp < 2) cp = 2;
+  const double rows_per_xcd = double(op.n) / 8.0;
+  const double ws = rows_per_xcd * cp * 3.0 * double(vec_bytes(op.prec));
+  return ws > 2.0 * 1024 * 1024;
+}
+
 template <typename T, int CP, int UMODE, bool CPLX>
 static void launch_elem(Ctx* ctx, const ElemArgs<T>& a) {
   dim3 g(spmm_rowblocks(a.n), ceil_div(a.ncols, CP));
@@ -465,6 +552,7 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
   check_every = check_every > 0 ? check_every : 8;
   int next_check = 1;   // first poll right after one iteration (trivial columns)
   bool done = false;
+  const bool split = use_split(ctx, op, ncols, cplx);
   auto iteration = [&](int it) {
     SpmmArgs<T> a1;
     a1.ncols = ncols;
@@ -481,7 +569,17 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
     a1.sc = sc.get();
     a1.st = st.get();
     a1.part = part.get();
-    launch_spmm<T>(ctx, op, MODE_BICG_P, cplx, a1);
+    if (split) {
+      launch_pre<T, MODE_BICG_P>(ctx, op, cplx, a1);
+      SpmmArgs<T> d1 = a1;
+      d1.X = a1.pnew;
+      d1.ldx = ld;
+      d1.Y = a1.vnew;
+      d1.ldy = ld;
+      launch_spmm<T>(ctx, op, MODE_DOT1, cplx, d1);
+    } else {
+      launch_spmm<T>(ctx, op, MODE_BICG_P, cplx, a1);
+    }
     scalar<1>(ctx, cplx, sc.get(), st.get(), part.get(), ncols, nrb, tol2);
     if (trace && it < 3) dump("S1");
 
@@ -489,7 +587,17 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
     a2.vold = Vb[(it + 1) & 1];
     a2.s = S.get();
     a2.t = Tt.get();
-    launch_spmm<T>(ctx, op, MODE_BICG_S, cplx, a2);
+    if (split) {
+      launch_pre<T, MODE_BICG_S>(ctx, op, cplx, a2);
+      SpmmArgs<T> d2 = a2;
+      d2.X = a2.s;
+      d2.ldx = ld;
+      d2.Y = a2.t;
+      d2.ldy = ld;
+      launch_spmm<T>(ctx, op, MODE_DOT2, cplx, d2);
+    } else {
+      launch_spmm<T>(ctx, op, MODE_BICG_S, cplx, a2);
+    }
     scalar<2>(ctx, cplx, sc.get(), st.get(), part.get(), ncols, nrb, tol2);
     if (trace && it < 3) dump("S2");
 
@@ -508,9 +616,11 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
   auto account = [&](int active) {
     if (!ctx->spmm_defer) return;
     const int kr = active * (cplx ? 2 : 1);
-    ctx->spmm_bytes += double(ctx->spmm_pending[MODE_BICG_P]) * op.bytes(kr, spmm_vec_passes(MODE_BICG_P, first_chunk)) +
-                       double(ctx->spmm_pending[MODE_BICG_S]) * op.bytes(kr, spmm_vec_passes(MODE_BICG_S));
-    ctx->spmm_pending[MODE_BICG_P] = ctx->spmm_pending[MODE_BICG_S] = 0;
+    for (int md = MODE_BICG_P; md <= MODE_DOT2; ++md) {
+      const int passes = md == MODE_BICG_P ? spmm_vec_passes(md, first_chunk) : spmm_vec_passes(md);
+      ctx->spmm_bytes += double(ctx->spmm_pending[md]) * op.bytes(kr, passes);
+      ctx->spmm_pending[md] = 0;
+    }
     first_chunk = false;
   };
   auto poll = [&]() {
@@ -528,7 +638,7 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
   const int CHUNK = 8;
   const bool use_graph = !ctx->profile && !trace && maxit > 2 * CHUNK;
   ctx->spmm_defer = ctx->profile != 0;
-  ctx->spmm_pending[MODE_BICG_P] = ctx->spmm_pending[MODE_BICG_S] = 0;
+  for (int md = 0; md < 5; ++md) ctx->spmm_pending[md] = 0;
   while (it < maxit && !done && (!use_graph || it < check_every)) {
     iteration(it);
     ++it;
@@ -605,6 +715,7 @@ constexpr int MAX_RESTARTS = 2;
 template <typename T>
 KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncols, const T* b, int64_t ldb, T* x,
                       int64_t ldx, double tol, int maxit, int check_every, const std::vector<int>* groups) {
+  if (op.dense) return dense_solve<T>(ctx, op, pr, pi, ncols, b, ldb, x, ldx);
   KrylovResult res = bicgstab_core<T>(ctx, op, pr, pi, ncols, b, ldb, x, ldx, tol, maxit, check_every, groups,
                                       nullptr);
   const bool cplx = pi != 0.0;

@@ -35,4 +35,10 @@ KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncol
                       int64_t ldb, T* x, int64_t ldx, double tol, int maxit, int check_every,
                       const std::vector<int>* groups = nullptr);
 
+// Direct shifted solve for a dense operator (dense_op.hip): LU of A^T + p I
+// in the operator precision, cached per real shift on the operator.
+template <typename T>
+KrylovResult dense_solve(Ctx* ctx, const SellOp& op, double pr, double pi, int ncols, const T* b, int64_t ldb, T* x,
+                         int64_t ldx);
+
 }  // namespace mpcare

@@ -57,6 +57,12 @@ void* Arena::get(size_t bytes) {
   return p;
 }
 
+void Arena::trim() {
+  (void)hipStreamSynchronize(stream_);
+  for (auto& kv : free_) (void)hipFree(kv.second);
+  free_.clear();
+}
+
 void Arena::put(void* p) {
   auto it = live_.find(p);
   if (it == live_.end()) return;

@@ -241,13 +241,17 @@ static void launch_cp(hipStream_t st, dim3 g, int mode, bool cplx, const SpmmArg
     if (cplx) {
       if (mode == MODE_PLAIN) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_PLAIN, true>), g, dim3(256), 0, st, a);
       else if (mode == MODE_BICG_P) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_P, true>), g, dim3(256), 0, st, a);
-      else hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_S, true>), g, dim3(256), 0, st, a);
+      else if (mode == MODE_BICG_S) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_S, true>), g, dim3(256), 0, st, a);
+      else if (mode == MODE_DOT1) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_DOT1, true>), g, dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_DOT2, true>), g, dim3(256), 0, st, a);
       return;
     }
   }
   if (mode == MODE_PLAIN) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_PLAIN, false>), g, dim3(256), 0, st, a);
   else if (mode == MODE_BICG_P) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_P, false>), g, dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_S, false>), g, dim3(256), 0, st, a);
+  else if (mode == MODE_BICG_S) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_S, false>), g, dim3(256), 0, st, a);
+  else if (mode == MODE_DOT1) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_DOT1, false>), g, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_DOT2, false>), g, dim3(256), 0, st, a);
 }
 
 template <typename TV, typename T>
@@ -293,7 +297,7 @@ template int launch_spmm<float>(Ctx*, const SellOp&, int, bool, SpmmArgs<float>&
 
 SpmmTimer::SpmmTimer(Ctx* c, const SellOp& op, int k_real, int mode) : ctx(c) {
   ctx->spmm_calls += 1;
-  if (ctx->spmm_defer) ctx->spmm_pending[mode & 3] += 1;
+  if (ctx->spmm_defer && mode >= 0 && mode < 5) ctx->spmm_pending[mode] += 1;
   else ctx->spmm_bytes += op.bytes(k_real, spmm_vec_passes(mode));
   if (ctx->profile) {
     ev = ctx->event_pair();
@@ -310,6 +314,10 @@ SpmmTimer::~SpmmTimer() {
 
 void spmm_plain(Ctx* ctx, const SellOp& op, double pr, double pi, const void* X, int64_t ldx, int k_real,
                 void* Y, int64_t ldy) {
+  if (op.dense) {
+    dense_apply(ctx, op, pr, pi, X, ldx, k_real, Y, ldy);
+    return;
+  }
   const bool cplx = pi != 0.0;
   if (op.prec == Prec::F64) {
     SpmmArgs<double> a;

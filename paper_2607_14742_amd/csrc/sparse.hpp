@@ -15,6 +15,9 @@
 // leading dimension rounded up to 64 rows.
 #pragma once
 
+#include <map>
+#include <memory>
+
 #include "common.hpp"
 #include "spmm_kernel.hpp"
 
@@ -30,6 +33,16 @@ struct SellOp {
   DBuf<uint8_t> vals;              // width_total * 64 * val_bytes
   DBuf<uint8_t> diag;              // n * vec_bytes
   double frob = 0.0;               // ||A||_F (FP64)
+  // Dense operator (dense_op.hip): A^T held as an n x n column-major matrix
+  // (leading dimension n) in the operator precision; shifted solves use LU
+  // factorisations of A^T + p I cached per real shift.
+  bool dense = false;
+  DBuf<uint8_t> dmat;
+  struct DenseLU {
+    DBuf<uint8_t> a;               // LU factors, n x n
+    DBuf<int> ipiv;
+  };
+  mutable std::map<double, std::shared_ptr<DenseLU>> lu;
   // algorithmic bytes of one product with k real columns: the CSR formula
   // nnz (s_v + 4) + 4 (n + 1) plus `passes` n-vectors per column (2 for
   // y = M x; the fused BiCGStab modes move more, see spmm_vec_passes)
@@ -48,6 +61,13 @@ void build_sell(Ctx* ctx, const care_csr* A, Prec prec, SellOp& op);
 void spmm_plain(Ctx* ctx, const SellOp& op, double pr, double pi, const void* X, int64_t ldx,
                 int k_real, void* Y, int64_t ldy);
 
+// Dense operators (dense_op.hip): build A^T from a dense column-major A
+// (device, leading dimension lda) in precision prec (FP64 or FP32), and
+// Y = (A^T + p I) X by GEMM (real p only).
+void build_dense(Ctx* ctx, const double* A, int64_t lda, int64_t n, Prec prec, SellOp& op);
+void dense_apply(Ctx* ctx, const SellOp& op, double pr, double pi, const void* X, int64_t ldx, int k, void* Y,
+                 int64_t ldy);
+
 // Launch one sparse product in `mode` (see spmm_kernel.hpp) with the panel
 // width picked from the column count; fills grid-dependent fields of `a`
 // (n, sptr, cols, vals, diag, nrb).  Returns the number of row blocks.
@@ -61,8 +81,15 @@ inline int spmm_rowblocks(int64_t n) { return (int)((n + 255) / 256); }
 // n-vector passes per real column of one launch in each mode: y = M x reads
 // x and writes y; MODE_BICG_P reads r, p, v, rhat and writes p, v (4 on a
 // column's first iteration, where p and v are not read); MODE_BICG_S reads
-// r, v and writes s, t.
-inline int spmm_vec_passes(int mode, bool first = false) { return mode == 0 ? 2 : (mode == 1 ? (first ? 4 : 6) : 4); }
+// r, v and writes s, t; the split second halves read x (and rhat) and write y.
+inline int spmm_vec_passes(int mode, bool first = false) {
+  switch (mode) {
+    case 1: return first ? 4 : 6;   // MODE_BICG_P
+    case 2: return 4;               // MODE_BICG_S
+    case 3: return 3;               // MODE_DOT1: x, rhat read; y written
+    default: return 2;              // MODE_PLAIN, MODE_DOT2: x read; y written
+  }
+}
 
 // Counts a launch and, when the context profiles, brackets it with HIP events
 // on the library stream.  While ctx->spmm_defer is set the launch's bytes are

@@ -14,6 +14,14 @@
 //                iteration); writes p_new = x~, v = M x~, partial <rhat, v>
 //   MODE_BICG_S  x~ = s = r - alpha v formed on the fly; writes s, t = M s,
 //                partials <t, s>, <t, t>
+//   MODE_DOT1    the second half of a split MODE_BICG_P: x~ = X already
+//                formed (k_bicg_pre), writes Y = M x~, partial <rhat, Y>
+//   MODE_DOT2    the second half of a split MODE_BICG_S: writes Y = M X,
+//                partials <Y, X>, <Y, Y>
+// The fused modes gather r, p, v (or r, v) at every neighbour row and form
+// x~ there again; when a panel's rows in flight on one XCD outgrow its L2,
+// those gathers miss repeatedly, and the split form (x~ written once by an
+// elementwise pass, then one gathered vector) moves fewer bytes.
 // With CPLX the panel holds CP/2 complex columns as interleaved (re, im)
 // column pairs; the shift is complex and dots are <u, v> = sum conj(u) v.
 #pragma once
@@ -22,7 +30,7 @@
 
 namespace mpcare {
 
-enum SpmmMode { MODE_PLAIN = 0, MODE_BICG_P = 1, MODE_BICG_S = 2 };
+enum SpmmMode { MODE_PLAIN = 0, MODE_BICG_P = 1, MODE_BICG_S = 2, MODE_DOT1 = 3, MODE_DOT2 = 4 };
 
 // per-logical-column BiCGStab scalars, KS doubles per column
 // (RMIN: smallest ||r||^2 met; RCKPT: ||r||^2 of the checkpointed iterate)
@@ -106,7 +114,8 @@ __device__ __forceinline__ void block_reduce_to(const T (&v)[NV], Dst dst) {
 
 template <typename TV, typename T, int CP, int MODE, bool CPLX>
 __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
-  constexpr int NDOT = MODE == MODE_PLAIN ? 0 : (MODE == MODE_BICG_P ? 1 : 2);
+  constexpr int NDOT = MODE == MODE_PLAIN ? 0 : ((MODE == MODE_BICG_P || MODE == MODE_DOT1) ? 1 : 2);
+  constexpr bool XIN = MODE == MODE_PLAIN || MODE == MODE_DOT1 || MODE == MODE_DOT2;   // input read from X
   constexpr int NL = CPLX ? CP / 2 : CP;          // logical columns in the panel
   static_assert(!CPLX || (CP % 2 == 0), "complex panels hold column pairs");
 
@@ -147,7 +156,7 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
   auto input = [&](int q, int64_t j, T& xr, T& xi) {
     const int cr = c0 + (CPLX ? 2 * q : q);
     const int64_t o = (int64_t)cr * ld + j;
-    if (MODE == MODE_PLAIN) {
+    if (XIN) {
       xr = a.X[(int64_t)cr * a.ldx + j];
       xi = CPLX ? a.X[(int64_t)(cr + 1) * a.ldx + j] : (T)0;
     } else if (MODE == MODE_BICG_P) {
@@ -226,6 +235,29 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
       if (MODE == MODE_PLAIN) {
         a.Y[(int64_t)cr * a.ldy + i] = yr;
         if (CPLX) a.Y[(int64_t)(cr + 1) * a.ldy + i] = yi;
+      } else if (MODE == MODE_DOT1) {
+        a.Y[(int64_t)cr * a.ldy + i] = yr;
+        const int64_t oh = (int64_t)cr * a.ldrhat + i;
+        if (!CPLX) {
+          dots[q] = a.rhat[oh] * yr;
+        } else {
+          a.Y[(int64_t)(cr + 1) * a.ldy + i] = yi;
+          const T hr = a.rhat[oh], hi = a.rhat[oh + a.ldrhat];
+          dots[2 * q] = hr * yr + hi * yi;          // conj(rhat) v
+          dots[2 * q + 1] = hr * yi - hi * yr;
+        }
+      } else if (MODE == MODE_DOT2) {
+        a.Y[(int64_t)cr * a.ldy + i] = yr;
+        if (!CPLX) {
+          dots[q] = yr * xr;                         // <t, s>
+          dots[CP + q] = yr * yr;                    // <t, t>
+        } else {
+          a.Y[(int64_t)(cr + 1) * a.ldy + i] = yi;
+          dots[2 * q] = yr * xr + yi * xi;           // conj(t) s
+          dots[2 * q + 1] = yr * xi - yi * xr;
+          dots[CP + 2 * q] = yr * yr + yi * yi;      // |t|^2
+          dots[CP + 2 * q + 1] = (T)0;
+        }
       } else if (MODE == MODE_BICG_P) {
         a.pnew[o] = xr;
         a.vnew[o] = yr;

@@ -159,7 +159,8 @@ def test_shifted_solve_parity(ctx, pk, prec, tol, p, smw):
     "real",
     "complex",
 ])
-def test_lradi_iterate_parity(ctx, pk, prec, ztol, shifts):
+@pytest.mark.parametrize("split", [1, 2])    # fused BiCGStab products, or update pass + product
+def test_lradi_iterate_parity(ctx, pk, prec, ztol, shifts, split):
     N = 20
     A = wl.fdm2d(N) if shifts == "real" else wl.fdm3d(7, 100.0)
     n = A.shape[0]
@@ -174,7 +175,7 @@ def test_lradi_iterate_parity(ctx, pk, prec, ztol, shifts):
         s = np.array([-60 + 40j, -60 - 40j, -400.0, -1500 + 300j, -1500 - 300j, -6000.0])
     jmax = 8
     Ad = pk.DeviceCSR.from_scipy(A)
-    opts = pk.default_opts(prec, j_max=jmax, krylov_tol=1e-12 if prec == "fp64" else 1e-6)
+    opts = pk.default_opts(prec, j_max=jmax, krylov_tol=1e-12 if prec == "fp64" else 1e-6, spmm_split=split)
     Z, stats, st = pk.lyap_lradi(ctx, Ad, dev(W0), s, B=dev(B), K=dev(K), tol=1e-30, opts=opts)
     Z = host(Z)
     Zr, Wr, info = adi.lradi(A, B, K, W0, s, tol=1e-30, jmax=jmax)
@@ -294,10 +295,12 @@ def test_care_solve_config1_vs_schur(ctx, pk, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_care_solve_fdm_vs_oracle(ctx, pk, prec):
+@pytest.mark.parametrize("split", [0, 2])    # automatic choice (fused at this size), forced split
+def test_care_solve_fdm_vs_oracle(ctx, pk, prec, split):
     P = wl.fdm2d_problem(40, 3, 4)
     Ad = pk.DeviceCSR.from_scipy(P.A)
-    Z, stats, st = pk.care_solve(ctx, Ad, dev(P.B), dev(P.C), tol=1e-12, shifts=P.shifts, prec=prec)
+    Z, stats, st = pk.care_solve(ctx, Ad, dev(P.B), dev(P.C), tol=1e-12, shifts=P.shifts, prec=prec,
+                                 spmm_split=split)
     assert st == 0, stats
     Z = host(Z)
     Zr, info = ocare.framework1(P.A, P.B, P.C, P.shifts, tol=1e-13)
