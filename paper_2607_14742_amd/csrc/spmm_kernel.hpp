@@ -152,31 +152,48 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
     }
   }
 
+  // Every load below is issued without a per-column branch: a column that is
+  // inactive (converged, or past ncols in the last panel) reads the rows of
+  // the panel's first active column instead, i.e. cache lines that are being
+  // fetched anyway, and its results are dropped.  A branch per column would
+  // make the compiler wait for each gather before issuing the next one.
+  int colq[NL];
+  int qa = -1;
+#pragma unroll
+  for (int q = 0; q < NL; ++q)
+    if (qa < 0 && act[q]) qa = q;
+  const int cra = c0 + (CPLX ? 2 * (qa < 0 ? 0 : qa) : (qa < 0 ? 0 : qa));
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int cr = c0 + (CPLX ? 2 * q : q);
+    colq[q] = act[q] ? cr : cra;
+  }
+
   // input value of logical column q at row j: (re, im)
   auto input = [&](int q, int64_t j, T& xr, T& xi) {
-    const int cr = c0 + (CPLX ? 2 * q : q);
+    const int cr = colq[q];
     const int64_t o = (int64_t)cr * ld + j;
     if (XIN) {
       xr = a.X[(int64_t)cr * a.ldx + j];
       xi = CPLX ? a.X[(int64_t)(cr + 1) * a.ldx + j] : (T)0;
     } else if (MODE == MODE_BICG_P) {
+      // p and v are read on every iteration and the result selected, so that
+      // the first iteration needs no branch (their contents are then unused)
       if (!CPLX) {
         const T rv = a.r[o];
-        xr = first[q] ? rv : rv + sA_r[q] * (a.pold[o] - sB_r[q] * a.vold[o]);
+        const T upd = rv + sA_r[q] * (a.pold[o] - sB_r[q] * a.vold[o]);
+        xr = first[q] ? rv : upd;
         xi = (T)0;
       } else {
         const T rr = a.r[o], ri = a.r[o + ld];
-        if (first[q]) {
-          xr = rr;
-          xi = ri;
-        } else {
-          const T pr = a.pold[o], pi = a.pold[o + ld];
-          const T vr = a.vold[o], vi = a.vold[o + ld];
-          const T ur = pr - (sB_r[q] * vr - sB_i[q] * vi);
-          const T ui = pi - (sB_r[q] * vi + sB_i[q] * vr);
-          xr = rr + (sA_r[q] * ur - sA_i[q] * ui);
-          xi = ri + (sA_r[q] * ui + sA_i[q] * ur);
-        }
+        const T pr = a.pold[o], pi = a.pold[o + ld];
+        const T vr = a.vold[o], vi = a.vold[o + ld];
+        const T ur = pr - (sB_r[q] * vr - sB_i[q] * vi);
+        const T ui = pi - (sB_r[q] * vi + sB_i[q] * vr);
+        const T ar = rr + (sA_r[q] * ur - sA_i[q] * ui);
+        const T ai = ri + (sA_r[q] * ui + sA_i[q] * ur);
+        xr = first[q] ? rr : ar;
+        xi = first[q] ? ri : ai;
       }
     } else {  // MODE_BICG_S
       if (!CPLX) {
@@ -198,90 +215,100 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
 #pragma unroll
   for (int k = 0; k < (NDOT > 0 ? NDOT * CP : 1); ++k) dots[k] = (T)0;
 
-  if (i < a.n) {
+  if (i < a.n && qa >= 0) {
     const int s = i >> 6, lane = i & 63;
     const int beg = a.sptr[s], end = a.sptr[s + 1];
     const TV* vals = (const TV*)a.vals;
+    // software pipeline: the next entry's column index and value are loaded
+    // after this entry's gathers have been issued
+    int jn = i;
+    T avn = (T)0;
+    if (beg < end) {
+      const int64_t e = (int64_t)beg * 64 + lane;
+      jn = a.cols[e];
+      avn = load_val<T, TV>(vals, e);
+    }
     for (int t = beg; t < end; ++t) {
-      const int64_t e = (int64_t)t * 64 + lane;
-      const int j = a.cols[e];
-      const T av = load_val<T, TV>(vals, e);
+      const int j = jn;
+      const T av = avn;
+      T xr[NL], xi[NL];
+#pragma unroll
+      for (int q = 0; q < NL; ++q) input(q, j, xr[q], xi[q]);
+      if (t + 1 < end) {
+        const int64_t e = (int64_t)(t + 1) * 64 + lane;
+        jn = a.cols[e];
+        avn = load_val<T, TV>(vals, e);
+      }
 #pragma unroll
       for (int q = 0; q < NL; ++q) {
-        if (act[q]) {
-          T xr, xi;
-          input(q, j, xr, xi);
-          acc_r[q] += av * xr;
-          if (CPLX) acc_i[q] += av * xi;
-        }
+        acc_r[q] += av * xr[q];
+        if (CPLX) acc_i[q] += av * xi[q];
       }
     }
     const T d = a.diag[i] + (T)a.sr;
     const T sim = (T)a.si;
+    T xr[NL], xi[NL], hr[NL], hi[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      input(q, i, xr[q], xi[q]);
+      hr[q] = hi[q] = (T)0;
+      if (MODE == MODE_BICG_P || MODE == MODE_DOT1) {
+        const int64_t oh = (int64_t)colq[q] * a.ldrhat + i;
+        hr[q] = a.rhat[oh];
+        if (CPLX) hi[q] = a.rhat[oh + a.ldrhat];
+      }
+    }
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
       if (!act[q]) continue;
-      T xr, xi;
-      input(q, i, xr, xi);
       T yr, yi = (T)0;
       if (!CPLX) {
-        yr = acc_r[q] + d * xr;
+        yr = acc_r[q] + d * xr[q];
       } else {
-        yr = acc_r[q] + d * xr - sim * xi;
-        yi = acc_i[q] + d * xi + sim * xr;
+        yr = acc_r[q] + d * xr[q] - sim * xi[q];
+        yi = acc_i[q] + d * xi[q] + sim * xr[q];
       }
       const int cr = c0 + (CPLX ? 2 * q : q);
       const int64_t o = (int64_t)cr * ld + i;
       if (MODE == MODE_PLAIN) {
         a.Y[(int64_t)cr * a.ldy + i] = yr;
         if (CPLX) a.Y[(int64_t)(cr + 1) * a.ldy + i] = yi;
-      } else if (MODE == MODE_DOT1) {
-        a.Y[(int64_t)cr * a.ldy + i] = yr;
-        const int64_t oh = (int64_t)cr * a.ldrhat + i;
-        if (!CPLX) {
-          dots[q] = a.rhat[oh] * yr;
+      } else if (MODE == MODE_DOT1 || MODE == MODE_BICG_P) {
+        if (MODE == MODE_DOT1) {
+          a.Y[(int64_t)cr * a.ldy + i] = yr;
+          if (CPLX) a.Y[(int64_t)(cr + 1) * a.ldy + i] = yi;
         } else {
-          a.Y[(int64_t)(cr + 1) * a.ldy + i] = yi;
-          const T hr = a.rhat[oh], hi = a.rhat[oh + a.ldrhat];
-          dots[2 * q] = hr * yr + hi * yi;          // conj(rhat) v
-          dots[2 * q + 1] = hr * yi - hi * yr;
+          a.pnew[o] = xr[q];
+          a.vnew[o] = yr;
+          if (CPLX) {
+            a.pnew[o + ld] = xi[q];
+            a.vnew[o + ld] = yi;
+          }
         }
-      } else if (MODE == MODE_DOT2) {
-        a.Y[(int64_t)cr * a.ldy + i] = yr;
         if (!CPLX) {
-          dots[q] = yr * xr;                         // <t, s>
+          dots[q] = hr[q] * yr;                      // <rhat, v>
+        } else {
+          dots[2 * q] = hr[q] * yr + hi[q] * yi;     // conj(rhat) v
+          dots[2 * q + 1] = hr[q] * yi - hi[q] * yr;
+        }
+      } else {   // MODE_DOT2, MODE_BICG_S
+        if (MODE == MODE_DOT2) {
+          a.Y[(int64_t)cr * a.ldy + i] = yr;
+          if (CPLX) a.Y[(int64_t)(cr + 1) * a.ldy + i] = yi;
+        } else {
+          a.s[o] = xr[q];
+          a.t[o] = yr;
+          if (CPLX) {
+            a.s[o + ld] = xi[q];
+            a.t[o + ld] = yi;
+          }
+        }
+        if (!CPLX) {
+          dots[q] = yr * xr[q];                      // <t, s>
           dots[CP + q] = yr * yr;                    // <t, t>
         } else {
-          a.Y[(int64_t)(cr + 1) * a.ldy + i] = yi;
-          dots[2 * q] = yr * xr + yi * xi;           // conj(t) s
-          dots[2 * q + 1] = yr * xi - yi * xr;
-          dots[CP + 2 * q] = yr * yr + yi * yi;      // |t|^2
-          dots[CP + 2 * q + 1] = (T)0;
-        }
-      } else if (MODE == MODE_BICG_P) {
-        a.pnew[o] = xr;
-        a.vnew[o] = yr;
-        const int64_t oh = (int64_t)cr * a.ldrhat + i;
-        if (!CPLX) {
-          dots[q] = a.rhat[oh] * yr;
-        } else {
-          a.pnew[o + ld] = xi;
-          a.vnew[o + ld] = yi;
-          const T hr = a.rhat[oh], hi = a.rhat[oh + a.ldrhat];
-          dots[2 * q] = hr * yr + hi * yi;          // conj(rhat) v
-          dots[2 * q + 1] = hr * yi - hi * yr;
-        }
-      } else {
-        a.s[o] = xr;
-        a.t[o] = yr;
-        if (!CPLX) {
-          dots[q] = yr * xr;                         // <t, s>
-          dots[CP + q] = yr * yr;                    // <t, t>
-        } else {
-          a.s[o + ld] = xi;
-          a.t[o + ld] = yi;
-          dots[2 * q] = yr * xr + yi * xi;           // conj(t) s
-          dots[2 * q + 1] = yr * xi - yi * xr;
+          dots[2 * q] = yr * xr[q] + yi * xi[q];     // conj(t) s
+          dots[2 * q + 1] = yr * xi[q] - yi * xr[q];
           dots[CP + 2 * q] = yr * yr + yi * yi;      // |t|^2
           dots[CP + 2 * q + 1] = (T)0;
         }
