@@ -59,13 +59,12 @@ __global__ void __launch_bounds__(256) k_bicg_elem(ElemArgs<T> a) {
 #pragma unroll
   for (int k = 0; k < NDOT * CP; ++k) dots[k] = (T)0;
 
+  if (UMODE == UPD_INIT) {
 #pragma unroll
-  for (int q = 0; q < NL; ++q) {
-    const int cr = c0 + (CPLX ? 2 * q : q);
-    if (cr >= a.ncols || i >= a.n) continue;
-    const int lc = CPLX ? cr / 2 : cr;
-    const int64_t ob = (int64_t)cr * a.ldb + i, ox = (int64_t)cr * a.ldx + i, o = (int64_t)cr * a.ld + i;
-    if (UMODE == UPD_INIT) {
+    for (int q = 0; q < NL; ++q) {
+      const int cr = c0 + (CPLX ? 2 * q : q);
+      if (cr >= a.ncols || i >= a.n) continue;
+      const int64_t ob = (int64_t)cr * a.ldb + i, ox = (int64_t)cr * a.ldx + i, o = (int64_t)cr * a.ld + i;
       const T br = a.b[ob];
       a.r[o] = br;
       a.x[ox] = (T)0;
@@ -78,34 +77,69 @@ __global__ void __launch_bounds__(256) k_bicg_elem(ElemArgs<T> a) {
         dots[2 * q] = br * br + bi * bi;
         dots[2 * q + 1] = (T)0;
       }
-    } else {
-      if (a.st[(int64_t)lc * KI + KI_ACTIVE] == 0) continue;
-      const double* sc = a.sc + (int64_t)lc * KS;
-      if (!CPLX) {
-        const T al = (T)sc[KS_ALPHA], om = (T)sc[KS_OMEGA];
-        const T sv = a.s[o], tv = a.t[o];
-        a.x[ox] += al * a.p[o] + om * sv;
-        const T rv = sv - om * tv;
-        a.r[o] = rv;
-        dots[q] = a.b[ob] * rv;             // <rhat, r>
-        dots[CP + q] = rv * rv;             // <r, r>
-      } else {
-        const T alr = (T)sc[KS_ALPHA], ali = (T)sc[KS_ALPHA + 1];
-        const T omr = (T)sc[KS_OMEGA], omi = (T)sc[KS_OMEGA + 1];
-        const T pr = a.p[o], pim = a.p[o + a.ld];
-        const T sr = a.s[o], sim = a.s[o + a.ld];
-        const T tr = a.t[o], tim = a.t[o + a.ld];
-        a.x[ox] += (alr * pr - ali * pim) + (omr * sr - omi * sim);
-        a.x[ox + a.ldx] += (alr * pim + ali * pr) + (omr * sim + omi * sr);
-        const T rr = sr - (omr * tr - omi * tim);
-        const T ri = sim - (omr * tim + omi * tr);
-        a.r[o] = rr;
-        a.r[o + a.ld] = ri;
-        const T hr = a.b[ob], hi = a.b[ob + a.ldb];
-        dots[2 * q] = hr * rr + hi * ri;          // conj(rhat) r
-        dots[2 * q + 1] = hr * ri - hi * rr;
-        dots[CP + 2 * q] = rr * rr + ri * ri;     // |r|^2
-        dots[CP + 2 * q + 1] = (T)0;
+    }
+  } else {
+    // all loads first, without a branch per column (inactive columns read the
+    // panel's first active column), then the stores of the active columns
+    bool act[NL];
+    int colq[NL];
+    int qa = -1;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int cr = c0 + (CPLX ? 2 * q : q);
+      act[q] = cr < a.ncols && a.st[(int64_t)(CPLX ? cr / 2 : cr) * KI + KI_ACTIVE] != 0;
+      if (qa < 0 && act[q]) qa = q;
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) colq[q] = act[q] ? c0 + (CPLX ? 2 * q : q) : c0 + (CPLX ? 2 * qa : qa);
+    if (qa >= 0 && i < a.n) {
+      T pr[NL], pim[NL], sr[NL], sim[NL], tr[NL], tim[NL], xr[NL], xim[NL], hr[NL], hi[NL];
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int cr = colq[q];
+        const int64_t ob = (int64_t)cr * a.ldb + i, ox = (int64_t)cr * a.ldx + i, o = (int64_t)cr * a.ld + i;
+        pr[q] = a.p[o];
+        sr[q] = a.s[o];
+        tr[q] = a.t[o];
+        xr[q] = a.x[ox];
+        hr[q] = a.b[ob];
+        pim[q] = sim[q] = tim[q] = xim[q] = hi[q] = (T)0;
+        if (CPLX) {
+          pim[q] = a.p[o + a.ld];
+          sim[q] = a.s[o + a.ld];
+          tim[q] = a.t[o + a.ld];
+          xim[q] = a.x[ox + a.ldx];
+          hi[q] = a.b[ob + a.ldb];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        if (!act[q]) continue;
+        const int cr = c0 + (CPLX ? 2 * q : q);
+        const int lc = CPLX ? cr / 2 : cr;
+        const int64_t ox = (int64_t)cr * a.ldx + i, o = (int64_t)cr * a.ld + i;
+        const double* sc = a.sc + (int64_t)lc * KS;
+        if (!CPLX) {
+          const T al = (T)sc[KS_ALPHA], om = (T)sc[KS_OMEGA];
+          a.x[ox] = xr[q] + (al * pr[q] + om * sr[q]);
+          const T rv = sr[q] - om * tr[q];
+          a.r[o] = rv;
+          dots[q] = hr[q] * rv;               // <rhat, r>
+          dots[CP + q] = rv * rv;             // <r, r>
+        } else {
+          const T alr = (T)sc[KS_ALPHA], ali = (T)sc[KS_ALPHA + 1];
+          const T omr = (T)sc[KS_OMEGA], omi = (T)sc[KS_OMEGA + 1];
+          a.x[ox] = xr[q] + ((alr * pr[q] - ali * pim[q]) + (omr * sr[q] - omi * sim[q]));
+          a.x[ox + a.ldx] = xim[q] + ((alr * pim[q] + ali * pr[q]) + (omr * sim[q] + omi * sr[q]));
+          const T rr = sr[q] - (omr * tr[q] - omi * tim[q]);
+          const T ri = sim[q] - (omr * tim[q] + omi * tr[q]);
+          a.r[o] = rr;
+          a.r[o + a.ld] = ri;
+          dots[2 * q] = hr[q] * rr + hi[q] * ri;          // conj(rhat) r
+          dots[2 * q + 1] = hr[q] * ri - hi[q] * rr;
+          dots[CP + 2 * q] = rr * rr + ri * ri;           // |r|^2
+          dots[CP + 2 * q + 1] = (T)0;
+        }
       }
     }
   }
@@ -357,44 +391,61 @@ __global__ void __launch_bounds__(256) k_bicg_pre(SpmmArgs<T> a) {
   const int i = rb * 256 + threadIdx.x;
   const int c0 = blockIdx.y * CP;
   if (i >= a.n) return;
+  // loads of every column first (inactive ones read the first active column),
+  // then the stores of the active columns
+  bool act[NL], first[NL];
+  int colq[NL];
+  int qa = -1;
 #pragma unroll
   for (int q = 0; q < NL; ++q) {
     const int cr = c0 + (CPLX ? 2 * q : q);
-    if (cr >= a.ncols) continue;
-    const int lc = CPLX ? cr / 2 : cr;
-    const int* st = a.st + (int64_t)lc * KI;
-    if (st[KI_ACTIVE] == 0) continue;
-    const double* sc = a.sc + (int64_t)lc * KS;
+    const int* st = a.st + (int64_t)(CPLX ? cr / 2 : cr) * KI;
+    act[q] = cr < a.ncols && st[KI_ACTIVE] != 0;
+    first[q] = act[q] && st[KI_ITERS] == 0;
+    if (qa < 0 && act[q]) qa = q;
+  }
+  if (qa < 0) return;
+#pragma unroll
+  for (int q = 0; q < NL; ++q) colq[q] = act[q] ? c0 + (CPLX ? 2 * q : q) : c0 + (CPLX ? 2 * qa : qa);
+  T rr[NL], ri[NL], vr[NL], vi[NL], pr[NL], pi[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int64_t o = (int64_t)colq[q] * a.ld + i;
+    rr[q] = a.r[o];
+    vr[q] = a.vold[o];
+    pr[q] = WHICH == MODE_BICG_P ? a.pold[o] : (T)0;
+    ri[q] = vi[q] = pi[q] = (T)0;
+    if (CPLX) {
+      ri[q] = a.r[o + a.ld];
+      vi[q] = a.vold[o + a.ld];
+      if (WHICH == MODE_BICG_P) pi[q] = a.pold[o + a.ld];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    if (!act[q]) continue;
+    const int cr = c0 + (CPLX ? 2 * q : q);
+    const double* sc = a.sc + (int64_t)(CPLX ? cr / 2 : cr) * KS;
     const int64_t o = (int64_t)cr * a.ld + i;
     if (WHICH == MODE_BICG_P) {
-      const bool first = st[KI_ITERS] == 0;
+      // the fused modes' formula; on a column's first iteration p = r
       const T br = (T)sc[KS_BETA], bi = (T)sc[KS_BETA + 1];
       const T wr = (T)sc[KS_OMEGA], wi = (T)sc[KS_OMEGA + 1];
       if (!CPLX) {
-        const T rv = a.r[o];
-        a.pnew[o] = first ? rv : rv + br * (a.pold[o] - wr * a.vold[o]);
+        a.pnew[o] = first[q] ? rr[q] : rr[q] + br * (pr[q] - wr * vr[q]);
       } else {
-        const T rr = a.r[o], ri = a.r[o + a.ld];
-        if (first) {
-          a.pnew[o] = rr;
-          a.pnew[o + a.ld] = ri;
-        } else {
-          const T pr = a.pold[o], pi = a.pold[o + a.ld];
-          const T vr = a.vold[o], vi = a.vold[o + a.ld];
-          const T ur = pr - (wr * vr - wi * vi);
-          const T ui = pi - (wr * vi + wi * vr);
-          a.pnew[o] = rr + (br * ur - bi * ui);
-          a.pnew[o + a.ld] = ri + (br * ui + bi * ur);
-        }
+        const T ur = pr[q] - (wr * vr[q] - wi * vi[q]);
+        const T ui = pi[q] - (wr * vi[q] + wi * vr[q]);
+        a.pnew[o] = first[q] ? rr[q] : rr[q] + (br * ur - bi * ui);
+        a.pnew[o + a.ld] = first[q] ? ri[q] : ri[q] + (br * ui + bi * ur);
       }
     } else {
       const T ar = (T)sc[KS_ALPHA], ai = (T)sc[KS_ALPHA + 1];
       if (!CPLX) {
-        a.s[o] = a.r[o] - ar * a.vold[o];
+        a.s[o] = rr[q] - ar * vr[q];
       } else {
-        const T vr = a.vold[o], vi = a.vold[o + a.ld];
-        a.s[o] = a.r[o] - (ar * vr - ai * vi);
-        a.s[o + a.ld] = a.r[o + a.ld] - (ar * vi + ai * vr);
+        a.s[o] = rr[q] - (ar * vr[q] - ai * vi[q]);
+        a.s[o + a.ld] = ri[q] - (ar * vi[q] + ai * vr[q]);
       }
     }
   }
