@@ -152,8 +152,11 @@ def spmm(ctx: Context, A: DeviceCSR, X: torch.Tensor, shift=0.0, prec="fp64") ->
 
 
 def gram(ctx, X, Y):
-    """C = X^T Y (FP64 matrix cores)."""
-    X, Y = colmajor(X), colmajor(Y)
+    """C = X^T Y (FP64 matrix cores).  Passing the same tensor twice gives an
+    exactly symmetric X^T X."""
+    same = X is Y
+    X = colmajor(X)
+    Y = X if same else colmajor(Y)
     C_ = empty_colmajor(X.shape[1], Y.shape[1], X.device)
     _check(_lib().care_gram(ctx.h, X.shape[0], _ptr(X), _ld(X), X.shape[1], _ptr(Y), _ld(Y), Y.shape[1], _ptr(C_),
                             _ld(C_)))

@@ -6,6 +6,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <cstdlib>
 #include <numeric>
@@ -142,6 +143,19 @@ __global__ void k_gram_reduce(const double* __restrict__ part, int ntl, int nspl
   }
 }
 
+// C(i, j) = sum_s W_s(i, j), s = 0 .. nsplit-1 in order (W_s: a x b, ld a);
+// sym: the lower triangle mirrors the upper one, so C is exactly symmetric
+__global__ void k_sum_partials(int a, int b, int nsplit, const double* __restrict__ W, double* __restrict__ C,
+                               int64_t ldc, int sym) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= a || j >= b) return;
+  const int64_t ab = (int64_t)a * b, o = (sym && i > j) ? (int64_t)i * a + j : (int64_t)j * a + i;
+  double s = 0.0;
+  for (int k = 0; k < nsplit; ++k) s += W[k * ab + o];
+  C[(int64_t)j * ldc + i] = s;
+}
+
 template <typename TX, typename TY>
 void gram(Ctx* ctx, int64_t n, const TX* X, int64_t ldx, int a, const TY* Y, int64_t ldy, int b, double* C,
           int64_t ldc) {
@@ -149,6 +163,42 @@ void gram(Ctx* ctx, int64_t n, const TX* X, int64_t ldx, int a, const TY* Y, int
   if (n <= 0) {
     for (int j = 0; j < b; ++j) dzero(ctx, C + (int64_t)j * ldc, a * sizeof(double));
     return;
+  }
+  if constexpr (sizeof(TX) == 8 && sizeof(TY) == 8) {
+    // large FP64 Grams: rocBLAS dgemm (MFMA) over row chunks (split-K as a
+    // strided batch), partial products summed in a fixed order, so the result
+    // is reproducible (atomics are also disabled on the context's handle)
+    if ((int64_t)a * b >= 32 * 32 && n <= INT32_MAX && ldx <= INT32_MAX && ldy <= INT32_MAX) {
+      const int64_t tiles = (int64_t)((a + 127) / 128) * ((b + 127) / 128);
+      int64_t nsplit = std::max<int64_t>(1, std::min<int64_t>(64, (2048 + tiles - 1) / tiles));
+      nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, n / 2048));
+      const double one = 1.0, zero = 0.0;
+      const bool sym = (const void*)X == (const void*)Y && ldx == ldy && a == b;
+      if (nsplit <= 1 && !sym) {
+        ROCBLAS_CHECK(rocblas_dgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, a, b, (int)n, &one,
+                                    (const double*)X, (int)ldx, (const double*)Y, (int)ldy, &zero, C, (int)ldc));
+        return;
+      }
+      // nsplit equal chunks of rc rows in one strided batch, the remainder
+      // (< 64 nsplit rows) as one more partial product
+      const int64_t rc = nsplit > 1 ? n / nsplit / 64 * 64 : n;
+      const int64_t rem = n - nsplit * rc;
+      const int64_t ab = (int64_t)a * b;
+      const int nparts = (int)nsplit + (rem > 0 ? 1 : 0);
+      DBuf<double> W(ctx, (size_t)(ab * nparts));
+      ROCBLAS_CHECK(rocblas_dgemm_strided_batched(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, a, b,
+                                                  (int)rc, &one, (const double*)X, (int)ldx, rc, (const double*)Y,
+                                                  (int)ldy, rc, &zero, W.get(), a, ab, (int)nsplit));
+      if (rem > 0)
+        ROCBLAS_CHECK(rocblas_dgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, a, b, (int)rem,
+                                    &one, (const double*)X + nsplit * rc, (int)ldx, (const double*)Y + nsplit * rc,
+                                    (int)ldy, &zero, W.get() + nsplit * ab, a));
+      dim3 g(ceil_div(a, 256), b);
+      hipLaunchKernelGGL(k_sum_partials, g, dim3(256), 0, ctx->stream, a, b, nparts, (const double*)W.get(), C, ldc,
+                         sym ? 1 : 0);
+      KERNEL_CHECK();
+      return;
+    }
   }
   const bool sym = (const void*)X == (const void*)Y && ldx == ldy && a == b && sizeof(TX) == sizeof(TY);
   const int tiles_i = (a + 31) / 32, tiles_j = (b + 31) / 32;
@@ -241,6 +291,13 @@ void tsgemm(Ctx* ctx, int64_t n, const TX* X, int64_t ldx, int q, const double* 
       axpby<TY>(ctx, n, k, 0.0, Y, ldy, beta, Y, ldy);
     }
     return;
+  }
+  if constexpr (sizeof(TX) == 8 && sizeof(TY) == 8) {
+    if ((int64_t)q * k >= 64 * 64 && n <= INT32_MAX && ldx <= INT32_MAX && ldy <= INT32_MAX) {
+      ROCBLAS_CHECK(rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, (int)n, k, q, &alpha,
+                                  (const double*)X, (int)ldx, S, (int)lds, &beta, (double*)Y, (int)ldy));
+      return;
+    }
   }
   dim3 grid(ceil_div(n, 64), ceil_div(k, 64));
   hipLaunchKernelGGL((k_tsgemm<TX, TY>), grid, dim3(256), 0, ctx->stream, n, X, ldx, q, S, lds, k, alpha, beta, Y,

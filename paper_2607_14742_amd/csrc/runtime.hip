@@ -172,6 +172,8 @@ void ctx_init(Ctx& c, int device, hipStream_t user_stream) {
     fail(CARE_ERR_DEVICE, "rocblas_create_handle failed");
   }
   rocblas_set_stream(c.blas, c.stream);
+  // reproducible products: no split-K kernels that sum with atomics
+  rocblas_set_atomics_mode(c.blas, rocblas_atomics_not_allowed);
 }
 
 void ctx_release(Ctx& c) {
