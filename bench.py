@@ -20,6 +20,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "CARE solve time & SpMM HBM GB/s: FP32-inner vs FP64, at rel residual <=1e-10"
+# HBM bytes per k_spmm launch measured with rocprofv3 counters (FETCH_SIZE,
+# WRITE_SIZE, calibrated on a 1 GiB copy) for this workload; used only while
+# the kernel source it was measured on is unchanged
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_spmm_fdm2d_500_fp32_hbm_counters.md")
+KERNEL_SOURCES = ("paper_2607_14742_amd/csrc/spmm_kernel.hpp", "paper_2607_14742_amd/csrc/sparse.hip")
 HBM_PEAK_GBS = 8000.0
 TOL = 1e-10
 
@@ -34,6 +39,27 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=12)
     return ap.parse_args()
+
+
+def measured_traffic():
+    """(bytes per launch, note) from the committed counter summary, or
+    (None, reason) when it is missing or was taken on other kernel source."""
+    import hashlib
+    import re
+    try:
+        text = open(PMC_SUMMARY).read()
+    except OSError:
+        return None, "no counter summary"
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.]+)", text)
+    k = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    if not m or not k:
+        return None, "counter summary incomplete"
+    if k.group(1) != h.hexdigest():
+        return None, "kernel changed since the counters were taken"
+    return float(m.group(1)), os.path.relpath(PMC_SUMMARY, ROOT)
 
 
 def cpu_baseline(P, gpu_stats64, sample_steps):
@@ -154,9 +180,13 @@ def main():
     # sparse products of the last FP32-inner solve, timed with HIP events on the solve's stream
     calls, nbytes, tsp = s32["spmm_calls"], s32["spmm_bytes"], s32["t_spmm"]
     spmm_gbs = nbytes / tsp / 1e9 if tsp > 0 else None
-    res["roofline"] = {"bound": "hbm", "kernel": "k_spmm (SELL-64 shifted product, fused BiCGStab passes)",
+    traffic, tnote = measured_traffic()
+    res["roofline"] = {"bound": "hbm",
+                       "kernel": "k_spmm (SELL-64 shifted product of A^T; every launch of the solve: split BiCGStab "
+                                 "products with their dots, and plain products)",
                        "achieved": round(spmm_gbs, 1) if spmm_gbs else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(spmm_gbs / HBM_PEAK_GBS, 4) if spmm_gbs else None, "traffic": None,
+                       "frac": round(spmm_gbs / HBM_PEAK_GBS, 4) if spmm_gbs else None,
+                       "traffic": round(traffic) if traffic else None, "traffic_source": tnote,
                        "launches": calls, "avg_launch_us": round(1e6 * tsp / calls, 2) if calls else None,
                        "algorithmic_bytes_per_launch": round(nbytes / calls) if calls else None}
     s64 = None
