@@ -6,11 +6,17 @@
 // instance (Krylov polls, eigen-splits) never stall the kernels of another,
 // and the sparse products of small instances, which alone cannot fill 256
 // CUs, overlap on the device.  Instances are taken largest first from a
-// shared counter (longest-processing-time order), so the big ones do not
-// start last.
+// shared list (longest-processing-time order), so the big ones do not start
+// last.  A memory budget (60 % of the device memory free at the start) caps
+// the estimated peak workspace of the instances running at once: a worker
+// takes the largest waiting instance that fits, or waits; an instance runs
+// alone when nothing else does.  Running out of device memory mid-solve can
+// also starve the runtime's own allocations (kernel scratch), which is not an
+// error the library could catch.
 #include <algorithm>
-#include <atomic>
+#include <condition_variable>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <thread>
@@ -41,7 +47,58 @@ void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, con
     std::strncpy(res[k].message, "not run", sizeof(res[k].message) - 1);
   }
 
-  std::atomic<int> next{0};
+  // estimated peak workspace per instance: the Newton corrections keep a few
+  // FP64 n x (hundreds to thousands) panels (ADI factor, Algorithm 2 basis,
+  // orthogonalisation remainder); dense instances add one LU per shift
+  const int prec = opts ? opts->inner_prec : CARE_FP64;
+  const int l0 = opts && opts->penzl_l0 > 0 ? opts->penzl_l0 : 16;
+  auto estimate = [&](int k) -> double {
+    const OpSpec sp = spec_of(k);
+    if (!sp.csr && !sp.dense) return 0.0;
+    const double n = (double)sp.size();
+    const double per_row = prec == CARE_FP64 ? 64e3 : 128e3;
+    double e = n * per_row;
+    if (sp.dense) e += n * n * (prec == CARE_FP64 ? 8.0 : 4.0) * (l0 + 2) + 3.0 * n * n * 8.0;
+    return e;
+  };
+  size_t mem_free = 0, mem_total = 0;
+  HIP_CHECK(hipMemGetInfo(&mem_free, &mem_total));
+  const double budget = 0.6 * (double)mem_free;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::vector<char> taken(count, 0);
+  int remaining = count, running = 0;
+  double in_use = 0.0;
+  // next instance for a worker (largest waiting one that fits), or -1 when
+  // none is left; blocks while none fits
+  auto acquire = [&](double& est) -> int {
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+      if (remaining == 0) return -1;
+      for (int i = 0; i < count; ++i) {
+        const int k = order[i];
+        if (taken[k]) continue;
+        const double e = estimate(k);
+        if (running == 0 || in_use + e <= budget) {
+          taken[k] = 1;
+          --remaining;
+          ++running;
+          in_use += e;
+          est = e;
+          return k;
+        }
+      }
+      cv.wait(lk);
+    }
+  };
+  auto release = [&](double est) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      --running;
+      in_use -= est;
+    }
+    cv.notify_all();
+  };
   std::vector<std::string> setup_err(nw);
   auto work = [&](int w) {
     Ctx wc;
@@ -57,8 +114,8 @@ void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, con
       setup_err[w] = "worker context setup failed";
       return;
     }
-    for (int i; (i = next.fetch_add(1)) < count;) {
-      const int k = order[i];
+    double est = 0.0;
+    for (int k; (k = acquire(est)) >= 0;) {
       const care_instance& I = inst[k];
       care_instance_result& R = res[k];
       int r = 0;
@@ -89,6 +146,7 @@ void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, con
       // concurrent workers share the device memory: hand this instance's
       // cached workspace back before the next one
       wc.arena->trim();
+      release(est);
     }
     ctx_release(wc);
   };

@@ -347,34 +347,41 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
     }
     prev = rel;
     if (k == S.prm.k_max - 1) break;     // no correction whose residual would go unchecked
-    DBuf<double> Zpm;
-    int np = 0, nm = 0;
-    if (S.prm.prec == Prec::F64) correction<double>(ctx, S, Z, rf, Zpm, np, nm, st);
-    else correction<float>(ctx, S, Z, rf, Zpm, np, nm, st);
-    // Each of Z+ and Z- is a PSD factor: compressing it alone to the
-    // eigenvalues of Z+- Z+-^T above a quarter of Algorithm 2's own threshold
-    // (eta_s max|lambda(P)|, with max|lambda(P)| ~ ||Z Z^T||_2) changes
-    // G N G^T by at most that much, and shrinks G from the raw ADI width to
-    // the correction's numerical rank.
-    const double tau = 0.25 * S.prm.eta_s_rel * Z.sig_max;
-    const double* parts[2] = {Zpm.get(), Zpm.get() + (int64_t)np * S.ld};
-    int widths[2] = {np, nm};
-    DBuf<double> comp[2];
-    for (int g = 0; g < 2; ++g) {
-      int r = 0;
-      if (tau > 0.0 && widths[g] > 0 && psd_compress(ctx, n, parts[g], S.ld, widths[g], tau, comp[g], r)) {
-        parts[g] = comp[g].get();
-        widths[g] = r;
+    // G = [Z, Z+, Z-] for Algorithm 2; the raw correction factor and its
+    // compressed parts are released before the orthogonalisation of G
+    DBuf<double> G;
+    int s = 0;
+    std::vector<double> sign;
+    {
+      DBuf<double> Zpm;
+      int np = 0, nm = 0;
+      if (S.prm.prec == Prec::F64) correction<double>(ctx, S, Z, rf, Zpm, np, nm, st);
+      else correction<float>(ctx, S, Z, rf, Zpm, np, nm, st);
+      // Each of Z+ and Z- is a PSD factor: compressing it alone to the
+      // eigenvalues of Z+- Z+-^T above a quarter of Algorithm 2's own threshold
+      // (eta_s max|lambda(P)|, with max|lambda(P)| ~ ||Z Z^T||_2) changes
+      // G N G^T by at most that much, and shrinks G from the raw ADI width to
+      // the correction's numerical rank.
+      const double tau = 0.25 * S.prm.eta_s_rel * Z.sig_max;
+      const double* parts[2] = {Zpm.get(), Zpm.get() + (int64_t)np * S.ld};
+      int widths[2] = {np, nm};
+      DBuf<double> comp[2];
+      for (int g = 0; g < 2; ++g) {
+        int r = 0;
+        if (tau > 0.0 && widths[g] > 0 && psd_compress(ctx, n, parts[g], S.ld, widths[g], tau, comp[g], r)) {
+          parts[g] = comp[g].get();
+          widths[g] = r;
+        }
       }
+      // G = [Z, Z+, Z-], Algorithm 2
+      s = Z.r + widths[0] + widths[1];
+      G.resize(ctx, (size_t)S.ld * std::max(s, 1));
+      d2d(ctx, G.get(), Z.Z.get(), (size_t)S.ld * Z.r * sizeof(double));
+      d2d(ctx, G.get() + (int64_t)Z.r * S.ld, parts[0], (size_t)S.ld * widths[0] * sizeof(double));
+      d2d(ctx, G.get() + (int64_t)(Z.r + widths[0]) * S.ld, parts[1], (size_t)S.ld * widths[1] * sizeof(double));
+      sign.assign(s, 1.0);
+      for (int c = Z.r + widths[0]; c < s; ++c) sign[c] = -1.0;
     }
-    // G = [Z, Z+, Z-], Algorithm 2
-    const int s = Z.r + widths[0] + widths[1];
-    DBuf<double> G(ctx, (size_t)S.ld * std::max(s, 1));
-    d2d(ctx, G.get(), Z.Z.get(), (size_t)S.ld * Z.r * sizeof(double));
-    d2d(ctx, G.get() + (int64_t)Z.r * S.ld, parts[0], (size_t)S.ld * widths[0] * sizeof(double));
-    d2d(ctx, G.get() + (int64_t)(Z.r + widths[0]) * S.ld, parts[1], (size_t)S.ld * widths[1] * sizeof(double));
-    std::vector<double> sign(s, 1.0);
-    for (int c = Z.r + widths[0]; c < s; ++c) sign[c] = -1.0;
     TruncResult Zn;
     signed_truncate(ctx, n, G.get(), S.ld, s, sign, S.prm.eta_s_rel, Zn);
     st->eta_n = Zn.eta_n;
