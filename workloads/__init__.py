@@ -231,6 +231,22 @@ def fdm2d_problem(N: int, m: int, p: int, nu: float = 10.0, seed: int = DEFAULT_
                    dict(N=N, nu=nu, seed=seed, lam_lo=lo, lam_hi=hi))
 
 
+def fdm3d_problem(N: int, m: int, p: int, nu: float = 100.0, field_kind: str = "rotating",
+                  seed: int = DEFAULT_SEED, name: str = None) -> Problem:
+    """3D FDM CARE with Gaussian B, C; no shift set (the complex spectrum of
+    the rotating field has no closed form: the shifts come from the
+    heuristic)."""
+    A = fdm3d(N, nu, field_kind)
+    B, C = gaussian_factors(N ** 3, m, p, seed)
+    return Problem(name or f"fdm3d_N{N}_m{m}_p{p}_{field_kind}", A, B, C, None,
+                   dict(N=N, nu=nu, field=field_kind, seed=seed))
+
+
+def config3() -> Problem:
+    """64^3 grid (n = 262,144, nnz = 1,810,432), rotating field, m = 1, p = 10."""
+    return fdm3d_problem(64, 1, 10, name="cfg3_fdm3d_64")
+
+
 def config1() -> Problem:
     """20 x 20 grid (n = 400, nnz = 1920), nu = 10, m = p = 1."""
     return fdm2d_problem(20, 1, 1, name="cfg1_fdm2d_20x20")
