@@ -117,6 +117,9 @@ typedef struct {
   int32_t penzl_real;     /* auto shifts: 1 keeps the real parts of the Ritz values */
   int32_t spmm_split;     /* BiCGStab products: 0 chooses by the L2 footprint of the
                              fused gathers, 1 fused, 2 split (update pass + product) */
+  int32_t krylov_relax;   /* 1 (default): inexact LR-ADI, the inner tolerance of step j
+                             grows as ktol / (4 ||W_j^T W_j|| / ||W_0^T W_0||), capped
+                             at sqrt(ktol); 0: ktol for every solve                  */
 } care_opts;
 
 /* Statistics written by the solvers (host struct). */

@@ -37,7 +37,7 @@ class care_opts(C.Structure):
         ("check_every", C.c_int32), ("penzl_l0", C.c_int32), ("penzl_kp", C.c_int32), ("penzl_km", C.c_int32),
         ("profile", C.c_int32), ("Z_init", C.c_void_p), ("ldz_init", C.c_int64), ("r_init", C.c_int32),
         ("adi_deflate", C.c_int32), ("krylov_block_tol", C.c_int32), ("penzl_real", C.c_int32),
-        ("spmm_split", C.c_int32),
+        ("spmm_split", C.c_int32), ("krylov_relax", C.c_int32),
     ]
 
 

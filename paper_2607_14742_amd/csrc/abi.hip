@@ -43,6 +43,10 @@ Ctx* unwrap(care_ctx* c) {
   return &c->c;
 }
 
+// After a solve the workspace cache may hold tens of GB (wide refinement
+// panels): keep a modest amount for the next call, hand the rest back.
+void release_cache(Ctx* ctx) { ctx->arena->trim_to(size_t(4) << 30); }
+
 void check_csr_shape(const care_csr* A) {
   if (!A) fail(CARE_ERR_ARG, "A is NULL");
   if (A->n < 1) fail(CARE_ERR_ARG, "A must have n >= 1");
@@ -76,6 +80,7 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->penzl_km = 10;
   o->penzl_real = 0;
   o->spmm_split = 0;
+  o->krylov_relax = 1;
   o->profile = 0;
   o->Z_init = nullptr;
   o->ldz_init = 0;
@@ -249,6 +254,7 @@ care_status lyap_lradi(care_ctx* cx, const care_csr* A, const double* B, const d
     lp.kmaxit = r.kmaxit;
     lp.check_every = r.check_every;
     lp.deflate = false;      // keep the documented block layout of Z
+    lp.relax = o->krylov_relax != 0;
     ctx->reset_counters();
     ctx->profile = o->profile;
     ctx->spmm_split = o->spmm_split;
@@ -294,6 +300,7 @@ care_status lyap_lradi(care_ctx* cx, const care_csr* A, const double* B, const d
       stats->hist_len = 1;
       stats->res_hist[0] = lo.res_rel;
     }
+    release_cache(ctx);
     if (w > 0 && lo.res_rel > lp.tol) return CARE_WARN_MAXIT;
     return lo.krylov_unconverged ? CARE_WARN_MAXIT : CARE_OK;
   });
@@ -365,6 +372,7 @@ care_status care_solve(care_ctx* cx, const care_csr* A, const double* B, int32_t
     care_solve_impl(ctx, sparse_spec(A), B, m, C, p, tol, shifts, nshifts, opts, Z, ldz, rmax, r_out,
                     stats ? stats : &local,
                     &warn);
+    release_cache(ctx);
     return warn;
   });
 }
@@ -380,6 +388,7 @@ care_status care_solve_dense(care_ctx* cx, const double* A, int64_t n, int64_t l
     care_status warn = CARE_OK;
     care_solve_impl(ctx, dense_spec(A, n, lda), B, m, C, p, tol, shifts, nshifts, opts, Z, ldz, rmax, r_out,
                     stats ? stats : &local, &warn);
+    release_cache(ctx);
     return warn;
   });
 }

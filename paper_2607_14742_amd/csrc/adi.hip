@@ -104,10 +104,13 @@ __global__ void __launch_bounds__(256) k_adi_update(int64_t n, int w, int m, int
 
 // ||W^T W||_F and the squared column norms of W
 template <typename T>
-static double gram_stats(Ctx* ctx, int64_t n, const T* W, int64_t ld, int w, std::vector<double>& colnorm2) {
+static double gram_stats(Ctx* ctx, int64_t n, const T* W, int64_t ld, int w, std::vector<double>& colnorm2,
+                         std::vector<double>* full = nullptr) {
   DBuf<double> G(ctx, (size_t)w * w);
   gram(ctx, n, W, ld, w, W, ld, w, G.get(), w);
-  std::vector<double> h((size_t)w * w);
+  std::vector<double> local;
+  std::vector<double>& h = full ? *full : local;
+  h.resize((size_t)w * w);
   d2h(ctx, h.data(), G.get(), h.size() * sizeof(double));
   double s = 0;
   for (double v : h) s += v * v;
@@ -212,25 +215,38 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
   std::vector<double> yr, yi;
   const bool trace = std::getenv("MPCARE_TRACE") != nullptr;
   // Column deflation: ADI acts on each column of W independently.  The
-  // columns kept at the front (physical 0 .. wa-1) are iterated; a column is
-  // frozen once its squared norm, added to those already frozen, stays below
-  // a quarter of the stopping level tau_L ||W0^T W0||_F, so the frozen part
-  // alone can never keep the stopping test from being met.
+  // columns kept at the front (physical 0 .. wa-1) are iterated; the others
+  // are frozen as they are.  Since W W^T = W_a W_a^T + W_f W_f^T, a frozen set
+  // F with ||W_F^T W_F||_F under a quarter of the stopping level
+  // tau_L ||W0^T W0||_F can never keep the stopping test (which always
+  // covers every column) from being met.  Columns join F smallest first
+  // while that Frobenius norm, computed from the Gram of W, allows.
   std::vector<int> perm(w);
   for (int c = 0; c < w; ++c) perm[c] = c;
   int wa = w;
-  double frozen = 0.0;
+  double frozen2 = 0.0;   // ||W_F^T W_F||_F^2 of the frozen columns
   const double budget = prm.deflate ? 0.25 * prm.tol * out.res0 : 0.0;
+  std::vector<double> gfull;
 
   size_t idx = 0;
+  LradiParams sp = prm;   // per-step copy (Krylov tolerance)
   while (out.steps < prm.jmax && wa > 0) {
     const Shift p = shifts[idx % shifts.size()];
     ShiftCache& sc = cache[idx % shifts.size()];
+    // Inexact ADI (relaxation of the inner solves): an inner solve of
+    // relative accuracy eps on W_{j-1} perturbs the Lyapunov residual by about
+    // eps ||W_{j-1}||^2 = eps res_rel ||W0||^2, so once the residual has
+    // dropped, looser solves keep that perturbation at the level of the first
+    // step's: tol_j = ktol / (4 res_rel), between ktol and sqrt(ktol).  The
+    // solves that also produce the cached SMW block M^{-1} K stay at ktol.
+    sp.ktol = prm.ktol;
+    if (prm.relax && out.steps > 0 && (sc.ready || !smw))
+      sp.ktol = std::min(std::sqrt(prm.ktol), std::max(prm.ktol, prm.ktol / (4.0 * std::max(out.res_rel, 1e-300))));
     const bool cp = p.im != 0.0;
     const int width = (cp ? 2 : 1) * wa;
     if (out.zcols + width > zmax) fail(CARE_ERR_CAPACITY, "LR-ADI factor buffer too small");
     Z.reserve(ctx, out.zcols, out.zcols + width);
-    KrylovResult kr = smw_step<T>(ctx, op, B, K, m, W, wa, p, sc, prm, rhs.get(), sol.get(), yr, yi);
+    KrylovResult kr = smw_step<T>(ctx, op, B, K, m, W, wa, p, sc, sp, rhs.get(), sol.get(), yr, yi);
     out.krylov_unconverged += kr.unconverged;
     out.krylov_max_iters = std::max(out.krylov_max_iters, kr.max_iters);
     if (smw) {
@@ -259,7 +275,7 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
     out.zcols += width;
     for (int rep = 0; rep < (cp ? 2 : 1); ++rep)
       for (int c = 0; c < wa; ++c) out.zsrc.push_back(perm[c]);
-    const double res = gram_stats(ctx, n, W, ld, w, cn);
+    const double res = gram_stats(ctx, n, W, ld, w, cn, budget > 0.0 ? &gfull : nullptr);
     if (!std::isfinite(res)) fail(CARE_ERR_NONFINITE, "LR-ADI residual became non-finite");
     out.res_rel = res / out.res0;
     if (trace)
@@ -275,9 +291,15 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
       for (int c = 0; c < wa; ++c) order[c] = c;
       std::sort(order.begin(), order.end(), [&](int a, int b) { return cn[a] < cn[b]; });
       std::vector<char> freeze(wa, 0);
+      std::vector<int> fset;     // physical columns of F: the frozen tail and the new ones
+      for (int c = wa; c < w; ++c) fset.push_back(c);
+      const double b2 = budget * budget;
       for (int c : order) {
-        if (frozen + cn[c] > budget) break;
-        frozen += cn[c];
+        double add = gfull[(size_t)c * w + c] * gfull[(size_t)c * w + c];
+        for (int f : fset) add += 2.0 * gfull[(size_t)c * w + f] * gfull[(size_t)c * w + f];
+        if (frozen2 + add > b2) break;
+        frozen2 += add;
+        fset.push_back(c);
         freeze[c] = 1;
       }
       // compact: move frozen columns behind the active ones

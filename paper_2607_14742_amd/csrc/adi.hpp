@@ -31,6 +31,7 @@ struct LradiParams {
   int check_every = 8;
   bool deflate = true;       // freeze converged columns of W (see lradi_run)
   bool group_tol = true;     // Krylov accuracy relative to the block's largest column
+  bool relax = false;        // inexact ADI: looser solves as the ADI residual shrinks (lradi_run)
 };
 
 struct LradiOut {

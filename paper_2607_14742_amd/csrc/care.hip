@@ -43,6 +43,7 @@ Resolved resolve_opts(const care_opts* o, double tol) {
   r.check_every = o->check_every > 0 ? o->check_every : 8;
   r.deflate = o->adi_deflate != 0;
   r.block_tol = o->krylov_block_tol != 0;
+  r.relax = o->krylov_relax != 0;
   if (r.k_max < 1 || r.k0_max < 1 || r.j_max < 1) fail(CARE_ERR_ARG, "k_max, k0_max and j_max must be >= 1");
   if (r.eta_r_rel < 0 || r.eta_s_rel < 0) fail(CARE_ERR_ARG, "truncation thresholds must be >= 0");
   return r;
@@ -115,6 +116,7 @@ static void stage0(Ctx* ctx, SolveState& S, TruncResult& Zout, care_stats* st, s
   lp.check_every = S.prm.check_every;
   lp.deflate = S.prm.deflate;
   lp.group_tol = S.prm.block_tol;
+  lp.relax = S.prm.relax;
   double prev = 0.0;
   int zcols = 0;
   for (int i = 0; i < S.prm.k0_max; ++i) {
@@ -192,6 +194,7 @@ static void correction(Ctx* ctx, SolveState& S, const TruncResult& Zk, const Res
   lp.check_every = S.prm.check_every;
   lp.deflate = S.prm.deflate;
   lp.group_tol = S.prm.block_tol;
+  lp.relax = S.prm.relax;
   LradiOut lo = lradi_run<T>(ctx, *S.As, Bs.get(), (m > 0 && Zk.r > 0) ? Ks.get() : nullptr, m, W.get(), w,
                              S.shifts, lp, Zb, zcap);
   st->iter_inner += lo.steps;

@@ -74,13 +74,17 @@ class Arena {
   void* get(size_t bytes);
   void put(void* p);
   void trim();   // return every cached block to the device (after a stream sync)
+  // return cached blocks, largest first, until at most `keep` bytes stay cached
+  void trim_to(size_t keep);
   size_t in_use() const { return in_use_; }
+  size_t cached() const { return cached_; }
 
  private:
   hipStream_t stream_;
   std::multimap<size_t, void*> free_;
   std::map<void*, size_t> live_;
   size_t in_use_ = 0;
+  size_t cached_ = 0;
 };
 
 // ----------------------------------------------------------------------------

@@ -34,6 +34,7 @@ void* Arena::get(size_t bytes) {
     void* p = it->second;
     size_t sz = it->first;
     free_.erase(it);
+    cached_ -= sz;
     live_[p] = sz;
     in_use_ += sz;
     return p;
@@ -46,6 +47,7 @@ void* Arena::get(size_t bytes) {
     (void)hipStreamSynchronize(stream_);
     for (auto& kv : free_) (void)hipFree(kv.second);
     free_.clear();
+    cached_ = 0;
     e = hipMalloc(&p, rb);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -57,16 +59,24 @@ void* Arena::get(size_t bytes) {
   return p;
 }
 
-void Arena::trim() {
+void Arena::trim() { trim_to(0); }
+
+void Arena::trim_to(size_t keep) {
+  if (cached_ <= keep) return;
   (void)hipStreamSynchronize(stream_);
-  for (auto& kv : free_) (void)hipFree(kv.second);
-  free_.clear();
+  while (cached_ > keep && !free_.empty()) {
+    auto it = std::prev(free_.end());   // largest cached block
+    (void)hipFree(it->second);
+    cached_ -= it->first;
+    free_.erase(it);
+  }
 }
 
 void Arena::put(void* p) {
   auto it = live_.find(p);
   if (it == live_.end()) return;
   in_use_ -= it->second;
+  cached_ += it->second;
   free_.emplace(it->second, p);
   live_.erase(it);
 }

@@ -119,6 +119,10 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
   constexpr int NL = CPLX ? CP / 2 : CP;          // logical columns in the panel
   static_assert(!CPLX || (CP % 2 == 0), "complex panels hold column pairs");
 
+  // grid: (row block, panel); consecutive row blocks of a panel share an XCD
+  // (and the halo rows of the neighbouring blocks in its L2).  Running the
+  // panels of one row block back to back instead (to read the matrix once)
+  // was measured slower: the halo rows matter more than the matrix re-reads.
   const int rb = (int)xcd_remap(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   const int i = rb * 256 + tid;
