@@ -187,14 +187,17 @@ care_status care_shifted_solve(care_ctx* ctx, const care_csr* A, const double* B
                                const double* W, int64_t ldw, int32_t w, int32_t prec,
                                double tol, int32_t maxit, double* V, int64_t ldv, int32_t* iters);
 
-/* Gram product C = X^T Y of tall-skinny FP64 panels (FP64 matrix cores),
- * the Gram step of the thin QR of F in Algorithm 1 and of G in Algorithm 2.
- * X: n x a (ldx >= n), Y: n x b (ldy >= n), C: a x b (ldc >= a).  Summation
- * over row blocks runs in a fixed order (run-to-run reproducible). */
+/* Gram product C = X^T Y of tall-skinny FP64 panels (FP64 matrix cores:
+ * rocBLAS dgemm over row chunks for a * b >= 1024, the library's own MFMA
+ * kernel below), the Gram step of the thin QR of F in Algorithm 1 and of G in
+ * Algorithm 2.  X: n x a (ldx >= n), Y: n x b (ldy >= n), C: a x b (ldc >= a).
+ * Partial products over row chunks are summed in a fixed order (run-to-run
+ * reproducible); X == Y (same pointer and ld) gives an exactly symmetric C. */
 care_status care_gram(care_ctx* ctx, int64_t n, const double* X, int64_t ldx, int32_t a, const double* Y,
                       int64_t ldy, int32_t b, double* C, int64_t ldc);
 
-/* Tall-skinny product Y = alpha X S + beta Y (FP64 matrix cores): X n x q
+/* Tall-skinny product Y = alpha X S + beta Y (FP64 matrix cores: rocBLAS
+ * dgemm for q * k >= 4096, the library's own MFMA kernel below): X n x q
  * (ldx >= n), S q x k (lds >= q), Y n x k (ldy >= n); beta = 0 does not read
  * Y.  Forms U = F T^{-1}, C+- = U Q+- |Lambda+-|^(1/2) and Z = V Theta+
  * Sigma+^(1/2) in Algorithms 1 and 2. */

@@ -1,0 +1,118 @@
+"""Edge cases of the CARE solver through the C ABI: closed forms (n = 1, a
+decoupled diagonal CARE, the Lyapunov case m = 0), error statuses raised
+before any device work, the capacity protocol, and the bf16-product variant on
+the 20 x 20 problem."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as wl
+from oracle import lowrank, riccati
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2607_14742_amd as pk
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pk.load()
+    return pk
+
+
+@pytest.fixture(scope="module")
+def ctx(pk):
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), device="cuda")
+
+
+def scalar_care(a, b2, c2):
+    # 2 a x - b^2 x^2 + c^2 = 0, stabilising root, cancellation-free for a < 0
+    return c2 / (np.sqrt(a * a + b2 * c2) - a)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_scalar_care_closed_form(pk, ctx, prec):
+    a, b, c = -2.0, 1.5, 0.7
+    A = sp.csr_matrix(np.array([[a]]))
+    Z, stats, st = pk.care_solve(ctx, pk.DeviceCSR.from_scipy(A), dev([[b]]), dev([[c]]), tol=1e-13,
+                                 shifts=np.array([-1.0, -3.0]), prec=prec)
+    assert st in (0, 1), stats
+    x = float((Z.cpu().numpy() ** 2).sum())
+    assert abs(x - scalar_care(a, b * b, c * c)) <= 1e-12 * scalar_care(a, b * b, c * c)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_decoupled_diagonal_care(pk, ctx, prec):
+    n = 50
+    rng = np.random.default_rng(21)
+    a = -np.logspace(0, 2, n)
+    b = rng.uniform(0.5, 2.0, n)
+    c = rng.uniform(0.5, 2.0, n)
+    A = sp.diags(a).tocsr()
+    Z, stats, st = pk.care_solve(ctx, pk.DeviceCSR.from_scipy(A), dev(np.diag(b)), dev(np.diag(c)), tol=1e-12,
+                                 shifts=wl.logspaced_real_shifts(1.0, 100.0, 12), prec=prec)
+    assert st == 0, stats
+    X = Z.cpu().numpy() @ Z.cpu().numpy().T
+    xd = scalar_care(a, b * b, c * c)
+    assert np.linalg.norm(X - np.diag(xd)) <= 1e-9 * np.linalg.norm(xd)
+
+
+def test_lyapunov_case_m0(pk, ctx):
+    # B absent: the CARE is the Lyapunov equation A^T X + X A + C^T C = 0
+    P = wl.fdm2d_problem(12, 1, 3)
+    Z, stats, st = pk.care_solve(ctx, pk.DeviceCSR.from_scipy(P.A), torch.zeros(P.n, 0, dtype=torch.float64,
+                                 device="cuda"), dev(P.C), tol=1e-12, shifts=P.shifts, prec="fp32")
+    assert st == 0, stats
+    Z = Z.cpu().numpy()
+    X = riccati.lyap_bartels_stewart(P.A.toarray().T, -(P.C.T @ P.C))
+    assert np.linalg.norm(Z @ Z.T - X) <= 1e-9 * np.linalg.norm(X)
+
+
+def test_bf16_products_on_config1(pk, ctx):
+    P = wl.config1()
+    Z, stats, st = pk.care_solve(ctx, pk.DeviceCSR.from_scipy(P.A), dev(P.B), dev(P.C), tol=1e-12, shifts=P.shifts,
+                                 prec="bf16")
+    assert st == 0, stats
+    Z = Z.cpu().numpy()
+    Xs = riccati.care_schur(P.A, P.B, P.C)
+    assert np.linalg.norm(Z @ Z.T - Xs) <= 1e-8 * np.linalg.norm(Xs)
+
+
+@pytest.mark.parametrize("shifts,what", [
+    (np.array([-5.0, 2.0]), "Re p >= 0"),
+    (np.array([-5.0 + 1j]), "complex shift without its conjugate"),
+    (np.array([-5.0 - 1j, -5.0 + 1j]), "pair with Im < 0 first"),
+])
+def test_invalid_shift_sets_are_argument_errors(pk, ctx, shifts, what):
+    P = wl.config1()
+    with pytest.raises(pk.CareError) as e:
+        pk.care_solve(ctx, pk.DeviceCSR.from_scipy(P.A), dev(P.B), dev(P.C), tol=1e-10, shifts=shifts)
+    assert e.value.name == "CARE_ERR_ARG", what
+
+
+def test_capacity_protocol(pk, ctx):
+    from paper_2607_14742_amd import _lib as L
+    import ctypes as C
+    P = wl.config1()
+    A = pk.DeviceCSR.from_scipy(P.A)
+    B, Cm = dev(P.B), dev(P.C)
+    Z = torch.empty(P.n, 2, dtype=torch.float64, device="cuda")
+    r = C.c_int32(0)
+    stats = L.care_stats()
+    opts = pk.default_opts("fp64")
+    arr, ns = pk.api._shift_array(P.shifts)
+    st = L.load().care_solve(ctx.h, A.c, C.c_void_p(B.data_ptr()), 1, C.c_void_p(Cm.data_ptr()), 1, 1e-12, arr, ns,
+                             C.byref(opts), C.c_void_p(Z.data_ptr()), P.n, 2, C.byref(r), C.byref(stats))
+    assert st == L.CARE_ERR_CAPACITY
+    assert r.value > 2                      # the columns the result needs
+    Z2, stats2, st2 = pk.care_solve(ctx, A, B, Cm, tol=1e-12, shifts=P.shifts, prec="fp64", rmax=r.value)
+    assert st2 == 0 and Z2.shape[1] == r.value
