@@ -94,7 +94,7 @@ typedef struct {
   double tau_L;           /* inner LR-ADI stop ||W^T W||_F <= tau_L ||W0^T W0||_F;
                              <= 0 selects 1e-12 (FP64) / 1e-5 (FP32) / 1e-3 (BF16)    */
   double tau_0;           /* initial NLR-ADI stop on the relative Riccati residual;
-                             <= 0 selects max(tol / 10, 10 tau_L)                     */
+                             <= 0 selects max(tol / 10, 10 tau_L0)                    */
   double stagnation;      /* stop when ||R_{k+1}|| / ||R_k|| > stagnation (0.999)     */
   int32_t krylov_maxit;   /* BiCGStab iteration cap per shifted solve (4000)          */
   double krylov_tol;      /* per-column relative residual; <= 0 selects
@@ -120,6 +120,17 @@ typedef struct {
   int32_t krylov_relax;   /* 1 (default): inexact LR-ADI, the inner tolerance of step j
                              grows as ktol / (4 ||W_j^T W_j|| / ||W_0^T W_0||), capped
                              at sqrt(ktol); 0: ktol for every solve                  */
+  double refine_forcing;  /* theta of the inexact-Newton forcing of the refinement
+                             corrections (0.1).  With rel_k = ||R(Z_k)||_F / ||C^T C||_F
+                             the correction LR-ADI stops at
+                             tau_k = min(0.1, max(tau_L, theta tol / rel_k)), its
+                             Krylov tolerance is max(krylov_tol, tau_k / 10), and
+                             Algorithm 1 also drops the smallest residual eigenvalues
+                             whose joint Frobenius norm stays below
+                             theta tol ||C^T C||_F.  0: tau_L, krylov_tol and eta_r
+                             alone, as in Sec. 5                                    */
+  double tau_L0;          /* LR-ADI tolerance inside the initial NLR-ADI solve; <= 0
+                             selects tau_L                                          */
 } care_opts;
 
 /* Statistics written by the solvers (host struct). */
@@ -160,6 +171,12 @@ const char* care_last_error(void);
 
 /* Library version string (static storage). */
 const char* care_version(void);
+
+/* sizeof of the ABI structs as this library was compiled, for bindings to
+ * check their own layouts: sizes[0..count) receives care_csr, care_shift,
+ * care_opts, care_stats, care_instance, care_instance_result (count <= 6).
+ * sizes is HOST memory.  Needs no device. */
+care_status care_struct_sizes(int64_t* sizes, int32_t count);
 
 /* ---------------------------------------------------------------------- */
 /* Building blocks of the LR-ADI inner loop (Sec. 4)                        */

@@ -37,7 +37,8 @@ class care_opts(C.Structure):
         ("check_every", C.c_int32), ("penzl_l0", C.c_int32), ("penzl_kp", C.c_int32), ("penzl_km", C.c_int32),
         ("profile", C.c_int32), ("Z_init", C.c_void_p), ("ldz_init", C.c_int64), ("r_init", C.c_int32),
         ("adi_deflate", C.c_int32), ("krylov_block_tol", C.c_int32), ("penzl_real", C.c_int32),
-        ("spmm_split", C.c_int32), ("krylov_relax", C.c_int32),
+        ("spmm_split", C.c_int32), ("krylov_relax", C.c_int32), ("refine_forcing", C.c_double),
+        ("tau_L0", C.c_double),
     ]
 
 
@@ -79,6 +80,7 @@ SIGNATURES = {
     "care_opts_default": (None, [C.POINTER(care_opts), I32]),
     "care_last_error": (C.c_char_p, []),
     "care_version": (C.c_char_p, []),
+    "care_struct_sizes": (I32, [C.POINTER(I64), I32]),
     "care_spmm": (I32, [P, C.POINTER(care_csr), I32, care_shift, P, I64, I32, P, I64]),
     "care_shifted_solve": (I32, [P, C.POINTER(care_csr), P, I64, P, I64, I32, care_shift, P, I64, I32, I32, DBL,
                                  I32, P, I64, PI32]),

@@ -58,6 +58,17 @@ extern "C" {
 
 const char* care_version(void) { return "mpcare 0.1 (gfx950)"; }
 
+care_status care_struct_sizes(int64_t* sizes, int32_t count) {
+  return guarded([&]() -> care_status {
+    if (!sizes || count < 0 || count > 6) fail(CARE_ERR_ARG, "sizes is NULL or count outside [0, 6]");
+    const int64_t all[6] = {(int64_t)sizeof(care_csr),  (int64_t)sizeof(care_shift),
+                            (int64_t)sizeof(care_opts), (int64_t)sizeof(care_stats),
+                            (int64_t)sizeof(care_instance), (int64_t)sizeof(care_instance_result)};
+    for (int i = 0; i < count; ++i) sizes[i] = all[i];
+    return CARE_OK;
+  });
+}
+
 const char* care_last_error(void) { return last_error_cstr(); }
 
 void care_opts_default(care_opts* o, int32_t inner_prec) {
@@ -81,6 +92,8 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->penzl_real = 0;
   o->spmm_split = 0;
   o->krylov_relax = 1;
+  o->refine_forcing = 0.1;
+  o->tau_L0 = 0.0;         // precision default
   o->profile = 0;
   o->Z_init = nullptr;
   o->ldz_init = 0;

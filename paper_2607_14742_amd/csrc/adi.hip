@@ -280,9 +280,10 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
     out.res_rel = res / out.res0;
     if (trace)
       std::fprintf(stderr,
-                   "[lradi] step %d p (%.4e, %.4e) w %d smw %d krylov it %d unconv %d relres %.2e adi res %.3e\n",
-                   out.steps, p.re, p.im, wa, smw ? 1 : 0, kr.max_iters, kr.unconverged, kr.worst_relres,
-                   out.res_rel);
+                   "[lradi] step %d p (%.4e, %.4e) w %d smw %d krylov it %d unconv %d restarts %d relres %.2e "
+                   "adi res %.3e\n",
+                   out.steps, p.re, p.im, wa, smw ? 1 : 0, kr.max_iters, kr.unconverged, kr.restarts,
+                   kr.worst_relres, out.res_rel);
     if (out.res_rel > 1e8) fail(CARE_ERR_UNSTABLE, "LR-ADI diverged (is A - B K^T stable?)");
     if (out.res_rel <= prm.tol) break;
     if (budget > 0.0) {

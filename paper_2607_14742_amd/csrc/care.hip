@@ -30,9 +30,11 @@ Resolved resolve_opts(const care_opts* o, double tol) {
                                             : (r.prec == Prec::F32 ? 1e-7 : 1e-3);
   r.tau_L = o->tau_L > 0 ? o->tau_L : tl_def;
   r.ktol = o->krylov_tol > 0 ? o->krylov_tol : kt_def;
+  r.tau_L0 = o->tau_L0 > 0 ? o->tau_L0 : r.tau_L;
   // the initial solve's residual estimate ignores the inner solves' own
   // errors, so it is asked for a tenth of the final tolerance
-  r.tau_0 = o->tau_0 > 0 ? o->tau_0 : std::max(0.1 * tol, 10.0 * r.tau_L);
+  r.tau_0 = o->tau_0 > 0 ? o->tau_0 : std::max(0.1 * tol, 10.0 * r.tau_L0);
+  r.theta = o->refine_forcing;
   r.eta_r_rel = o->eta_r_rel;
   r.eta_s_rel = o->eta_s_rel;
   r.stagnation = o->stagnation > 0 ? o->stagnation : 0.999;
@@ -46,6 +48,7 @@ Resolved resolve_opts(const care_opts* o, double tol) {
   r.relax = o->krylov_relax != 0;
   if (r.k_max < 1 || r.k0_max < 1 || r.j_max < 1) fail(CARE_ERR_ARG, "k_max, k0_max and j_max must be >= 1");
   if (r.eta_r_rel < 0 || r.eta_s_rel < 0) fail(CARE_ERR_ARG, "truncation thresholds must be >= 0");
+  if (!(r.theta >= 0.0 && r.theta < 1.0)) fail(CARE_ERR_ARG, "refine_forcing must lie in [0, 1)");
   return r;
 }
 
@@ -109,7 +112,7 @@ static void stage0(Ctx* ctx, SolveState& S, TruncResult& Zout, care_stats* st, s
   Zb.init(ctx, n, std::min(zcap, 16 * wmax));
   DBuf<double> Y;
   LradiParams lp;
-  lp.tol = S.prm.tau_L;
+  lp.tol = S.prm.tau_L0;
   lp.jmax = S.prm.j_max;
   lp.ktol = S.prm.ktol;
   lp.kmaxit = S.prm.kmaxit;
@@ -164,8 +167,8 @@ static void stage0(Ctx* ctx, SolveState& S, TruncResult& Zout, care_stats* st, s
 // precision T; returns the factor promoted to FP64 with its columns grouped
 // by origin: Zpm = [Z+ (np columns), Z- (nm columns)]
 template <typename T>
-static void correction(Ctx* ctx, SolveState& S, const TruncResult& Zk, const ResidualFactor& rf, DBuf<double>& Zpm,
-                       int& np, int& nm, care_stats* st) {
+static void correction(Ctx* ctx, SolveState& S, const TruncResult& Zk, const ResidualFactor& rf, double tau,
+                       double ktol, DBuf<double>& Zpm, int& np, int& nm, care_stats* st) {
   const int64_t n = S.n, ld = S.ld;
   const int m = S.m;
   const int w = rf.rp + rf.rm;
@@ -187,9 +190,9 @@ static void correction(Ctx* ctx, SolveState& S, const TruncResult& Zk, const Res
   ZBuffer<T> Zb;
   Zb.init(ctx, n, std::min(zcap, 16 * std::max(w, 1)));
   LradiParams lp;
-  lp.tol = S.prm.tau_L;
+  lp.tol = tau;
   lp.jmax = S.prm.j_max;
-  lp.ktol = S.prm.ktol;
+  lp.ktol = ktol;
   lp.kmaxit = S.prm.kmaxit;
   lp.check_every = S.prm.check_every;
   lp.deflate = S.prm.deflate;
@@ -322,9 +325,18 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   TruncResult bestZ;
   bool converged = false, stagnated = false;
   double last_res = NAN;
+  // Inexact Newton forcing: correction k only has to bring the residual from
+  // rel_k down to the tolerance, so its Lyapunov solve stops at
+  // theta tol / rel_k relative (never looser than 0.1, never tighter than
+  // tau_L), its shifted solves at a tenth of that, and the residual
+  // eigenvalues Algorithm 1 drops may add up to theta tol ||C^T C||_F on top
+  // of its relative threshold.  These terms add at most about 2 theta tol to
+  // the next residual.
+  const double theta = S.prm.theta;
   for (int k = 0; k < S.prm.k_max; ++k) {
     ResidualFactor rf;
-    residual_factor(ctx, A64, S.B64.get(), m, S.Ct64.get(), p, Z.Z.get(), S.ld, Z.r, S.prm.eta_r_rel, rf);
+    residual_factor(ctx, A64, S.B64.get(), m, S.Ct64.get(), p, Z.Z.get(), S.ld, Z.r, S.prm.eta_r_rel, rf,
+                    theta * tol * S.nrm_ctc);
     st->iter_outer += 1;
     const double rel = rf.res_fro / S.nrm_ctc;
     if (!std::isfinite(rel)) fail(CARE_ERR_NONFINITE, "Riccati residual is not finite");
@@ -358,8 +370,14 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
     {
       DBuf<double> Zpm;
       int np = 0, nm = 0;
-      if (S.prm.prec == Prec::F64) correction<double>(ctx, S, Z, rf, Zpm, np, nm, st);
-      else correction<float>(ctx, S, Z, rf, Zpm, np, nm, st);
+      double tau_k = S.prm.tau_L, kt_k = S.prm.ktol;
+      if (theta > 0.0) {
+        tau_k = std::min(0.1, std::max(S.prm.tau_L, theta * tol / rel));
+        kt_k = std::max(S.prm.ktol, 0.1 * tau_k);
+      }
+      if (std::getenv("MPCARE_TRACE")) std::fprintf(stderr, "[refine] correction tau %.3e ktol %.3e\n", tau_k, kt_k);
+      if (S.prm.prec == Prec::F64) correction<double>(ctx, S, Z, rf, tau_k, kt_k, Zpm, np, nm, st);
+      else correction<float>(ctx, S, Z, rf, tau_k, kt_k, Zpm, np, nm, st);
       // Each of Z+ and Z- is a PSD factor: compressing it alone to the
       // eigenvalues of Z+- Z+-^T above a quarter of Algorithm 2's own threshold
       // (eta_s max|lambda(P)|, with max|lambda(P)| ~ ||Z Z^T||_2) changes

@@ -18,7 +18,7 @@ namespace mpcare {
 // accuracy), H = T M' T^T, H = Q Lambda Q^T, J+- = {lambda >= eta} / {lambda <= -eta},
 // C+ = U Q+ Lambda+^(1/2), C- = U Q- (-Lambda-)^(1/2), ||R||_F = ||Lambda||_2.
 void residual_factor(Ctx* ctx, const SellOp& A64, const double* B, int m, const double* Ct, int p, const double* Z,
-                     int64_t ldz, int r, double eta_r_rel, ResidualFactor& out) {
+                     int64_t ldz, int r, double eta_r_rel, ResidualFactor& out, double drop_fro) {
   const int64_t n = A64.n;
   const int64_t ld = pad_ld(n);
   const int q = 2 * r + p;
@@ -73,7 +73,23 @@ void residual_factor(Ctx* ctx, const SellOp& A64, const double* B, int m, const 
   }
   out.res_fro = std::sqrt(ss);
   out.lam_max = lmax;
-  const double eta = eta_r_rel * lmax;
+  double eta = eta_r_rel * lmax;
+  if (drop_fro > 0.0) {
+    // the largest magnitude c such that all eigenvalues of magnitude <= c
+    // together stay within drop_fro in the Frobenius norm
+    std::vector<double> mag(lam.size());
+    for (size_t i = 0; i < lam.size(); ++i) mag[i] = std::fabs(lam[i]);
+    std::sort(mag.begin(), mag.end());
+    double acc = 0.0, cut = 0.0;
+    for (size_t i = 0; i < mag.size(); ++i) {
+      acc += mag[i] * mag[i];
+      if (acc > drop_fro * drop_fro) break;
+      // ties: a magnitude is dropped only with every eigenvalue equal to it
+      if (i + 1 == mag.size() || mag[i + 1] > mag[i]) cut = mag[i];
+    }
+    // eigenvalues strictly above the cut are kept: nudge eta just past it
+    if (cut > 0.0) eta = std::max(eta, std::nextafter(cut, INFINITY));
+  }
   std::vector<int> selp, selm;
   std::vector<double> scp, scm;
   for (int i = k - 1; i >= 0; --i) {

@@ -15,9 +15,12 @@ struct ResidualFactor {
 };
 
 // Algorithm 1.  A64: FP64 operator; B (n x m) and Ct = C^T (n x p) FP64 with
-// leading dimension pad_ld(n); Z: n x r (ldz).
+// leading dimension pad_ld(n); Z: n x r (ldz).  Eigenvalues of H below
+// eta_r_rel max|lambda(H)| in magnitude are dropped; with drop_fro > 0 so are
+// the smallest ones whose joint Frobenius norm is at most drop_fro.
 void residual_factor(Ctx* ctx, const SellOp& A64, const double* B, int m, const double* Ct, int p,
-                     const double* Z, int64_t ldz, int r, double eta_r_rel, ResidualFactor& out);
+                     const double* Z, int64_t ldz, int r, double eta_r_rel, ResidualFactor& out,
+                     double drop_fro = 0.0);
 
 // Algorithm 2 for a general signature: Z Z^T = positive part of G N G^T
 // above eta_s_rel * max|lambda(P)|.  Output Z: n x *r (ld pad_ld(n)).

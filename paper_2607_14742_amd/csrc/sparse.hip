@@ -2,6 +2,8 @@
 // and the launcher of the sparse-product kernel template.
 #include "sparse.hpp"
 
+#include <algorithm>
+
 #include <hipcub/hipcub.hpp>
 
 namespace mpcare {
@@ -133,6 +135,25 @@ __global__ void k_sumsq(const double* __restrict__ v, int64_t n, double* __restr
   block_reduce_to<1>(vv, [&](int, double val) { part[blockIdx.x] = val; });
 }
 
+// largest absolute row sum, one partial maximum per block (blockDim 256)
+__global__ void __launch_bounds__(256) k_rowabs_max(const int32_t* __restrict__ rp, const double* __restrict__ val,
+                                                    int64_t n, double* __restrict__ part) {
+  double mx = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) s += fabs(val[e]);
+    mx = fmax(mx, s);
+  }
+  __shared__ double sh[256];
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
 template <typename T>
 static void exclusive_scan(Ctx* ctx, const T* in, T* out, int64_t count) {
   size_t tmp = 0;
@@ -228,6 +249,11 @@ void build_sell(Ctx* ctx, const care_csr* A, Prec prec, SellOp& op) {
     double s = 0;
     for (double v : h) s += v;
     op.frob = std::sqrt(s);
+    // ||A||_inf (row_ptr was validated above)
+    hipLaunchKernelGGL(k_rowabs_max, dim3(nb), dim3(256), 0, st, A->row_ptr, A->val, n, part.get());
+    KERNEL_CHECK();
+    d2h(ctx, h.data(), part.get(), nb * sizeof(double));
+    op.norm_inf = *std::max_element(h.begin(), h.end());
   }
   ctx->sync();
 }

@@ -33,6 +33,7 @@ struct SellOp {
   DBuf<uint8_t> vals;              // width_total * 64 * val_bytes
   DBuf<uint8_t> diag;              // n * vec_bytes
   double frob = 0.0;               // ||A||_F (FP64)
+  double norm_inf = 0.0;           // ||A||_inf = max_i sum_j |a_ij| (FP64; 0 for a dense operator)
   // Dense operator (dense_op.hip): A^T held as an n x n column-major matrix
   // (leading dimension n) in the operator precision; shifted solves use LU
   // factorisations of A^T + p I cached per real shift.

@@ -54,6 +54,18 @@ def test_struct_layouts_match_header_order():
 
 
 @needs_lib
+def test_struct_sizes_match_the_compiled_library():
+    from paper_2607_14742_amd import _lib as L
+    lib = L.load()
+    sizes = (C.c_int64 * 6)()
+    assert lib.care_struct_sizes(sizes, 6) == L.CARE_OK
+    mine = [C.sizeof(t) for t in (L.care_csr, L.care_shift, L.care_opts, L.care_stats, L.care_instance,
+                                  L.care_instance_result)]
+    assert list(sizes) == mine
+    assert lib.care_struct_sizes(sizes, 7) == L.CARE_ERR_ARG
+
+
+@needs_lib
 def test_opts_defaults_follow_the_paper():
     from paper_2607_14742_amd import _lib as L
     lib = L.load()
@@ -64,6 +76,7 @@ def test_opts_defaults_follow_the_paper():
     assert o.eta_r_rel == 1e-4
     assert abs(o.eta_s_rel - 10 * 2.0 ** -53) < 1e-30
     assert o.stagnation == 0.999
+    assert o.tau_L0 == 0.0 and o.refine_forcing == 0.1
 
 
 @needs_lib
