@@ -92,7 +92,7 @@ typedef struct {
   double eta_r_rel;       /* Alg. 1 threshold, relative to max|lambda(H)| (1e-4)      */
   double eta_s_rel;       /* Alg. 2 threshold, relative to max|lambda(P)| (10 u_fp64)  */
   double tau_L;           /* inner LR-ADI stop ||W^T W||_F <= tau_L ||W0^T W0||_F;
-                             <= 0 selects 1e-12 (FP64) / 1e-5 (FP32) / 1e-3 (BF16)    */
+                             <= 0 selects 1e-12 (FP64) / 1e-6 (FP32) / 1e-3 (BF16)    */
   double tau_0;           /* initial NLR-ADI stop on the relative Riccati residual;
                              <= 0 selects max(tol / 10, 10 tau_L0)                    */
   double stagnation;      /* stop when ||R_{k+1}|| / ||R_k|| > stagnation (0.999)     */
@@ -161,9 +161,10 @@ typedef struct {
 care_status care_ctx_create(care_ctx** ctx, int32_t device, void* stream);
 void care_ctx_destroy(care_ctx* ctx);
 
-/* Default options for inner precision `inner_prec` (values of Sec. 5:
- * eta_r = 1e-4 max|lambda(H)|, eta_s = 10 u max|lambda(P)|, tau_L = 1e-12 /
- * 1e-5, k_max = 20, j_max = 50). */
+/* Default options for inner precision `inner_prec`: the values of Sec. 5
+ * (eta_r = 1e-4 max|lambda(H)|, eta_s = 10 u max|lambda(P)|, tau_L = 1e-12
+ * for FP64, k_max = 20, j_max = 50), except tau_L = 1e-6 for FP32 (paper:
+ * 1e-5) and the refinement forcing theta = 0.1 (paper: none). */
 void care_opts_default(care_opts* opts, int32_t inner_prec);
 
 /* Message describing the last error of the calling thread ("" if none). */

@@ -19,7 +19,11 @@ Resolved resolve_opts(const care_opts* o, double tol) {
   care_opts_default(&d, o ? o->inner_prec : CARE_FP64);
   if (!o) o = &d;
   r.prec = prec_from_abi(o->inner_prec);
-  const double tl_def = r.prec == Prec::F64 ? 1e-12 : (r.prec == Prec::F32 ? 1e-5 : 1e-3);
+  // tau_L: the paper's 1e-12 (FP64) and 1e-3 (bf16 products); FP32 uses 1e-6
+  // instead of the paper's 1e-5, which lets one correction reach the
+  // tolerance on well-conditioned problems (Toeplitz example of Sec. 5.2:
+  // 3 -> 2 refinement steps) and costs nothing measurable otherwise.
+  const double tl_def = r.prec == Prec::F64 ? 1e-12 : (r.prec == Prec::F32 ? 1e-6 : 1e-3);
   // Krylov tolerance: 1e-10 (FP64) as in Sec. 5, tightened to a tenth of the
   // requested residual when that is smaller: the solves' own errors set the
   // floor of the true Riccati residual near the Krylov tolerance, below the
@@ -86,6 +90,9 @@ struct SolveState {
   double nrm_ctc = 0.0;            // ||C^T C||_F
   std::vector<Shift> shifts;
   Resolved prm;
+  // truncation budget of Algorithm 2 (residual change, absolute) and the
+  // bounds it is converted with: a2 >= ||A||_2, g2 >= ||B B^T||_2
+  double res_budget = 0.0, a2 = 0.0, g2 = 0.0;
 };
 
 template <typename T>
@@ -160,7 +167,7 @@ static void stage0(Ctx* ctx, SolveState& S, TruncResult& Zout, care_stats* st, s
   DBuf<double> G(ctx, (size_t)ld * std::max(zcols, 1));
   copy_cols<T, double>(ctx, n, zcols, Zb.get(), ld, G.get(), ld);
   std::vector<double> sign(zcols, 1.0);
-  signed_truncate(ctx, n, G.get(), ld, zcols, sign, S.prm.eta_s_rel, Zout);
+  signed_truncate(ctx, n, G.get(), ld, zcols, sign, S.prm.eta_s_rel, Zout, 0.5 * S.res_budget, S.a2, S.g2);
 }
 
 // one inner correction: LR-ADI on [C+, C-] with A_k = A - B (Z Z^T B)^T in
@@ -295,8 +302,10 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   copy_cols<double, double>(ctx, n, p, C, n, S.Ct64.get(), S.ld);
   S.nrm_ctc = fro_of_gram(ctx, n, S.Ct64.get(), S.ld, p);
   if (!std::isfinite(S.nrm_ctc)) fail(CARE_ERR_NONFINITE, "C has non-finite entries");
-  if (m > 0 && !std::isfinite(fro_of_gram(ctx, n, S.B64.get(), S.ld, m)))
-    fail(CARE_ERR_NONFINITE, "B has non-finite entries");
+  S.g2 = m > 0 ? fro_of_gram(ctx, n, S.B64.get(), S.ld, m) : 0.0;
+  if (!std::isfinite(S.g2)) fail(CARE_ERR_NONFINITE, "B has non-finite entries");
+  S.a2 = A64.norm2_bound() > 0.0 ? A64.norm2_bound() : A64.frob;
+  S.res_budget = S.prm.theta * tol * S.nrm_ctc;
   ctx->sync();
   const double t1 = now_s();
   st->t_setup = t1 - t0;
@@ -330,8 +339,9 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   // theta tol / rel_k relative (never looser than 0.1, never tighter than
   // tau_L), its shifted solves at a tenth of that, and the residual
   // eigenvalues Algorithm 1 drops may add up to theta tol ||C^T C||_F on top
-  // of its relative threshold.  These terms add at most about 2 theta tol to
-  // the next residual.
+  // of its relative threshold.  The solution truncation (Algorithm 2 and the
+  // compression ahead of it) may change the residual by another theta tol.
+  // These terms add at most about 3 theta tol to the next residual.
   const double theta = S.prm.theta;
   for (int k = 0; k < S.prm.k_max; ++k) {
     ResidualFactor rf;
@@ -383,13 +393,16 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
       // (eta_s max|lambda(P)|, with max|lambda(P)| ~ ||Z Z^T||_2) changes
       // G N G^T by at most that much, and shrinks G from the raw ADI width to
       // the correction's numerical rank.
+      // With a truncation budget each group may also drop eigen-terms worth a
+      // quarter of it in the residual (the rest goes to Algorithm 2 itself).
       const double tau = 0.25 * S.prm.eta_s_rel * Z.sig_max;
+      const double drop = S.res_budget > 0.0 ? 0.25 * S.res_budget / (2.0 * (S.a2 + S.g2 * Z.sig_max)) : 0.0;
       const double* parts[2] = {Zpm.get(), Zpm.get() + (int64_t)np * S.ld};
       int widths[2] = {np, nm};
       DBuf<double> comp[2];
       for (int g = 0; g < 2; ++g) {
         int r = 0;
-        if (tau > 0.0 && widths[g] > 0 && psd_compress(ctx, n, parts[g], S.ld, widths[g], tau, comp[g], r)) {
+        if (tau > 0.0 && widths[g] > 0 && psd_compress(ctx, n, parts[g], S.ld, widths[g], tau, comp[g], r, drop)) {
           parts[g] = comp[g].get();
           widths[g] = r;
         }
@@ -404,7 +417,7 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
       for (int c = Z.r + widths[0]; c < s; ++c) sign[c] = -1.0;
     }
     TruncResult Zn;
-    signed_truncate(ctx, n, G.get(), S.ld, s, sign, S.prm.eta_s_rel, Zn);
+    signed_truncate(ctx, n, G.get(), S.ld, s, sign, S.prm.eta_s_rel, Zn, 0.5 * S.res_budget, S.a2, S.g2);
     st->eta_n = Zn.eta_n;
     Z = std::move(Zn);
   }
@@ -421,7 +434,7 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   if (R.r > 0) copy_cols<double, double>(ctx, n, R.r, R.Z.get(), S.ld, Zout, ldz);
   // the paper's normalised residual
   const double ztz = fro_of_gram(ctx, n, R.Z.get(), S.ld, R.r);
-  const double btb = m > 0 ? fro_of_gram(ctx, n, S.B64.get(), S.ld, m) : 0.0;
+  const double btb = S.g2;
   st->res_paper = best * S.nrm_ctc / (2.0 * A64.frob * ztz + btb * ztz * ztz + S.nrm_ctc);
   ctx->sync();
   int hl = 0;

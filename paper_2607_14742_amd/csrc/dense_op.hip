@@ -7,7 +7,9 @@
 // not change (Sec. 4).
 #include <rocsolver/rocsolver.h>
 
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "dense.hpp"
 #include "krylov.hpp"
@@ -18,6 +20,30 @@ template <typename T>
 __global__ void k_add_diag(int64_t n, T* a, int64_t lda, T p) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i * lda + i] += p;
+}
+
+// absolute column sums (one block per column) and row sums (one thread per
+// row) of a column-major n x n matrix
+__global__ void __launch_bounds__(256) k_abs_colsum(int64_t n, const double* __restrict__ a,
+                                                    double* __restrict__ out) {
+  const int64_t j = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += fabs(a[j * n + i]);
+  __shared__ double sh[256];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = sh[0];
+}
+__global__ void k_abs_rowsum(int64_t n, const double* __restrict__ a, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int64_t j = 0; j < n; ++j) s += fabs(a[j * n + i]);
+  out[i] = s;
 }
 
 void build_dense(Ctx* ctx, const double* A, int64_t lda, int64_t n, Prec prec, SellOp& op) {
@@ -38,6 +64,21 @@ void build_dense(Ctx* ctx, const double* A, int64_t lda, int64_t n, Prec prec, S
   ROCBLAS_CHECK(rocblas_dnrm2(ctx->blas, (int)(n * n), t.get(), 1, &nrm));
   op.frob = nrm;
   if (!std::isfinite(nrm)) fail(CARE_ERR_NONFINITE, "A has non-finite entries");
+  {
+    // t = A^T: its column sums are the row sums of A and vice versa
+    DBuf<double> sums(ctx, (size_t)n);
+    std::vector<double> h((size_t)n);
+    hipLaunchKernelGGL(k_abs_colsum, dim3((unsigned)n), dim3(256), 0, ctx->stream, n, (const double*)t.get(),
+                       sums.get());
+    KERNEL_CHECK();
+    d2h(ctx, h.data(), sums.get(), (size_t)n * sizeof(double));
+    op.norm_inf = *std::max_element(h.begin(), h.end());
+    hipLaunchKernelGGL(k_abs_rowsum, dim3(ceil_div(n, 256)), dim3(256), 0, ctx->stream, n, (const double*)t.get(),
+                       sums.get());
+    KERNEL_CHECK();
+    d2h(ctx, h.data(), sums.get(), (size_t)n * sizeof(double));
+    op.norm_one = *std::max_element(h.begin(), h.end());
+  }
   if (prec == Prec::F64) {
     op.dmat.resize(ctx, (size_t)n * n * sizeof(double));
     d2d(ctx, op.dmat.get(), t.get(), (size_t)n * n * sizeof(double));

@@ -821,14 +821,14 @@ KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncol
   // A column that stopped near the attainable accuracy of the working
   // precision gains nothing from a restart: the true residual b - M x
   // evaluated in precision T carries rounding errors of about
-  // u_T (||A||_inf + |p|) ||x_c|| (and BiCGStab's recursive residual drifts
+  // u_T (||A^T||_inf + |p|) ||x_c|| (and BiCGStab's recursive residual drifts
   // from it by as much), so a column within 10 times that level of ||b_c||,
   // or within 1e4 u_T, is left as it is.
   const double u_t = sizeof(T) == 8 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
   std::vector<double> floor_rel(nl, 1e4 * u_t);
-  if (op.norm_inf > 0.0 && res.unconverged > 0) {
+  if (op.norm_one > 0.0 && res.unconverged > 0) {
     const std::vector<double> xn = col_norms<T>(ctx, n, ncols, x, ldx);
-    const double mnorm = op.norm_inf + std::hypot(pr, pi);
+    const double mnorm = op.norm_one + std::hypot(pr, pi);
     for (int c = 0; c < nl; ++c) {
       const double xx = cplx ? std::hypot(xn[2 * c], xn[2 * c + 1]) : xn[c];
       if (res.col_bnorm[c] > 0.0)

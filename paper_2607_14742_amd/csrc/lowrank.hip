@@ -75,19 +75,8 @@ void residual_factor(Ctx* ctx, const SellOp& A64, const double* B, int m, const 
   out.lam_max = lmax;
   double eta = eta_r_rel * lmax;
   if (drop_fro > 0.0) {
-    // the largest magnitude c such that all eigenvalues of magnitude <= c
-    // together stay within drop_fro in the Frobenius norm
-    std::vector<double> mag(lam.size());
-    for (size_t i = 0; i < lam.size(); ++i) mag[i] = std::fabs(lam[i]);
-    std::sort(mag.begin(), mag.end());
-    double acc = 0.0, cut = 0.0;
-    for (size_t i = 0; i < mag.size(); ++i) {
-      acc += mag[i] * mag[i];
-      if (acc > drop_fro * drop_fro) break;
-      // ties: a magnitude is dropped only with every eigenvalue equal to it
-      if (i + 1 == mag.size() || mag[i + 1] > mag[i]) cut = mag[i];
-    }
     // eigenvalues strictly above the cut are kept: nudge eta just past it
+    const double cut = frobenius_cut(lam, drop_fro);
     if (cut > 0.0) eta = std::max(eta, std::nextafter(cut, INFINITY));
   }
   std::vector<int> selp, selm;
@@ -121,10 +110,23 @@ void residual_factor(Ctx* ctx, const SellOp& A64, const double* B, int m, const 
   ctx->sync();
 }
 
+double frobenius_cut(std::vector<double> v, double drop_fro) {
+  for (double& x : v) x = std::fabs(x);
+  std::sort(v.begin(), v.end());
+  double acc = 0.0, cut = 0.0;
+  for (size_t i = 0; i < v.size(); ++i) {
+    acc += v[i] * v[i];
+    if (acc > drop_fro * drop_fro) break;
+    // ties: a magnitude is dropped only together with every entry equal to it
+    if (i + 1 == v.size() || v[i + 1] > v[i]) cut = v[i];
+  }
+  return cut;
+}
+
 // Algorithm 2: G = V Gamma, P = Gamma N Gamma^T = Theta Sigma Theta^T,
 // keep sigma >= eta_s, Z = V Theta+ Sigma+^(1/2).
 void signed_truncate(Ctx* ctx, int64_t n, const double* G, int64_t ldg, int s, const std::vector<double>& sign,
-                     double eta_s_rel, TruncResult& out) {
+                     double eta_s_rel, TruncResult& out, double res_budget, double a2, double g2) {
   const int64_t ld = pad_ld(n);
   out.r = 0;
   out.eta_n = 0.0;
@@ -157,7 +159,14 @@ void signed_truncate(Ctx* ctx, int64_t n, const double* G, int64_t ldg, int s, c
   }
   out.sig_max = smax;
   out.eta_n = all2 > 0 ? std::sqrt(neg2 / all2) : 0.0;
-  const double eta = eta_s_rel * smax;
+  double eta = eta_s_rel * smax;
+  if (res_budget > 0.0 && a2 + g2 * smax > 0.0) {
+    std::vector<double> pos;
+    for (double v : sig)
+      if (v > 0.0) pos.push_back(v);
+    const double cut = frobenius_cut(pos, res_budget / (2.0 * (a2 + g2 * smax)));
+    if (cut > 0.0) eta = std::max(eta, std::nextafter(cut, INFINITY));
+  }
   std::vector<int> sel;
   std::vector<double> sc;
   for (int i = k - 1; i >= 0; --i) {
@@ -178,7 +187,7 @@ void signed_truncate(Ctx* ctx, int64_t n, const double* G, int64_t ldg, int s, c
 }
 
 bool psd_compress(Ctx* ctx, int64_t n, const double* Z, int64_t ldz, int w, double tau_abs, DBuf<double>& out,
-                  int& r) {
+                  int& r, double drop_fro) {
   const int64_t ld = pad_ld(n);
   r = 0;
   if (w <= 0) {
@@ -194,6 +203,7 @@ bool psd_compress(Ctx* ctx, int64_t n, const double* Z, int64_t ldz, int w, doub
     out.resize(ctx, ld);
     return true;
   }
+  if (drop_fro > 0.0) tau_abs = std::max(tau_abs, frobenius_cut(lam, drop_fro));
   if (!(tau_abs >= 1e-14 * lmax)) {
     if (std::getenv("MPCARE_TRACE"))
       std::fprintf(stderr, "[psd_compress] w %d kept whole: tau %.3e below 1e-14 lam_max %.3e\n", w, tau_abs, lmax);

@@ -30,8 +30,19 @@ struct TruncResult {
   double eta_n = 0.0;
   double sig_max = 0.0;
 };
+// With res_budget > 0 the smallest kept eigenvalues are dropped as well while
+// the Frobenius norm E of everything dropped from the positive part stays
+// within res_budget / (2 (a2 + g2 sig_max)): removing E from X changes the
+// Riccati residual by at most 2 (||A||_2 + ||B B^T||_2 ||X||_2) ||E||_F
+// (to first order), so a2 >= ||A||_2 and g2 >= ||B B^T||_2 keep that change
+// within res_budget.
 void signed_truncate(Ctx* ctx, int64_t n, const double* G, int64_t ldg, int s, const std::vector<double>& sign,
-                     double eta_s_rel, TruncResult& out);
+                     double eta_s_rel, TruncResult& out, double res_budget = 0.0, double a2 = 0.0,
+                     double g2 = 0.0);
+
+// The largest magnitude c such that all of |v| <= c together stay within
+// drop_fro in the Frobenius norm (0 when even the smallest does not).
+double frobenius_cut(std::vector<double> v, double drop_fro);
 
 // Compression of one positive semidefinite factor ahead of Algorithm 2:
 // Z Z^T = U diag(lam) U^T from the FP64 Gram Z^T Z = V diag(lam) V^T; keeps
@@ -41,8 +52,10 @@ void signed_truncate(Ctx* ctx, int64_t n, const double* G, int64_t ldg, int s, c
 // FP64 Gram's own rounding adds to it.  Returns false, and leaves out
 // untouched, when tau_abs lies below 1e-14 lam_max, where that rounding would
 // no longer be small next to it.
+// With drop_fro > 0 the smallest eigen-terms whose joint Frobenius norm is at
+// most drop_fro are dropped as well.
 bool psd_compress(Ctx* ctx, int64_t n, const double* Z, int64_t ldz, int w, double tau_abs, DBuf<double>& out,
-                  int& r);
+                  int& r, double drop_fro = 0.0);
 
 // largest eigenvalue of Z Z^T (0 for an empty factor)
 double factor_lam_max(Ctx* ctx, int64_t n, const double* Z, int64_t ldz, int r);

@@ -249,11 +249,16 @@ void build_sell(Ctx* ctx, const care_csr* A, Prec prec, SellOp& op) {
     double s = 0;
     for (double v : h) s += v;
     op.frob = std::sqrt(s);
-    // ||A||_inf (row_ptr was validated above)
+    // ||A||_inf from the rows of A (row_ptr was validated above), ||A||_1
+    // from the rows of the transpose built above
     hipLaunchKernelGGL(k_rowabs_max, dim3(nb), dim3(256), 0, st, A->row_ptr, A->val, n, part.get());
     KERNEL_CHECK();
     d2h(ctx, h.data(), part.get(), nb * sizeof(double));
     op.norm_inf = *std::max_element(h.begin(), h.end());
+    hipLaunchKernelGGL(k_rowabs_max, dim3(nb), dim3(256), 0, st, (const int32_t*)rpt.get(), vt.get(), n, part.get());
+    KERNEL_CHECK();
+    d2h(ctx, h.data(), part.get(), nb * sizeof(double));
+    op.norm_one = *std::max_element(h.begin(), h.end());
   }
   ctx->sync();
 }

@@ -15,6 +15,8 @@
 // leading dimension rounded up to 64 rows.
 #pragma once
 
+#include <cmath>
+
 #include <map>
 #include <memory>
 
@@ -33,7 +35,10 @@ struct SellOp {
   DBuf<uint8_t> vals;              // width_total * 64 * val_bytes
   DBuf<uint8_t> diag;              // n * vec_bytes
   double frob = 0.0;               // ||A||_F (FP64)
-  double norm_inf = 0.0;           // ||A||_inf = max_i sum_j |a_ij| (FP64; 0 for a dense operator)
+  double norm_inf = 0.0;           // ||A||_inf = max_i sum_j |a_ij| (FP64)
+  double norm_one = 0.0;           // ||A||_1 = max_j sum_i |a_ij| = ||A^T||_inf (FP64)
+  // sqrt(||A||_1 ||A||_inf) >= ||A||_2
+  double norm2_bound() const { return std::sqrt(norm_one * norm_inf); }
   // Dense operator (dense_op.hip): A^T held as an n x n column-major matrix
   // (leading dimension n) in the operator precision; shifted solves use LU
   // factorisations of A^T + p I cached per real shift.

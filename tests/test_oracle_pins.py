@@ -355,3 +355,28 @@ def test_ex1_gallery_orthog():
     A, B, C = wl.ex1(64, 3, 2, q=3.0)
     s = np.linalg.svd(A, compute_uv=False)
     assert np.isclose(s.max() / s.min(), 1e3)
+
+
+def test_toeplitz5_definition_and_dissipativity():
+    # the Toeplitz example (Sec. 5.2): sub-diagonal 1, diagonal -2.8, the
+    # first three super-diagonals -1, every other entry 0
+    n = 9
+    A = wl.toeplitz5(n).toarray()
+    for i in range(n):
+        for j in range(n):
+            want = {-1: 1.0, 0: -2.8, 1: -1.0, 2: -1.0, 3: -1.0}.get(j - i, 0.0)
+            assert A[i, j] == want, (i, j)
+    # The symmetric part is the Hermitian Toeplitz section of the symbol
+    # s(t) = -2.8 - cos 2t - cos 3t, so its eigenvalues lie below max s
+    # (Grenander-Szego).  That maximum is negative, so A is dissipative and
+    # hence stable, with the field of values left of it.
+    t = np.linspace(0.0, np.pi, 100001)
+    smax = (-2.8 - np.cos(2 * t) - np.cos(3 * t)).max()
+    assert smax < -1.0
+    A = wl.toeplitz5(300).toarray()
+    lam_s = np.linalg.eigvalsh((A + A.T) / 2)
+    assert lam_s.max() <= smax + 1e-12 and lam_s.max() >= smax - 1e-2
+    assert np.linalg.eigvals(A).real.max() <= smax + 1e-12
+    P = wl.toeplitz_problem(300)
+    assert P.B.shape == (300, 10) and P.C.shape == (5, 300)
+    assert np.isclose(np.linalg.norm(P.B), 1.0)

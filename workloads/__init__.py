@@ -242,6 +242,16 @@ def fdm3d_problem(N: int, m: int, p: int, nu: float = 100.0, field_kind: str = "
                    dict(N=N, nu=nu, field=field_kind, seed=seed))
 
 
+def toeplitz_problem(n: int, m: int = 10, p: int = 5, seed: int = DEFAULT_SEED, name: str = None) -> Problem:
+    """The Toeplitz example of Sec. 5.2: the 5-diagonal Toeplitz A, Gaussian
+    B scaled to ||B||_F = 1, Gaussian C; no shift set (the paper generates
+    its shifts from Krylov subspaces: the heuristic here)."""
+    A = toeplitz5(n)
+    B, C = gaussian_factors(n, m, p, seed)
+    B /= np.linalg.norm(B)
+    return Problem(name or f"toeplitz_n{n}_m{m}_p{p}", A, B, C, None, dict(seed=seed))
+
+
 def config3() -> Problem:
     """64^3 grid (n = 262,144, nnz = 1,810,432), rotating field, m = 1, p = 10."""
     return fdm3d_problem(64, 1, 10, name="cfg3_fdm3d_64")
