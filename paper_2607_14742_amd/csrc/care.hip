@@ -343,10 +343,21 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   // compression ahead of it) may change the residual by another theta tol.
   // These terms add at most about 3 theta tol to the next residual.
   const double theta = S.prm.theta;
+  // MPCARE_TRACE: wall time of each phase of a refinement step
+  const bool trace = std::getenv("MPCARE_TRACE") != nullptr;
+  double tmark_last = now_s();
+  auto tmark = [&](const char* what) {
+    if (!trace) return;
+    ctx->sync();
+    const double t = now_s();
+    std::fprintf(stderr, "[refine] phase %s %.1f ms\n", what, 1e3 * (t - tmark_last));
+    tmark_last = t;
+  };
   for (int k = 0; k < S.prm.k_max; ++k) {
     ResidualFactor rf;
     residual_factor(ctx, A64, S.B64.get(), m, S.Ct64.get(), p, Z.Z.get(), S.ld, Z.r, S.prm.eta_r_rel, rf,
-                    theta * tol * S.nrm_ctc);
+                    theta * tol * S.nrm_ctc, &Z);
+    tmark("algorithm 1");
     st->iter_outer += 1;
     const double rel = rf.res_fro / S.nrm_ctc;
     if (!std::isfinite(rel)) fail(CARE_ERR_NONFINITE, "Riccati residual is not finite");
@@ -388,6 +399,7 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
       if (std::getenv("MPCARE_TRACE")) std::fprintf(stderr, "[refine] correction tau %.3e ktol %.3e\n", tau_k, kt_k);
       if (S.prm.prec == Prec::F64) correction<double>(ctx, S, Z, rf, tau_k, kt_k, Zpm, np, nm, st);
       else correction<float>(ctx, S, Z, rf, tau_k, kt_k, Zpm, np, nm, st);
+      tmark("correction");
       // Each of Z+ and Z- is a PSD factor: compressing it alone to the
       // eigenvalues of Z+- Z+-^T above a quarter of Algorithm 2's own threshold
       // (eta_s max|lambda(P)|, with max|lambda(P)| ~ ||Z Z^T||_2) changes
@@ -407,17 +419,24 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
           widths[g] = r;
         }
       }
-      // G = [Z, Z+, Z-], Algorithm 2
-      s = Z.r + widths[0] + widths[1];
+      // G = [Z, Z+, Z-], Algorithm 2.  When Z carries its orthonormal basis
+      // only [Z+, Z-] is assembled: the orthogonalisation starts from it.
+      const int lead = Z.has_q ? 0 : Z.r;
+      s = lead + widths[0] + widths[1];
       G.resize(ctx, (size_t)S.ld * std::max(s, 1));
-      d2d(ctx, G.get(), Z.Z.get(), (size_t)S.ld * Z.r * sizeof(double));
-      d2d(ctx, G.get() + (int64_t)Z.r * S.ld, parts[0], (size_t)S.ld * widths[0] * sizeof(double));
-      d2d(ctx, G.get() + (int64_t)(Z.r + widths[0]) * S.ld, parts[1], (size_t)S.ld * widths[1] * sizeof(double));
+      if (lead) d2d(ctx, G.get(), Z.Z.get(), (size_t)S.ld * lead * sizeof(double));
+      d2d(ctx, G.get() + (int64_t)lead * S.ld, parts[0], (size_t)S.ld * widths[0] * sizeof(double));
+      d2d(ctx, G.get() + (int64_t)(lead + widths[0]) * S.ld, parts[1], (size_t)S.ld * widths[1] * sizeof(double));
       sign.assign(s, 1.0);
-      for (int c = Z.r + widths[0]; c < s; ++c) sign[c] = -1.0;
+      for (int c = lead + widths[0]; c < s; ++c) sign[c] = -1.0;
     }
+    tmark("compression");
     TruncResult Zn;
-    signed_truncate(ctx, n, G.get(), S.ld, s, sign, S.prm.eta_s_rel, Zn, 0.5 * S.res_budget, S.a2, S.g2);
+    if (Z.has_q)
+      signed_truncate_basis(ctx, n, Z, G.get(), S.ld, s, sign, S.prm.eta_s_rel, Zn, 0.5 * S.res_budget, S.a2, S.g2);
+    else
+      signed_truncate(ctx, n, G.get(), S.ld, s, sign, S.prm.eta_s_rel, Zn, 0.5 * S.res_budget, S.a2, S.g2);
+    tmark("algorithm 2");
     st->eta_n = Zn.eta_n;
     Z = std::move(Zn);
   }

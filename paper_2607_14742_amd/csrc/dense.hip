@@ -471,15 +471,45 @@ static int polish(Ctx* ctx, int64_t n, double* U, int64_t ldu, int k, bool trace
   return kk;
 }
 
+// out[j] = sum_i (s_i G_ij s_j)^2, one block per column j
+__global__ void __launch_bounds__(256) k_scaled_colsq(const double* __restrict__ G, int64_t ldg, int q,
+                                                      const double* __restrict__ s, double* __restrict__ out) {
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < q; i += 256) {
+    const double v = s[i] * G[(int64_t)j * ldg + i] * s[j];
+    acc += v * v;
+  }
+  __shared__ double sh[256];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = sh[0];
+}
+
 void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out) {
+  rr_orth(ctx, n, F, ldf, q, out, nullptr, 0, 0);
+}
+
+void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out, const double* U0, int64_t ldu0,
+             int k0) {
   const double u = 1.1102230246251565e-16;
   const bool trace = std::getenv("MPCARE_TRACE") != nullptr;
   const int64_t ld = pad_ld(n);
+  if (!U0) k0 = 0;
+  const int kcap = k0 + q;           // rank bound of [U0, F]
   out.ldu = ld;
   out.k = 0;
-  out.U.resize(ctx, (size_t)ld * std::max(q, 1));
-  out.T.resize(ctx, (size_t)std::max(q, 1) * std::max(q, 1));
-  if (q <= 0) return;
+  out.U.resize(ctx, (size_t)ld * std::max(kcap, 1));
+  out.T.resize(ctx, (size_t)std::max(kcap, 1) * std::max(q, 1));
+  if (k0 > 0) copy_cols<double, double>(ctx, n, k0, U0, ldu0, out.U.get(), ld);
+  if (q <= 0) {
+    out.k = k0;
+    return;
+  }
 
   // column norms of F -> s = 1 / ||F_j|| (0 for zero columns)
   DBuf<double> G(ctx, (size_t)q * q);
@@ -498,10 +528,46 @@ void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out
   const double* Ecur = F;
   int64_t lde = ldf;
   const double noise = (64.0 * u) * (64.0 * u) * q;
-  DBuf<double> W(ctx, (size_t)q * q), B(ctx, (size_t)q * q), Tf(ctx, (size_t)q * q), T2(ctx, (size_t)q * q);
+  DBuf<double> W(ctx, (size_t)q * q), B(ctx, (size_t)q * q), Tf(ctx, (size_t)kcap * q), T2(ctx, (size_t)kcap * q);
   std::vector<double> lam;
+  // E = F - U (U^T F), twice; T = U^T F accumulated over both projections
+  auto project = [&]() {
+    gram(ctx, n, out.U.get(), ld, out.k, F, ldf, q, Tf.get(), out.k);
+    copy_cols<double, double>(ctx, n, q, F, ldf, E.get(), ld);
+    tsgemm(ctx, n, out.U.get(), ld, out.k, Tf.get(), out.k, q, -1.0, 1.0, E.get(), ld);
+    gram(ctx, n, out.U.get(), ld, out.k, E.get(), ld, q, T2.get(), out.k);
+    tsgemm(ctx, n, out.U.get(), ld, out.k, T2.get(), out.k, q, -1.0, 1.0, E.get(), ld);
+    const double one = 1.0;
+    ROCBLAS_CHECK(rocblas_dgeam(ctx->blas, rocblas_operation_none, rocblas_operation_none, out.k, q, &one, Tf.get(),
+                                out.k, &one, T2.get(), out.k, out.T.get(), out.k));
+    Ecur = E.get();
+    lde = ld;
+  };
+  if (k0 > 0) {
+    out.k = k0;
+    project();
+  }
+  DBuf<double> csq(ctx, q);
+  std::vector<double> hcsq(q);
   for (int pass = 0; pass < 5; ++pass) {
-    if (pass > 0) gram(ctx, n, Ecur, lde, q, Ecur, lde, q, G.get(), q);
+    if (pass > 0 || k0 > 0) {
+      gram(ctx, n, Ecur, lde, q, Ecur, lde, q, G.get(), q);
+      // the scaled Gram's Frobenius norm bounds its largest eigenvalue: a
+      // remainder at the noise level ends the loop here, as the eigen-
+      // decomposition below would (it selects nothing when lmax <= noise)
+      hipLaunchKernelGGL(k_scaled_colsq, dim3(q), dim3(256), 0, ctx->stream, G.get(), (int64_t)q, q, ds.get(),
+                         csq.get());
+      KERNEL_CHECK();
+      d2h(ctx, hcsq.data(), csq.get(), (size_t)q * sizeof(double));
+      double fro2 = 0.0;
+      for (double v : hcsq) fro2 += v;
+      if (std::sqrt(fro2) <= noise) {
+        if (trace)
+          std::fprintf(stderr, "[rr_orth] n %lld q %d pass %d ||G||_F %.3e at noise: done\n", (long long)n, q, pass,
+                       std::sqrt(fro2));
+        break;
+      }
+    }
     d2d(ctx, W.get(), G.get(), (size_t)q * q * sizeof(double));
     dim3 gs(ceil_div(q, 64), q);
     hipLaunchKernelGGL(k_scale_sym, gs, dim3(64), 0, ctx->stream, W.get(), (int64_t)q, q, ds.get());
@@ -512,7 +578,7 @@ void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out
     std::vector<int> sel;
     std::vector<double> isq;
     for (int i = q - 1; i >= 0; --i)
-      if (lam[i] > thr && out.k + (int)sel.size() < q) {
+      if (lam[i] > thr && out.k + (int)sel.size() < kcap) {
         sel.push_back(i);
         isq.push_back(1.0 / std::sqrt(lam[i]));
       }
@@ -537,21 +603,8 @@ void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out
     const int kept = polish(ctx, n, Unew, ld, kk, trace);
     if (kept == 0) break;
     out.k += kept;
-    // E = F - U (U^T F), twice; Tf = U^T F
-    gram(ctx, n, out.U.get(), ld, out.k, F, ldf, q, Tf.get(), out.k);
-    for (int j = 0; j < q; ++j) d2d(ctx, E.get() + (int64_t)j * ld, F + (int64_t)j * ldf, n * sizeof(double));
-    tsgemm(ctx, n, out.U.get(), ld, out.k, Tf.get(), out.k, q, -1.0, 1.0, E.get(), ld);
-    gram(ctx, n, out.U.get(), ld, out.k, E.get(), ld, q, T2.get(), out.k);
-    tsgemm(ctx, n, out.U.get(), ld, out.k, T2.get(), out.k, q, -1.0, 1.0, E.get(), ld);
-    // Tf += T2 (k x q, ld k): small add through rocBLAS geam-free path
-    {
-      const double one = 1.0;
-      ROCBLAS_CHECK(rocblas_dgeam(ctx->blas, rocblas_operation_none, rocblas_operation_none, out.k, q, &one,
-                                  Tf.get(), out.k, &one, T2.get(), out.k, out.T.get(), out.k));
-    }
-    Ecur = E.get();
-    lde = ld;
-    if (out.k >= q) break;
+    project();
+    if (out.k >= kcap) break;
   }
   if (out.k == 0) return;
   ctx->sync();

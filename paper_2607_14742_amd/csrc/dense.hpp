@@ -51,5 +51,10 @@ struct Orth {
   int k = 0;
 };
 void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out);
+// The same with a known orthonormal basis U0 (n x k0, ld ldu0) of part of
+// the column space: U = [U0, U_new] with U_new orthogonal to U0, and
+// T = U^T F (k x q) for the q columns of F only.
+void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out, const double* U0, int64_t ldu0,
+             int k0);
 
 }  // namespace mpcare

@@ -17,8 +17,33 @@ namespace mpcare {
 // columns in the thin QR.  Then F' = U T (rank-revealing, Householder
 // accuracy), H = T M' T^T, H = Q Lambda Q^T, J+- = {lambda >= eta} / {lambda <= -eta},
 // C+ = U Q+ Lambda+^(1/2), C- = U Q- (-Lambda-)^(1/2), ||R||_F = ||Lambda||_2.
+// T (k x (r + c), ld k) = [[diag(sqrt(sig)), Trest(0:r, :)], [0, Trest(r:k, :)]]
+// for U = [Q, U_new] and a matrix [Q diag(sqrt(sig)), rest]: the coefficients
+// of the leading block are exact, those of the rest come from the
+// orthogonalisation (Trest, k x c, ld k).
+__global__ void k_basis_block(double* __restrict__ T, int k, int r, const double* __restrict__ sq) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i < k && j < r) T[(int64_t)j * k + i] = i == j ? sq[j] : 0.0;
+}
+
+static void basis_coefficients(Ctx* ctx, const TruncResult& Zk, const Orth& o, int c, DBuf<double>& T) {
+  const int k = o.k, r = Zk.r;
+  T.resize(ctx, (size_t)k * std::max(r + c, 1));
+  std::vector<double> sq(r);
+  for (int j = 0; j < r; ++j) sq[j] = std::sqrt(std::max(Zk.sig[j], 0.0));
+  DBuf<double> dsq(ctx, std::max(r, 1));
+  if (r > 0) {
+    h2d(ctx, dsq.get(), sq.data(), r * sizeof(double));
+    hipLaunchKernelGGL(k_basis_block, dim3(ceil_div(k, 64), r), dim3(64), 0, ctx->stream, T.get(), k, r, dsq.get());
+    KERNEL_CHECK();
+  }
+  if (c > 0) copy_cols<double, double>(ctx, k, c, o.T.get(), k, T.get() + (int64_t)r * k, k);
+  ctx->sync();
+}
+
 void residual_factor(Ctx* ctx, const SellOp& A64, const double* B, int m, const double* Ct, int p, const double* Z,
-                     int64_t ldz, int r, double eta_r_rel, ResidualFactor& out, double drop_fro) {
+                     int64_t ldz, int r, double eta_r_rel, ResidualFactor& out, double drop_fro,
+                     const TruncResult* basis) {
   const int64_t n = A64.n;
   const int64_t ld = pad_ld(n);
   const int q = 2 * r + p;
@@ -52,13 +77,25 @@ void residual_factor(Ctx* ctx, const SellOp& A64, const double* B, int m, const 
   for (int i = 0; i < p; ++i) Mh[(size_t)(2 * r + i) * q + (2 * r + i)] = 1.0;
 
   Orth o;
-  rr_orth(ctx, n, F.get(), ld, q, o);
+  DBuf<double> Tb;
+  const double* T = nullptr;
+  if (basis && basis->has_q && basis->r == r && r > 0) {
+    // Z = Q diag(sqrt(sig)) with orthonormal Q: orthogonalise [A^T Z, C^T]
+    // against Q and among themselves only
+    rr_orth(ctx, n, F.get() + (int64_t)r * ld, ld, r + p, o, basis->Q.get(), ld, r);
+    if (o.k == 0) return;
+    basis_coefficients(ctx, *basis, o, r + p, Tb);
+    T = Tb.get();
+  } else {
+    rr_orth(ctx, n, F.get(), ld, q, o);
+    T = o.T.get();
+  }
   const int k = o.k;
   if (k == 0) return;
   DBuf<double> M(ctx, (size_t)q * q), TM(ctx, (size_t)k * q), H(ctx, (size_t)k * k), Hs(ctx, (size_t)k * k);
   h2d(ctx, M.get(), Mh.data(), Mh.size() * sizeof(double));
-  dgemm(ctx, false, false, k, q, q, 1.0, o.T.get(), k, M.get(), q, 0.0, TM.get(), k);
-  dgemm(ctx, false, true, k, k, q, 1.0, TM.get(), k, o.T.get(), k, 0.0, H.get(), k);
+  dgemm(ctx, false, false, k, q, q, 1.0, T, k, M.get(), q, 0.0, TM.get(), k);
+  dgemm(ctx, false, true, k, k, q, 1.0, TM.get(), k, T, k, 0.0, H.get(), k);
   {
     const double half = 0.5;
     ROCBLAS_CHECK(rocblas_dgeam(ctx->blas, rocblas_operation_none, rocblas_operation_transpose, k, k, &half, H.get(),
@@ -125,25 +162,15 @@ double frobenius_cut(std::vector<double> v, double drop_fro) {
 
 // Algorithm 2: G = V Gamma, P = Gamma N Gamma^T = Theta Sigma Theta^T,
 // keep sigma >= eta_s, Z = V Theta+ Sigma+^(1/2).
-void signed_truncate(Ctx* ctx, int64_t n, const double* G, int64_t ldg, int s, const std::vector<double>& sign,
-                     double eta_s_rel, TruncResult& out, double res_budget, double a2, double g2) {
+// the part of Algorithm 2 after the orthogonalisation G = U T (U: o.U, k
+// columns; T: k x s, ld k)
+static void truncate_core(Ctx* ctx, int64_t n, const Orth& o, const double* T, int s, const std::vector<double>& sign,
+                          double eta_s_rel, TruncResult& out, double res_budget, double a2, double g2) {
   const int64_t ld = pad_ld(n);
-  out.r = 0;
-  out.eta_n = 0.0;
-  if (s <= 0) {
-    out.Z.resize(ctx, ld);
-    return;
-  }
-  Orth o;
-  rr_orth(ctx, n, G, ldg, s, o);
   const int k = o.k;
-  if (k == 0) {
-    out.Z.resize(ctx, ld);
-    return;
-  }
   DBuf<double> GN(ctx, (size_t)k * s), P(ctx, (size_t)k * k), Ps(ctx, (size_t)k * k);
-  copy_cols<double, double>(ctx, k, s, o.T.get(), k, GN.get(), k, nullptr, sign.data());
-  dgemm(ctx, false, true, k, k, s, 1.0, GN.get(), k, o.T.get(), k, 0.0, P.get(), k);
+  copy_cols<double, double>(ctx, k, s, T, k, GN.get(), k, nullptr, sign.data());
+  dgemm(ctx, false, true, k, k, s, 1.0, GN.get(), k, T, k, 0.0, P.get(), k);
   {
     const double half = 0.5;
     ROCBLAS_CHECK(rocblas_dgeam(ctx->blas, rocblas_operation_none, rocblas_operation_transpose, k, k, &half, P.get(),
@@ -178,12 +205,65 @@ void signed_truncate(Ctx* ctx, int64_t n, const double* G, int64_t ldg, int s, c
   }
   out.r = (int)sel.size();
   out.Z.resize(ctx, (size_t)ld * std::max(1, out.r));
+  out.Q.resize(ctx, (size_t)ld * std::max(1, out.r));
+  out.sig.resize(out.r);
+  for (int j = 0; j < out.r; ++j) out.sig[j] = sig[sel[j]];
   if (out.r) {
     DBuf<double> coef(ctx, (size_t)k * out.r);
     copy_cols<double, double>(ctx, k, out.r, Ps.get(), k, coef.get(), k, sel.data(), sc.data());
     tsgemm(ctx, n, o.U.get(), o.ldu, k, coef.get(), k, out.r, 1.0, 0.0, out.Z.get(), ld);
+    copy_cols<double, double>(ctx, k, out.r, Ps.get(), k, coef.get(), k, sel.data());
+    tsgemm(ctx, n, o.U.get(), o.ldu, k, coef.get(), k, out.r, 1.0, 0.0, out.Q.get(), ld);
   }
+  out.has_q = true;
   ctx->sync();
+}
+
+void signed_truncate(Ctx* ctx, int64_t n, const double* G, int64_t ldg, int s, const std::vector<double>& sign,
+                     double eta_s_rel, TruncResult& out, double res_budget, double a2, double g2) {
+  const int64_t ld = pad_ld(n);
+  out.r = 0;
+  out.eta_n = 0.0;
+  out.has_q = false;
+  out.sig.clear();
+  if (s <= 0) {
+    out.Z.resize(ctx, ld);
+    return;
+  }
+  Orth o;
+  rr_orth(ctx, n, G, ldg, s, o);
+  if (o.k == 0) {
+    out.Z.resize(ctx, ld);
+    return;
+  }
+  truncate_core(ctx, n, o, o.T.get(), s, sign, eta_s_rel, out, res_budget, a2, g2);
+}
+
+void signed_truncate_basis(Ctx* ctx, int64_t n, const TruncResult& Zk, const double* Grest, int64_t ldg, int s,
+                           const std::vector<double>& sign, double eta_s_rel, TruncResult& out, double res_budget,
+                           double a2, double g2) {
+  if (!Zk.has_q) fail(CARE_ERR_ARG, "signed_truncate_basis needs a factor with its orthonormal basis");
+  const int64_t ld = pad_ld(n);
+  out.r = 0;
+  out.eta_n = 0.0;
+  out.has_q = false;
+  out.sig.clear();
+  const int r = Zk.r;
+  if (r + s <= 0) {
+    out.Z.resize(ctx, ld);
+    return;
+  }
+  Orth o;
+  rr_orth(ctx, n, Grest, ldg, s, o, Zk.Q.get(), ld, r);
+  if (o.k == 0) {
+    out.Z.resize(ctx, ld);
+    return;
+  }
+  DBuf<double> T;
+  basis_coefficients(ctx, Zk, o, s, T);
+  std::vector<double> full(r, 1.0);
+  full.insert(full.end(), sign.begin(), sign.end());
+  truncate_core(ctx, n, o, T.get(), r + s, full, eta_s_rel, out, res_budget, a2, g2);
 }
 
 bool psd_compress(Ctx* ctx, int64_t n, const double* Z, int64_t ldz, int w, double tau_abs, DBuf<double>& out,

@@ -18,17 +18,24 @@ struct ResidualFactor {
 // leading dimension pad_ld(n); Z: n x r (ldz).  Eigenvalues of H below
 // eta_r_rel max|lambda(H)| in magnitude are dropped; with drop_fro > 0 so are
 // the smallest ones whose joint Frobenius norm is at most drop_fro.
+struct TruncResult;
 void residual_factor(Ctx* ctx, const SellOp& A64, const double* B, int m, const double* Ct, int p,
                      const double* Z, int64_t ldz, int r, double eta_r_rel, ResidualFactor& out,
-                     double drop_fro = 0.0);
+                     double drop_fro = 0.0, const TruncResult* basis = nullptr);
 
 // Algorithm 2 for a general signature: Z Z^T = positive part of G N G^T
 // above eta_s_rel * max|lambda(P)|.  Output Z: n x *r (ld pad_ld(n)).
+// Z = Q diag(sqrt(sig)) with orthonormal Q (kept when has_q): a later
+// Algorithm 1 or 2 on a matrix whose leading block is Z starts its
+// orthogonalisation from Q (residual_factor's `basis`, signed_truncate_basis).
 struct TruncResult {
   DBuf<double> Z;
   int r = 0;
   double eta_n = 0.0;
   double sig_max = 0.0;
+  DBuf<double> Q;               // n x r, ld pad_ld(n)
+  std::vector<double> sig;      // r kept eigenvalues of Z Z^T
+  bool has_q = false;
 };
 // With res_budget > 0 the smallest kept eigenvalues are dropped as well while
 // the Frobenius norm E of everything dropped from the positive part stays
@@ -39,6 +46,12 @@ struct TruncResult {
 void signed_truncate(Ctx* ctx, int64_t n, const double* G, int64_t ldg, int s, const std::vector<double>& sign,
                      double eta_s_rel, TruncResult& out, double res_budget = 0.0, double a2 = 0.0,
                      double g2 = 0.0);
+
+// Algorithm 2 for G = [Zk, Grest] with signature [+1 (Zk.r times), sign]:
+// the orthogonalisation starts from Zk's orthonormal basis (Zk.has_q).
+void signed_truncate_basis(Ctx* ctx, int64_t n, const TruncResult& Zk, const double* Grest, int64_t ldg, int s,
+                           const std::vector<double>& sign, double eta_s_rel, TruncResult& out,
+                           double res_budget = 0.0, double a2 = 0.0, double g2 = 0.0);
 
 // The largest magnitude c such that all of |v| <= c together stay within
 // drop_fro in the Frobenius norm (0 when even the smallest does not).
