@@ -208,6 +208,25 @@ def main():
                        "traffic": round(traffic) if traffic else None, "traffic_source": tnote,
                        "launches": calls, "avg_launch_us": round(1e6 * tsp / calls, 2) if calls else None,
                        "algorithmic_bytes_per_launch": round(nbytes / calls) if calls else None}
+    # FP64 Gram of the residual factor's orthogonalisation (Algorithm 1: F is
+    # n x (2 r + p) at the final FP32-inner rank), on the matrix cores:
+    # 2 n q^2 flop per call, wall time per call after a warm-up
+    q = 2 * s32["rank"] + p
+    Fg = torch.randn(P.n, q, dtype=torch.float64, device=dev)
+    for _ in range(2):
+        pk.gram(ctx, Fg, Fg)
+    torch.cuda.synchronize()
+    tg = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        pk.gram(ctx, Fg, Fg)
+    torch.cuda.synchronize()
+    tg = (time.perf_counter() - tg) / reps
+    gflop = 2.0 * P.n * q * q / 1e9
+    res["gram_fp64"] = {"n": P.n, "q": q, "ms_per_call": round(1e3 * tg, 3),
+                        "achieved": round(gflop / tg / 1e3, 1), "peak": 78.6, "unit": "TFLOP/s",
+                        "frac": round(gflop / tg / 1e3 / 78.6, 4)}
+    del Fg
     s64 = None
     if not args.no_fp64:
         t64, (Z64, s64, st64) = run("fp64", args.warmup, args.steps)
