@@ -212,7 +212,7 @@ def main():
     # n x (2 r + p) at the final FP32-inner rank), on the matrix cores:
     # 2 n q^2 flop per call, wall time per call after a warm-up
     q = 2 * s32["rank"] + p
-    Fg = torch.randn(P.n, q, dtype=torch.float64, device=dev)
+    Fg = torch.randn(q, P.n, dtype=torch.float64, device=dev).t()   # column-major n x q
     for _ in range(2):
         pk.gram(ctx, Fg, Fg)
     torch.cuda.synchronize()
