@@ -131,6 +131,10 @@ typedef struct {
                              alone, as in Sec. 5                                    */
   double tau_L0;          /* LR-ADI tolerance inside the initial NLR-ADI solve; <= 0
                              selects tau_L                                          */
+  int32_t spmm_tune;      /* 1 (default): the first sparse product of each shape
+                             (operator, precision, mode, column count rounded up to
+                             16) times 16- and 8-column panels and keeps the faster
+                             for the context's operator; 0: 16-column panels       */
 } care_opts;
 
 /* Statistics written by the solvers (host struct). */

@@ -94,6 +94,7 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->krylov_relax = 1;
   o->refine_forcing = 0.1;
   o->tau_L0 = 0.0;         // precision default
+  o->spmm_tune = 1;
   o->profile = 0;
   o->Z_init = nullptr;
   o->ldz_init = 0;
@@ -271,6 +272,7 @@ care_status lyap_lradi(care_ctx* cx, const care_csr* A, const double* B, const d
     ctx->reset_counters();
     ctx->profile = o->profile;
     ctx->spmm_split = o->spmm_split;
+    ctx->spmm_tune = o->spmm_tune;
     const double t0 = now_s();
     SellOp op;
     build_sell(ctx, A, r.prec, op);

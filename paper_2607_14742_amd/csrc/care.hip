@@ -275,6 +275,7 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   ctx->reset_counters();
   ctx->profile = opts ? opts->profile : 0;
   ctx->spmm_split = opts ? opts->spmm_split : 0;
+  ctx->spmm_tune = opts ? opts->spmm_tune : 1;
 
   SellOp A64, As;
   build_op(ctx, A, Prec::F64, A64);

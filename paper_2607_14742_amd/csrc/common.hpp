@@ -107,6 +107,7 @@ struct Ctx {
   bool spmm_defer = false;          // bytes of sparse launches counted by the caller
   int64_t spmm_pending[5] = {0, 0, 0, 0, 0};   // deferred launches per mode
   int spmm_split = 0;               // BiCGStab products: 0 auto, 1 fused, 2 split
+  int spmm_tune = 0;                // 1: time the panel widths of a product shape once, keep the faster
   double t_spmm = 0.0;
   int64_t krylov_iters = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_events;

@@ -3,6 +3,8 @@
 #include "sparse.hpp"
 
 #include <algorithm>
+#include <cstdlib>
+#include <cstdio>
 
 #include <hipcub/hipcub.hpp>
 
@@ -285,11 +287,15 @@ static void launch_cp(hipStream_t st, dim3 g, int mode, bool cplx, const SpmmArg
   else hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_DOT2, false>), g, dim3(256), 0, st, a);
 }
 
-template <typename TV, typename T>
-static void launch_tv(hipStream_t st, int64_t n, int mode, bool cplx, const SpmmArgs<T>& a) {
-  const int k = a.ncols;
+static int default_cp(int k, bool cplx) {
   int cp = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
   if (cplx && cp < 2) cp = 2;
+  return cp;
+}
+
+template <typename TV, typename T>
+static void launch_tv(hipStream_t st, int64_t n, int mode, bool cplx, const SpmmArgs<T>& a, int cp) {
+  const int k = a.ncols;
   dim3 g(spmm_rowblocks(n), ceil_div(k, cp));
   switch (cp) {
     case 1: launch_cp<TV, T, 1>(st, g, mode, cplx, a); break;
@@ -298,6 +304,62 @@ static void launch_tv(hipStream_t st, int64_t n, int mode, bool cplx, const Spmm
     case 8: launch_cp<TV, T, 8>(st, g, mode, cplx, a); break;
     default: launch_cp<TV, T, 16>(st, g, mode, cplx, a); break;
   }
+}
+
+template <typename T>
+static void launch_prec(Ctx* ctx, const SellOp& op, int mode, bool cplx, const SpmmArgs<T>& a, int cp) {
+  if constexpr (sizeof(T) == 8) {
+    if (op.prec != Prec::F64) fail(CARE_ERR_ARG, "FP64 vectors need the FP64 operator");
+    launch_tv<double, double>(ctx->stream, op.n, mode, cplx, a, cp);
+  } else {
+    if (op.prec == Prec::F32) launch_tv<float, float>(ctx->stream, op.n, mode, cplx, a, cp);
+    else if (op.prec == Prec::BF16) launch_tv<bf16, float>(ctx->stream, op.n, mode, cplx, a, cp);
+    else fail(CARE_ERR_ARG, "FP32 vectors need an FP32 or BF16 operator");
+  }
+  KERNEL_CHECK();
+}
+
+// Panel-width autotuner.  A product of k > 8 columns runs in panels of 16 or
+// of 8 columns.  Wider panels read the matrix fewer times; narrower ones keep
+// fewer gathers in flight per thread and need fewer registers.  Which wins
+// depends on the matrix, the precision and k.  The first launch of a shape
+// (operator, precision, mode, real/complex, k rounded up to 16) runs both
+// widths twice with HIP events around each and keeps the faster for that
+// shape.  Only modes whose outputs every launch overwrites completely (plain
+// product, split BiCGStab products) are tuned: the extra launches then leave
+// the same results behind, since the panel width does not change any column's
+// arithmetic.  Launches inside a stream capture use the stored choice or the
+// default.
+template <typename T>
+static int tuned_cp(Ctx* ctx, const SellOp& op, int mode, bool cplx, const SpmmArgs<T>& a) {
+  const int k = a.ncols;
+  const int cp0 = default_cp(k, cplx);
+  if (!ctx->spmm_tune || cp0 != 16 || !(mode == MODE_PLAIN || mode == MODE_DOT1 || mode == MODE_DOT2)) return cp0;
+  const int key = mode | (cplx ? 8 : 0) | (std::min((int)ceil_div(k, 16), 64) << 4) | (sizeof(T) == 8 ? 1 << 12 : 0);
+  auto it = op.cp_choice.find(key);
+  if (it != op.cp_choice.end()) return it->second;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_CHECK(hipStreamIsCapturing(ctx->stream, &cs));
+  if (cs != hipStreamCaptureStatusNone) return cp0;
+  hipEvent_t ev[5];
+  for (auto& e : ev) HIP_CHECK(hipEventCreate(&e));
+  const int cand[4] = {16, 8, 16, 8};
+  HIP_CHECK(hipEventRecord(ev[0], ctx->stream));
+  for (int v = 0; v < 4; ++v) {
+    launch_prec<T>(ctx, op, mode, cplx, a, cand[v]);
+    HIP_CHECK(hipEventRecord(ev[v + 1], ctx->stream));
+  }
+  HIP_CHECK(hipEventSynchronize(ev[4]));
+  float t[4];
+  for (int v = 0; v < 4; ++v) HIP_CHECK(hipEventElapsedTime(&t[v], ev[v], ev[v + 1]));
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  const float t16 = std::min(t[0], t[2]), t8 = std::min(t[1], t[3]);
+  const int cp = t8 < 0.97f * t16 ? 8 : 16;
+  op.cp_choice[key] = cp;
+  if (std::getenv("MPCARE_TRACE"))
+    std::fprintf(stderr, "[spmm-tune] n %lld mode %d cplx %d k %d fp%d: 16 cols %.1f us, 8 cols %.1f us -> %d\n",
+                 (long long)op.n, mode, cplx ? 1 : 0, k, (int)(8 * sizeof(T)), 1e3f * t16, 1e3f * t8, cp);
+  return cp;
 }
 
 template <typename T>
@@ -310,16 +372,9 @@ int launch_spmm(Ctx* ctx, const SellOp& op, int mode, bool cplx, SpmmArgs<T>& a)
   a.nrb = spmm_rowblocks(op.n);
   if (a.ncols <= 0) return a.nrb;
   if (cplx && (a.ncols % 2)) fail(CARE_ERR_ARG, "complex panel with an odd number of real columns");
+  const int cp = tuned_cp<T>(ctx, op, mode, cplx, a);
   SpmmTimer timer(ctx, op, a.ncols, mode);
-  if constexpr (sizeof(T) == 8) {
-    if (op.prec != Prec::F64) fail(CARE_ERR_ARG, "FP64 vectors need the FP64 operator");
-    launch_tv<double, double>(ctx->stream, op.n, mode, cplx, a);
-  } else {
-    if (op.prec == Prec::F32) launch_tv<float, float>(ctx->stream, op.n, mode, cplx, a);
-    else if (op.prec == Prec::BF16) launch_tv<bf16, float>(ctx->stream, op.n, mode, cplx, a);
-    else fail(CARE_ERR_ARG, "FP32 vectors need an FP32 or BF16 operator");
-  }
-  KERNEL_CHECK();
+  launch_prec<T>(ctx, op, mode, cplx, a, cp);
   return a.nrb;
 }
 

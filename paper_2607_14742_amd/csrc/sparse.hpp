@@ -37,6 +37,8 @@ struct SellOp {
   double frob = 0.0;               // ||A||_F (FP64)
   double norm_inf = 0.0;           // ||A||_inf = max_i sum_j |a_ij| (FP64)
   double norm_one = 0.0;           // ||A||_1 = max_j sum_i |a_ij| = ||A^T||_inf (FP64)
+  // panel width chosen by the autotuner per product shape (launch_spmm)
+  mutable std::map<int, int> cp_choice;
   // sqrt(||A||_1 ||A||_inf) >= ||A||_2
   double norm2_bound() const { return std::sqrt(norm_one * norm_inf); }
   // Dense operator (dense_op.hip): A^T held as an n x n column-major matrix

@@ -116,3 +116,20 @@ def test_capacity_protocol(pk, ctx):
     assert r.value > 2                      # the columns the result needs
     Z2, stats2, st2 = pk.care_solve(ctx, A, B, Cm, tol=1e-12, shifts=P.shifts, prec="fp64", rmax=r.value)
     assert st2 == 0 and Z2.shape[1] == r.value
+
+
+def test_spmm_panel_autotuner_leaves_results_unchanged(pk, ctx):
+    # the tuner picks 16- or 8-column panels by timing; a column's arithmetic
+    # does not depend on the panel width, so a solve with and without it
+    # returns the same factor bit for bit (the solve is run-to-run
+    # deterministic: fixed-order reductions, no atomics)
+    P = wl.fdm2d_problem(60, 3, 4)
+    A = pk.DeviceCSR.from_scipy(P.A)
+    outs = []
+    for tune in (1, 0, 1):
+        Z, stats, st = pk.care_solve(ctx, A, dev(P.B), dev(P.C), tol=1e-11, shifts=P.shifts, prec="fp32",
+                                     spmm_tune=tune)
+        assert st == 0, stats
+        outs.append(Z.cpu().numpy())
+    assert outs[0].shape == outs[1].shape == outs[2].shape
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
