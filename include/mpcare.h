@@ -61,8 +61,13 @@ enum {
 enum {
   CARE_FP64 = 0,                /* u_s = FP64 (the all-double baseline)             */
   CARE_FP32 = 1,                /* u_s = FP32                                       */
-  CARE_BF16_SPMM = 2            /* FP32 inner solves whose sparse products read the
+  CARE_BF16_SPMM = 2,           /* FP32 inner solves whose sparse products read the
                                    off-diagonal values of A in bfloat16            */
+  CARE_AUTO = 3                 /* care_solve* only: CARE_FP32 when the shift set's
+                                   spread max|p| / min|p| (a stand-in for the
+                                   condition of A in Theorem 1) is at most 100 for
+                                   a sparse A or 1e5 for a dense A, else CARE_FP64;
+                                   the choice is reported in care_stats.inner_prec */
 };
 
 /* CSR of A itself (NOT of A^T); 0-based int32 indices, column indices sorted
@@ -153,6 +158,7 @@ typedef struct {
   int64_t krylov_iters;               /* BiCGStab iterations summed over columns' solves */
   int32_t hist_len;                   /* entries of res_hist used                      */
   double res_hist[48];                /* relative residual after each outer step      */
+  int32_t inner_prec;                 /* inner precision used (CARE_AUTO resolved)     */
 } care_stats;
 
 /* ---------------------------------------------------------------------- */

@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libmpcare.so")
 CARE_OK, CARE_WARN_STAGNATED, CARE_WARN_MAXIT = 0, 1, 2
 CARE_ERR_ARG, CARE_ERR_CAPACITY, CARE_ERR_UNSTABLE, CARE_ERR_BREAKDOWN = -1, -2, -3, -4
 CARE_ERR_NONFINITE, CARE_ERR_DEVICE, CARE_ERR_NOMEM, CARE_ERR_NOT_IMPLEMENTED = -5, -6, -7, -8
-CARE_FP64, CARE_FP32, CARE_BF16_SPMM = 0, 1, 2
+CARE_FP64, CARE_FP32, CARE_BF16_SPMM, CARE_AUTO = 0, 1, 2, 3
 
 STATUS_NAMES = {
     0: "CARE_OK", 1: "CARE_WARN_STAGNATED", 2: "CARE_WARN_MAXIT", -1: "CARE_ERR_ARG",
@@ -50,6 +50,7 @@ class care_stats(C.Structure):
         ("t_total", C.c_double), ("t_stage0", C.c_double), ("t_refine", C.c_double), ("t_setup", C.c_double),
         ("spmm_calls", C.c_int64), ("spmm_bytes", C.c_double), ("t_spmm", C.c_double),
         ("krylov_iters", C.c_int64), ("hist_len", C.c_int32), ("res_hist", C.c_double * 48),
+        ("inner_prec", C.c_int32),
     ]
 
     def to_dict(self):

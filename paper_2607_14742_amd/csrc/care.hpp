@@ -16,6 +16,8 @@ struct Resolved {
 };
 
 Resolved resolve_opts(const care_opts* o, double tol);
+// CARE_FP32 or CARE_FP64 for inner_prec = CARE_AUTO, from the shift spread
+int choose_inner_precision(const std::vector<Shift>& shifts, bool dense);
 
 // The operator of one solve: a sparse CSR of A, or a dense column-major A.
 struct OpSpec {

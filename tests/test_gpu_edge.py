@@ -133,3 +133,28 @@ def test_spmm_panel_autotuner_leaves_results_unchanged(pk, ctx):
         outs.append(Z.cpu().numpy())
     assert outs[0].shape == outs[1].shape == outs[2].shape
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("case,want", [("fdm2d", "fp64"), ("toeplitz", "fp32"), ("dense", "fp32")])
+def test_auto_precision_choice(pk, ctx, case, want):
+    # CARE_AUTO: FP32 inner solves only when the shift spread (the stand-in
+    # for kappa in Theorem 1) is small: <= 100 for a sparse A, <= 1e5 for a
+    # dense A with LU shifted solves
+    if case == "fdm2d":
+        P = wl.fdm2d_problem(60, 2, 3)            # spread ~1.5e3
+        A, B, Cm, shifts, Xs = P.A, P.B, P.C, P.shifts, None
+        Z, stats, st = pk.care_solve(ctx, pk.DeviceCSR.from_scipy(A), dev(B), dev(Cm), tol=1e-11, shifts=shifts,
+                                     prec="auto")
+    elif case == "toeplitz":
+        P = wl.toeplitz_problem(400)
+        A, B, Cm = P.A, P.B, P.C
+        Z, stats, st = pk.care_solve(ctx, pk.DeviceCSR.from_scipy(A), dev(B), dev(Cm), tol=1e-11, shifts=None,
+                                     prec="auto")
+    else:
+        A, B, Cm = wl.ex1(200, 4, 3, 3.0)           # kappa 1e3, shifts over [1, 1e3]
+        Z, stats, st = pk.care_solve_dense(ctx, dev(A), dev(B), dev(Cm), tol=1e-11,
+                                           shifts=wl.logspaced_real_shifts(1.0, 1e3, 16), prec="auto")
+    assert st == 0, stats
+    assert stats["inner_prec"] == {"fp64": pk.CARE_FP64, "fp32": pk.CARE_FP32}[want]
+    rel = lowrank.residual_norm(A, B, Cm, Z.cpu().numpy()) / np.linalg.norm(Cm @ Cm.T)
+    assert rel <= 1e-11
