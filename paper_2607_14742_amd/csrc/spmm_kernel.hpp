@@ -219,6 +219,25 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
 #pragma unroll
   for (int k = 0; k < (NDOT > 0 ? NDOT * CP : 1); ++k) dots[k] = (T)0;
 
+  // plain product and the first split product need the row's own input only
+  // for the diagonal term: it seeds the accumulators before the gathers, so
+  // those inputs are not live across the loop
+  constexpr bool DIAG_FIRST = MODE == MODE_PLAIN || MODE == MODE_DOT1;
+  if (DIAG_FIRST && i < a.n && qa >= 0) {
+    const T d0 = a.diag[i] + (T)a.sr;
+    const T sim0 = (T)a.si;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      T x0r, x0i;
+      input(q, i, x0r, x0i);
+      if (!CPLX) {
+        acc_r[q] = d0 * x0r;
+      } else {
+        acc_r[q] = d0 * x0r - sim0 * x0i;
+        acc_i[q] = d0 * x0i + sim0 * x0r;
+      }
+    }
+  }
   if (i < a.n && qa >= 0) {
     const int s = i >> 6, lane = i & 63;
     const int beg = a.sptr[s], end = a.sptr[s + 1];
@@ -254,7 +273,8 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
     T xr[NL], xi[NL], hr[NL], hi[NL];
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
-      input(q, i, xr[q], xi[q]);
+      xr[q] = xi[q] = (T)0;
+      if (!DIAG_FIRST) input(q, i, xr[q], xi[q]);
       hr[q] = hi[q] = (T)0;
       if (MODE == MODE_BICG_P || MODE == MODE_DOT1) {
         const int64_t oh = (int64_t)colq[q] * a.ldrhat + i;
@@ -266,7 +286,10 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
     for (int q = 0; q < NL; ++q) {
       if (!act[q]) continue;
       T yr, yi = (T)0;
-      if (!CPLX) {
+      if (DIAG_FIRST) {
+        yr = acc_r[q];
+        yi = CPLX ? acc_i[q] : (T)0;
+      } else if (!CPLX) {
         yr = acc_r[q] + d * xr[q];
       } else {
         yr = acc_r[q] + d * xr[q] - sim * xi[q];
