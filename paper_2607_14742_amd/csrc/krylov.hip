@@ -22,11 +22,16 @@ namespace mpcare {
 
 enum { FLAG_NONE = 0, FLAG_CONVERGED = 1, FLAG_BREAKDOWN = 2, FLAG_NONFINITE = 3, FLAG_STAGNATED = 4, FLAG_DIVERGED = 5 };
 // a column stops when its residual norm has not dropped by 10 % for
-// max(STALL_MAX, iterations / 4) iterations (the attainable accuracy of the
-// working precision is reached, or BiCGStab stagnates; see the restarts),
-// or when it exceeds 1e3 x the smallest residual met (divergence); it then
-// returns the best checkpointed iterate
+// max(STALL_MAX, iterations / 4) iterations in FP64, max(STALL_MAX_F32,
+// iterations / 8) in FP32 (the attainable accuracy of the working precision
+// is reached, or BiCGStab stagnates; see the restarts), or when it exceeds
+// 1e3 x the smallest residual met (divergence); it then returns the best
+// checkpointed iterate.  FP32 columns meet their precision's floor often (at
+// small shifts the floor lies above the requested tolerance), so their window
+// is shorter; FP64 keeps the longer one (the inverse Arnoldi of the shift
+// heuristic needs it to reach 1e-12).
 constexpr int STALL_MAX = 150;
+constexpr int STALL_MAX_F32 = 50;
 constexpr double DIVERGE_RR = 1e6;
 enum { UPD_INIT = 0, UPD_XR = 1 };
 
@@ -204,7 +209,8 @@ __device__ __forceinline__ void cdiv(double ar, double ai, double br, double bi,
 // PHASE 0: init (bnrm2, rho); 1: alpha; 2: omega; 3: beta + convergence
 template <int PHASE, bool CPLX>
 __global__ void __launch_bounds__(SCALAR_THREADS) k_bicg_scalar(double* __restrict__ scv, int* __restrict__ stv,
-                                                    const double* __restrict__ part, int ncols, int nrb, double tol2) {
+                                                    const double* __restrict__ part, int ncols, int nrb, double tol2,
+                                                    int stall_min, int stall_div) {
   const int lc = blockIdx.x;
   const int cr = CPLX ? 2 * lc : lc;
   double* sc = scv + (int64_t)lc * KS;
@@ -302,7 +308,7 @@ __global__ void __launch_bounds__(SCALAR_THREADS) k_bicg_scalar(double* __restri
       st[KI_FLAG] = FLAG_DIVERGED;
       return;
     }
-    if (st[KI_STALL] > STALL_MAX && st[KI_STALL] > st[KI_ITERS] / 4) {
+    if (st[KI_STALL] > stall_min && st[KI_STALL] > st[KI_ITERS] / stall_div) {
       st[KI_ACTIVE] = 0;
       st[KI_FLAG] = FLAG_STAGNATED;
       return;
@@ -507,12 +513,16 @@ static void elem(Ctx* ctx, bool cplx, const ElemArgs<T>& a) {
 }
 
 template <int PHASE>
-static void scalar(Ctx* ctx, bool cplx, double* sc, int* st, const double* part, int ncols, int nrb, double tol2) {
+static void scalar(Ctx* ctx, bool cplx, double* sc, int* st, const double* part, int ncols, int nrb, double tol2,
+                   bool fp32) {
   const int nl = cplx ? ncols / 2 : ncols;
+  const int smin = fp32 ? STALL_MAX_F32 : STALL_MAX, sdiv = fp32 ? 8 : 4;
   if (cplx)
-    hipLaunchKernelGGL((k_bicg_scalar<PHASE, true>), dim3(nl), dim3(SCALAR_THREADS), 0, ctx->stream, sc, st, part, ncols, nrb, tol2);
+    hipLaunchKernelGGL((k_bicg_scalar<PHASE, true>), dim3(nl), dim3(SCALAR_THREADS), 0, ctx->stream, sc, st, part,
+                       ncols, nrb, tol2, smin, sdiv);
   else
-    hipLaunchKernelGGL((k_bicg_scalar<PHASE, false>), dim3(nl), dim3(SCALAR_THREADS), 0, ctx->stream, sc, st, part, ncols, nrb, tol2);
+    hipLaunchKernelGGL((k_bicg_scalar<PHASE, false>), dim3(nl), dim3(SCALAR_THREADS), 0, ctx->stream, sc, st, part,
+                       ncols, nrb, tol2, smin, sdiv);
   KERNEL_CHECK();
 }
 
@@ -569,7 +579,7 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
     }
   };
   elem<T, UPD_INIT>(ctx, cplx, ea);
-  scalar<0>(ctx, cplx, sc.get(), st.get(), part.get(), ncols, nrb, tol2);
+  scalar<0>(ctx, cplx, sc.get(), st.get(), part.get(), ncols, nrb, tol2, sizeof(T) == 4);
   if (groups || target2) {
     // tolerance relative to the largest right-hand side of each group, or an
     // absolute target ||r_c||^2 <= target2[c] (restarts)
@@ -631,7 +641,7 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
     } else {
       launch_spmm<T>(ctx, op, MODE_BICG_P, cplx, a1);
     }
-    scalar<1>(ctx, cplx, sc.get(), st.get(), part.get(), ncols, nrb, tol2);
+    scalar<1>(ctx, cplx, sc.get(), st.get(), part.get(), ncols, nrb, tol2, sizeof(T) == 4);
     if (trace && it < 3) dump("S1");
 
     SpmmArgs<T> a2 = a1;
@@ -649,7 +659,7 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
     } else {
       launch_spmm<T>(ctx, op, MODE_BICG_S, cplx, a2);
     }
-    scalar<2>(ctx, cplx, sc.get(), st.get(), part.get(), ncols, nrb, tol2);
+    scalar<2>(ctx, cplx, sc.get(), st.get(), part.get(), ncols, nrb, tol2, sizeof(T) == 4);
     if (trace && it < 3) dump("S2");
 
     ElemArgs<T> e3 = ea;
@@ -657,7 +667,7 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
     e3.s = S.get();
     e3.t = Tt.get();
     elem<T, UPD_XR>(ctx, cplx, e3);
-    scalar<3>(ctx, cplx, sc.get(), st.get(), part.get(), ncols, nrb, tol2);
+    scalar<3>(ctx, cplx, sc.get(), st.get(), part.get(), ncols, nrb, tol2, sizeof(T) == 4);
     if (trace && it < 3) dump("S3");
   };
   // Profiling: the bytes of the launches since the previous poll are counted
