@@ -68,14 +68,18 @@ static double unit_roundoff(Prec p) { return p == Prec::F64 ? U64 : (p == Prec::
 // 1.1x faster; the 3D problem (kappa ~1.7e3) is 1.4x slower and the 2D FDM
 // problem (2.9e4) 2.6x slower.  So FP32 for a spread <= 100.  With direct (LU)
 // shifted solves the paper's Table 1 shows FP32 gains up to kappa = 1e5.
-int choose_inner_precision(const std::vector<Shift>& shifts, bool dense) {
+double shift_spread(const std::vector<Shift>& shifts) {
   double lo = INFINITY, hi = 0.0;
   for (const Shift& p : shifts) {
     const double a = std::hypot(p.re, p.im);
     lo = std::min(lo, a);
     hi = std::max(hi, a);
   }
-  const double spread = lo > 0.0 ? hi / lo : INFINITY;
+  return lo > 0.0 && hi > 0.0 ? hi / lo : 1.0;
+}
+
+int choose_inner_precision(const std::vector<Shift>& shifts, bool dense) {
+  const double spread = shift_spread(shifts);
   const double limit = dense ? 1e5 : 100.0;
   const int choice = spread <= limit ? CARE_FP32 : CARE_FP64;
   if (std::getenv("MPCARE_TRACE"))
@@ -429,7 +433,11 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
       int np = 0, nm = 0;
       double tau_k = S.prm.tau_L, kt_k = S.prm.ktol;
       if (theta > 0.0) {
-        tau_k = std::min(0.1, std::max(S.prm.tau_L, theta * tol / rel));
+        // An FP32 correction gains at most ~ kappa u_s in relative accuracy
+        // (Theorem 1; kappa read off the shift spread), so its Lyapunov solve
+        // is not asked for much more than a tenth of that.
+        const double floor_k = S.prm.prec == Prec::F32 ? 0.1 * shift_spread(S.shifts) * U32 : 0.0;
+        tau_k = std::min(0.1, std::max({S.prm.tau_L, theta * tol / rel, floor_k}));
         kt_k = std::max(S.prm.ktol, 0.1 * tau_k);
       }
       if (std::getenv("MPCARE_TRACE")) std::fprintf(stderr, "[refine] correction tau %.3e ktol %.3e\n", tau_k, kt_k);

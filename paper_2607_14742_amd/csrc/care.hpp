@@ -16,6 +16,8 @@ struct Resolved {
 };
 
 Resolved resolve_opts(const care_opts* o, double tol);
+// max|p| / min|p| over a shift set (1 for an empty or degenerate set)
+double shift_spread(const std::vector<Shift>& shifts);
 // CARE_FP32 or CARE_FP64 for inner_prec = CARE_AUTO, from the shift spread
 int choose_inner_precision(const std::vector<Shift>& shifts, bool dense);
 
