@@ -140,6 +140,11 @@ typedef struct {
                              (operator, precision, mode, column count rounded up to
                              16) times 16- and 8-column panels and keeps the faster
                              for the context's operator; 0: 16-column panels       */
+  int32_t shift_update;   /* heuristic shifts only (nshifts = 0): 1 recomputes them
+                             for every Lyapunov solve from its closed-loop operator
+                             A - B K^T (Newton steps >= 1, corrections), the
+                             inverse Arnoldi through SMW; 0 (default): one set
+                             from A for the whole solve                            */
 } care_opts;
 
 /* Statistics written by the solvers (host struct). */

@@ -95,6 +95,7 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->refine_forcing = 0.1;
   o->tau_L0 = 0.0;         // precision default
   o->spmm_tune = 1;
+  o->shift_update = 0;
   o->profile = 0;
   o->Z_init = nullptr;
   o->ldz_init = 0;

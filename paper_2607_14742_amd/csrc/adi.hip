@@ -33,7 +33,7 @@ std::vector<Shift> check_shifts(const care_shift* s, int count) {
 }
 
 // Gauss-Jordan inverse of a small complex matrix (column-major), partial pivoting
-static bool cinv(int m, std::vector<cplx>& A) {
+bool cinv(int m, std::vector<std::complex<double>>& A) {
   std::vector<cplx> I((size_t)m * m, 0.0);
   for (int i = 0; i < m; ++i) I[(size_t)i * m + i] = 1.0;
   for (int c = 0; c < m; ++c) {

@@ -45,6 +45,10 @@ struct LradiOut {
   std::vector<int> zsrc;     // column of W0 that each column of Z comes from
 };
 
+// in-place inverse of a small m x m complex matrix (column-major, partial
+// pivoting); false if singular
+bool cinv(int m, std::vector<std::complex<double>>& A);
+
 // shift list checks: Re < 0, complex shifts as (p, conj p) with Im p > 0 first
 std::vector<Shift> check_shifts(const care_shift* s, int count);
 

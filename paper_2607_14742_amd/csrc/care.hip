@@ -123,7 +123,22 @@ struct SolveState {
   // truncation budget of Algorithm 2 (residual change, absolute) and the
   // bounds it is converted with: a2 >= ||A||_2, g2 >= ||B B^T||_2
   double res_budget = 0.0, a2 = 0.0, g2 = 0.0;
+  // shifts recomputed for each closed-loop operator A - B K^T (heuristic
+  // mode with shift_update = 1)
+  bool dyn_shifts = false;
+  int l0 = 16, kp = 20, km = 10;
+  bool real_only = false;
 };
+
+// the shift set for the operator A - B K^T of one Lyapunov solve: the fixed
+// set, or (dynamic shifts) the heuristic applied to that operator
+static std::vector<Shift> shifts_for(Ctx* ctx, const SolveState& S, const double* K64) {
+  if (!S.dyn_shifts || !K64 || S.m == 0) return S.shifts;
+  std::vector<Shift> sh = penzl_shifts(ctx, *S.A64, S.l0, S.kp, S.km, S.real_only, S.B64.get(), K64, S.m);
+  if (std::getenv("MPCARE_TRACE"))
+    for (const Shift& p : sh) std::fprintf(stderr, "[penzl A-BK^T] shift (%.6e, %.6e)\n", p.re, p.im);
+  return sh;
+}
 
 template <typename T>
 static void cast_in(Ctx* ctx, int64_t n, int cols, const double* src, int64_t lds, DBuf<T>& dst) {
@@ -163,8 +178,14 @@ static void stage0(Ctx* ctx, SolveState& S, TruncResult& Zout, care_stats* st, s
     const int w = (i == 0 || m == 0) ? p : p + m;
     d2d(ctx, W.get(), Cts.get(), (size_t)ld * p * sizeof(T));
     if (w > p) d2d(ctx, W.get() + (int64_t)p * ld, K.get(), (size_t)ld * m * sizeof(T));
-    LradiOut lo = lradi_run<T>(ctx, *S.As, Bs.get(), (i > 0 && m > 0) ? K.get() : nullptr, m, W.get(), w, S.shifts,
-                               lp, Zb, zcap);
+    std::vector<Shift> sh = S.shifts;
+    if (S.dyn_shifts && i > 0 && m > 0) {
+      DBuf<double> K64(ctx, (size_t)ld * m);
+      copy_cols<T, double>(ctx, n, m, K.get(), ld, K64.get(), ld);
+      sh = shifts_for(ctx, S, K64.get());
+    }
+    LradiOut lo = lradi_run<T>(ctx, *S.As, Bs.get(), (i > 0 && m > 0) ? K.get() : nullptr, m, W.get(), w, sh, lp,
+                               Zb, zcap);
     st->iter0_outer += 1;
     st->iter0_inner += lo.steps;
     zcols = lo.zcols;
@@ -235,8 +256,9 @@ static void correction(Ctx* ctx, SolveState& S, const TruncResult& Zk, const Res
   lp.deflate = S.prm.deflate;
   lp.group_tol = S.prm.block_tol;
   lp.relax = S.prm.relax;
-  LradiOut lo = lradi_run<T>(ctx, *S.As, Bs.get(), (m > 0 && Zk.r > 0) ? Ks.get() : nullptr, m, W.get(), w,
-                             S.shifts, lp, Zb, zcap);
+  const std::vector<Shift> sh = shifts_for(ctx, S, (m > 0 && Zk.r > 0) ? K64.get() : nullptr);
+  LradiOut lo = lradi_run<T>(ctx, *S.As, Bs.get(), (m > 0 && Zk.r > 0) ? Ks.get() : nullptr, m, W.get(), w, sh,
+                             lp, Zb, zcap);
   st->iter_inner += lo.steps;
   const int zcols = lo.zcols;
   std::vector<int> map;
@@ -317,6 +339,11 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   SellOp A64, As;
   build_op(ctx, A, Prec::F64, A64);
   S.A64 = &A64;
+  S.l0 = eff.penzl_l0;
+  S.kp = eff.penzl_kp;
+  S.km = eff.penzl_km;
+  S.real_only = eff.penzl_real != 0;
+  S.dyn_shifts = nshifts == 0 && eff.shift_update != 0;
   if (nshifts > 0) {
     S.shifts = check_shifts(shifts, nshifts);
   } else {

@@ -43,7 +43,10 @@ void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, con
 
 // Penzl's heuristic (penzl.hip): Ritz values of A^T and A^-T on the GPU, then
 // the greedy min-max choice of l0 shifts; real_only keeps real parts.
-std::vector<Shift> penzl_shifts(Ctx* ctx, const SellOp& A64, int l0, int kp, int km, bool real_only);
+// shift heuristic (Penzl) from Ritz values of A_k^T = A^T - K B^T and its
+// inverse; K = NULL (or m = 0) gives the shifts of A itself
+std::vector<Shift> penzl_shifts(Ctx* ctx, const SellOp& A64, int l0, int kp, int km, bool real_only,
+                                const double* B = nullptr, const double* K = nullptr, int m = 0);
 // host steps of the heuristic
 std::vector<std::complex<double>> hessenberg_eigvals(const double* H, int k, int64_t ldh);
 std::vector<Shift> penzl_select(std::vector<std::complex<double>> R, int l0);

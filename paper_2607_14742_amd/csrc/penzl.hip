@@ -172,11 +172,35 @@ std::vector<Shift> penzl_select(std::vector<cplx> R, int l0) {
   return out;
 }
 
-// Ritz values of k Arnoldi steps with F = A^T (inverse: F^{-1}, applied by
-// BiCGStab to relative residual 1e-12) from ones / sqrt(n).
-static std::vector<cplx> arnoldi_ritz(Ctx* ctx, const SellOp& op, int k, bool inverse) {
+// Ritz values of k Arnoldi steps with F = A_k^T = A^T - K B^T (K = NULL or
+// m = 0: F = A^T) from ones / sqrt(n).  The inverse F^{-1} is applied by
+// BiCGStab on A^T to relative residual 1e-12 plus the Sherman-Morrison-
+// Woodbury correction F^{-1} v = M^{-1} v + S (I - B^T S)^{-1} B^T M^{-1} v,
+// M = A^T, S = M^{-1} K (Sec. 4).  B, K: FP64, n x m, ld pad_ld(n).
+static std::vector<cplx> arnoldi_ritz(Ctx* ctx, const SellOp& op, int k, bool inverse, const double* B,
+                                      const double* K, int m) {
   const int64_t n = op.n, ld = pad_ld(n);
+  if (!B || !K) m = 0;
   DBuf<double> V(ctx, (size_t)ld * (k + 1)), w(ctx, ld), h1(ctx, k + 1), h2(ctx, k + 1), nn(ctx, 1);
+  DBuf<double> bw(ctx, (size_t)std::max(m, 1)), Sm(ctx, (size_t)ld * std::max(m, 1)), coef(ctx, (size_t)std::max(m, 1));
+  std::vector<double> Tinv((size_t)m * m);
+  auto solve_m = [&](const double* rhs, int cols, double* out) {
+    KrylovResult kr = bicgstab<double>(ctx, op, 0.0, 0.0, cols, rhs, ld, out, ld, 1e-12, 20000, 8);
+    if (!(kr.worst_relres < 1e-6)) fail(CARE_ERR_BREAKDOWN, "inverse Arnoldi solve with A^T did not converge");
+  };
+  if (inverse && m > 0) {
+    // S = M^{-1} K, Tinv = (I - B^T S)^{-1} (host, m x m)
+    solve_m(K, m, Sm.get());
+    DBuf<double> G(ctx, (size_t)m * m);
+    gram(ctx, n, B, ld, m, Sm.get(), ld, m, G.get(), m);
+    std::vector<double> g((size_t)m * m);
+    d2h(ctx, g.data(), G.get(), g.size() * sizeof(double));
+    std::vector<cplx> T((size_t)m * m);
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i) T[(size_t)j * m + i] = (i == j ? 1.0 : 0.0) - g[(size_t)j * m + i];
+    if (!cinv(m, T)) fail(CARE_ERR_BREAKDOWN, "singular capacitance matrix I - B^T A^-T K");
+    for (size_t e = 0; e < T.size(); ++e) Tinv[e] = T[e].real();
+  }
   {
     std::vector<double> b0(n, 1.0 / std::sqrt((double)n));
     h2d(ctx, V.get(), b0.data(), n * sizeof(double));
@@ -187,10 +211,21 @@ static std::vector<cplx> arnoldi_ritz(Ctx* ctx, const SellOp& op, int k, bool in
     const double* vj = V.get() + (int64_t)j * ld;
     if (!inverse) {
       spmm_plain(ctx, op, 0.0, 0.0, vj, ld, 1, w.get(), ld);
+      if (m > 0) {   // w -= K (B^T v)
+        gram(ctx, n, B, ld, m, vj, ld, 1, bw.get(), m);
+        tsgemm(ctx, n, K, ld, m, bw.get(), m, 1, -1.0, 1.0, w.get(), ld);
+      }
     } else {
-      KrylovResult kr = bicgstab<double>(ctx, op, 0.0, 0.0, 1, vj, ld, w.get(), ld, 1e-12, 20000, 8);
-      if (!(kr.worst_relres < 1e-6))
-        fail(CARE_ERR_BREAKDOWN, "inverse Arnoldi solve with A^T did not converge");
+      solve_m(vj, 1, w.get());
+      if (m > 0) {   // w += S Tinv (B^T w)
+        std::vector<double> bt(m), c(m, 0.0);
+        gram(ctx, n, B, ld, m, w.get(), ld, 1, bw.get(), m);
+        d2h(ctx, bt.data(), bw.get(), m * sizeof(double));
+        for (int i = 0; i < m; ++i)
+          for (int l = 0; l < m; ++l) c[i] += Tinv[(size_t)l * m + i] * bt[l];
+        h2d(ctx, coef.get(), c.data(), m * sizeof(double));
+        tsgemm(ctx, n, Sm.get(), ld, m, coef.get(), m, 1, 1.0, 1.0, w.get(), ld);
+      }
     }
     // classical Gram-Schmidt, twice
     std::vector<double> hc(j + 1, 0.0), tmp(j + 1);
@@ -223,13 +258,14 @@ static std::vector<cplx> arnoldi_ritz(Ctx* ctx, const SellOp& op, int k, bool in
   return ev;
 }
 
-std::vector<Shift> penzl_shifts(Ctx* ctx, const SellOp& A64, int l0, int kp, int km, bool real_only) {
+std::vector<Shift> penzl_shifts(Ctx* ctx, const SellOp& A64, int l0, int kp, int km, bool real_only, const double* B,
+                                const double* K, int m) {
   if (A64.prec != Prec::F64) fail(CARE_ERR_ARG, "Ritz values need the FP64 operator");
   if (l0 < 1 || kp < 1 || km < 0) fail(CARE_ERR_ARG, "need l0 >= 1, kp >= 1, km >= 0");
   const int kcap = (int)std::min<int64_t>(A64.n, 1000);
-  std::vector<cplx> R = arnoldi_ritz(ctx, A64, std::min(kp, kcap), false);
+  std::vector<cplx> R = arnoldi_ritz(ctx, A64, std::min(kp, kcap), false, B, K, m);
   if (km > 0) {
-    std::vector<cplx> Ri = arnoldi_ritz(ctx, A64, std::min(km, kcap), true);
+    std::vector<cplx> Ri = arnoldi_ritz(ctx, A64, std::min(km, kcap), true, B, K, m);
     R.insert(R.end(), Ri.begin(), Ri.end());
   }
   if (real_only)

@@ -139,3 +139,24 @@ def test_example1_against_table1(pk, ctx, row):
     print(f"  fp64 rank {r} res {st64['res_paper']:.2e} | fp32 status {s32} rank {st32['rank']} "
           f"res {st32['res_paper']:.2e} relres {st32['res_rel']:.2e}", flush=True)
     assert ok32 == row["fp32_converged"], (s32, st32["res_paper"], st32["res_rel"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_example1_dynamic_shifts(pk, ctx, prec):
+    # Example 1 at kappa = 10: B = 0.2 ones moves the closed-loop spectrum far
+    # from A's, so shifts recomputed for each A - B K^T (shift_update = 1)
+    # need far fewer ADI steps than one set from A; both reach the Schur
+    # solution
+    A, B, C = wl.ex1(300, 10, 5, 1.0)
+    Xs = riccati.care_schur(A, B, C)
+    steps = {}
+    for dyn in (0, 1):
+        Z, st, s = pk.care_solve_dense(ctx, dev(A), dev(B), dev(C), tol=1e-12, shifts=None, prec=prec,
+                                       shift_update=dyn)
+        assert s in (0, 1), st
+        Z = Z.cpu().numpy()
+        assert relres(A, B, C, Z) <= 1e-11
+        assert np.linalg.norm(Z @ Z.T - Xs) <= 1e-8 * np.linalg.norm(Xs)
+        steps[dyn] = st["iter0_inner"] + st["iter_inner"]
+    print(f"  ADI steps: fixed shifts {steps[0]}, shifts per operator {steps[1]}", flush=True)
+    assert 2 * steps[1] <= steps[0], steps
