@@ -145,6 +145,11 @@ typedef struct {
                              A - B K^T (Newton steps >= 1, corrections), the
                              inverse Arnoldi through SMW; 0 (default): one set
                              from A for the whole solve                            */
+  int32_t krylov_method;  /* shifted solves: 0 (default) column-batched BiCGStab;
+                             1 restarted GMRES for real shifts (complex pairs stay
+                             on BiCGStab); krylov_maxit then counts Arnoldi steps  */
+  int32_t krylov_restart; /* GMRES restart length; <= 0 selects 30 (FP32) / 50 (FP64),
+                             the values of Sec. 5                                   */
 } care_opts;
 
 /* Statistics written by the solvers (host struct). */

@@ -39,6 +39,7 @@ class care_opts(C.Structure):
         ("adi_deflate", C.c_int32), ("krylov_block_tol", C.c_int32), ("penzl_real", C.c_int32),
         ("spmm_split", C.c_int32), ("krylov_relax", C.c_int32), ("refine_forcing", C.c_double),
         ("tau_L0", C.c_double), ("spmm_tune", C.c_int32), ("shift_update", C.c_int32),
+        ("krylov_method", C.c_int32), ("krylov_restart", C.c_int32),
     ]
 
 

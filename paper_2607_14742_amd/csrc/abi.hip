@@ -96,6 +96,8 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->tau_L0 = 0.0;         // precision default
   o->spmm_tune = 1;
   o->shift_update = 0;
+  o->krylov_method = 0;
+  o->krylov_restart = 0;
   o->profile = 0;
   o->Z_init = nullptr;
   o->ldz_init = 0;
@@ -173,6 +175,7 @@ care_status care_shifted_solve(care_ctx* cx, const care_csr* A, const double* B,
     const Prec pr = prec_from_abi(prec);
     const int64_t n = A->n, ld = pad_ld(n);
     if (w < 0 || m < 0) fail(CARE_ERR_ARG, "w and m must be >= 0");
+    ctx->krylov_method = 0;   // this entry point documents BiCGStab
     if (w == 0) return CARE_OK;
     if (!W || !V || ldw < n || ldv < n) fail(CARE_ERR_ARG, "invalid W / V");
     const bool smw = K != nullptr && m > 0;
@@ -274,6 +277,8 @@ care_status lyap_lradi(care_ctx* cx, const care_csr* A, const double* B, const d
     ctx->profile = o->profile;
     ctx->spmm_split = o->spmm_split;
     ctx->spmm_tune = o->spmm_tune;
+    ctx->krylov_method = o->krylov_method;
+    ctx->krylov_restart = o->krylov_restart;
     const double t0 = now_s();
     SellOp op;
     build_sell(ctx, A, r.prec, op);

@@ -335,6 +335,9 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   ctx->profile = opts ? opts->profile : 0;
   ctx->spmm_split = opts ? opts->spmm_split : 0;
   ctx->spmm_tune = opts ? opts->spmm_tune : 1;
+  ctx->krylov_method = opts ? opts->krylov_method : 0;
+  ctx->krylov_restart = opts ? opts->krylov_restart : 0;
+  if (ctx->krylov_method < 0 || ctx->krylov_method > 1) fail(CARE_ERR_ARG, "krylov_method must be 0 or 1");
 
   SellOp A64, As;
   build_op(ctx, A, Prec::F64, A64);

@@ -35,6 +35,14 @@ KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncol
                       int64_t ldb, T* x, int64_t ldx, double tol, int maxit, int check_every,
                       const std::vector<int>* groups = nullptr);
 
+// Restarted GMRES(restart) for a real shift (gmres.hip): the same contract as
+// bicgstab (zero initial guess, per-column or per-group tolerance); maxit
+// counts Arnoldi steps over all cycles.  bicgstab() dispatches here when the
+// context selects it and the shift is real.
+template <typename T>
+KrylovResult gmres(Ctx* ctx, const SellOp& op, double pr, int ncols, const T* b, int64_t ldb, T* x, int64_t ldx,
+                   double tol, int maxit, int restart, const std::vector<int>* groups);
+
 // Direct shifted solve for a dense operator (dense_op.hip): LU of A^T + p I
 // in the operator precision, cached per real shift on the operator.
 template <typename T>

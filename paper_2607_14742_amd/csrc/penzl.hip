@@ -185,7 +185,18 @@ static std::vector<cplx> arnoldi_ritz(Ctx* ctx, const SellOp& op, int k, bool in
   DBuf<double> bw(ctx, (size_t)std::max(m, 1)), Sm(ctx, (size_t)ld * std::max(m, 1)), coef(ctx, (size_t)std::max(m, 1));
   std::vector<double> Tinv((size_t)m * m);
   auto solve_m = [&](const double* rhs, int cols, double* out) {
-    KrylovResult kr = bicgstab<double>(ctx, op, 0.0, 0.0, cols, rhs, ld, out, ld, 1e-12, 20000, 8);
+    // BiCGStab whatever the context's choice for the ADI solves: the
+    // unshifted solves need 1e-12 and a long iteration budget
+    const int method = ctx->krylov_method;
+    ctx->krylov_method = 0;
+    KrylovResult kr;
+    try {
+      kr = bicgstab<double>(ctx, op, 0.0, 0.0, cols, rhs, ld, out, ld, 1e-12, 20000, 8);
+    } catch (...) {
+      ctx->krylov_method = method;
+      throw;
+    }
+    ctx->krylov_method = method;
     if (!(kr.worst_relres < 1e-6)) fail(CARE_ERR_BREAKDOWN, "inverse Arnoldi solve with A^T did not converge");
   };
   if (inverse && m > 0) {

@@ -1,0 +1,74 @@
+"""Restarted GMRES as the inner solver (option krylov_method = 1; the solver
+family of Sec. 5, without the paper's ILU(0) preconditioner): CARE solves
+against dense Schur solutions and against the BiCGStab path, and the
+fallback to BiCGStab for complex shift pairs."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import lowrank, riccati
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2607_14742_amd as pk
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pk.load()
+    return pk
+
+
+@pytest.fixture(scope="module")
+def ctx(pk):
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), device="cuda")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["fdm20", "toeplitz400"])
+def test_gmres_inner_solves_vs_schur(pk, ctx, prec, case):
+    P = wl.config1() if case == "fdm20" else wl.toeplitz_problem(400)
+    print(f"gmres {case} {prec}", flush=True)
+    A = pk.DeviceCSR.from_scipy(P.A)
+    Z, stats, st = pk.care_solve(ctx, A, dev(P.B), dev(P.C), tol=1e-12, shifts=P.shifts, prec=prec,
+                                 krylov_method=1)
+    assert st == 0, stats
+    Z = Z.cpu().numpy()
+    Xs = riccati.care_schur(P.A, P.B, P.C)
+    assert lowrank.residual_norm(P.A, P.B, P.C, Z) <= 1e-10 * np.linalg.norm(P.C @ P.C.T)
+    assert np.linalg.norm(Z @ Z.T - Xs) <= 1e-8 * np.linalg.norm(Xs)
+    # the same solve with BiCGStab reaches the same solution
+    Zb, sb, stb = pk.care_solve(ctx, A, dev(P.B), dev(P.C), tol=1e-12, shifts=P.shifts, prec=prec, krylov_method=0)
+    assert stb == 0
+    Zb = Zb.cpu().numpy()
+    assert lowrank.factored_diff_norm(Z, Zb) <= 1e-8 * lowrank.factored_norm(Zb)
+
+
+def test_gmres_complex_pairs_fall_back_to_bicgstab(pk, ctx):
+    # heuristic shifts of the rotating-field 3D problem include conjugate
+    # pairs; those steps run BiCGStab, the real ones GMRES
+    P = wl.fdm3d_problem(10, 1, 3)
+    A = pk.DeviceCSR.from_scipy(P.A)
+    sh = pk.penzl_shifts(ctx, A)
+    assert np.any(np.abs(sh.imag) > 0)
+    Z, stats, st = pk.care_solve(ctx, A, dev(P.B), dev(P.C), tol=1e-11, shifts=sh, prec="fp64", krylov_method=1)
+    assert st == 0, stats
+    rel = lowrank.residual_norm(P.A, P.B, P.C, Z.cpu().numpy()) / np.linalg.norm(P.C @ P.C.T)
+    assert rel <= 1e-11
+
+
+def test_gmres_rejects_unknown_method(pk, ctx):
+    P = wl.config1()
+    with pytest.raises(pk.CareError) as e:
+        pk.care_solve(ctx, pk.DeviceCSR.from_scipy(P.A), dev(P.B), dev(P.C), tol=1e-10, shifts=P.shifts,
+                      krylov_method=2)
+    assert e.value.name == "CARE_ERR_ARG"
