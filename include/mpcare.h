@@ -126,7 +126,7 @@ typedef struct {
                              grows as ktol / (4 ||W_j^T W_j|| / ||W_0^T W_0||), capped
                              at sqrt(ktol); 0: ktol for every solve                  */
   double refine_forcing;  /* theta of the inexact-Newton forcing of the refinement
-                             corrections (0.1).  With rel_k = ||R(Z_k)||_F / ||C^T C||_F
+                             corrections (0.25).  With rel_k = ||R(Z_k)||_F / ||C^T C||_F
                              the correction LR-ADI stops at
                              tau_k = min(0.1, max(tau_L, theta tol / rel_k)), its
                              Krylov tolerance is max(krylov_tol, tau_k / 10), and
@@ -184,7 +184,7 @@ void care_ctx_destroy(care_ctx* ctx);
 /* Default options for inner precision `inner_prec`: the values of Sec. 5
  * (eta_r = 1e-4 max|lambda(H)|, eta_s = 10 u max|lambda(P)|, tau_L = 1e-12
  * for FP64, k_max = 20, j_max = 50), except tau_L = 1e-6 for FP32 (paper:
- * 1e-5) and the refinement forcing theta = 0.1 (paper: none). */
+ * 1e-5) and the refinement forcing theta = 0.25 (paper: none). */
 void care_opts_default(care_opts* opts, int32_t inner_prec);
 
 /* Message describing the last error of the calling thread ("" if none). */

@@ -92,7 +92,7 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->penzl_real = 0;
   o->spmm_split = 0;
   o->krylov_relax = 1;
-  o->refine_forcing = 0.1;
+  o->refine_forcing = 0.25;
   o->tau_L0 = 0.0;         // precision default
   o->spmm_tune = 1;
   o->shift_update = 0;

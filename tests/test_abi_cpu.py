@@ -76,7 +76,7 @@ def test_opts_defaults_follow_the_paper():
     assert o.eta_r_rel == 1e-4
     assert abs(o.eta_s_rel - 10 * 2.0 ** -53) < 1e-30
     assert o.stagnation == 0.999
-    assert o.tau_L0 == 0.0 and o.refine_forcing == 0.1
+    assert o.tau_L0 == 0.0 and o.refine_forcing == 0.25
 
 
 @needs_lib
