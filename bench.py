@@ -2,8 +2,8 @@
 mixed-precision refinement vs the all-FP64 path, at relative residual
 ||R||_F / ||C^T C||_F <= 1e-10, on the 500 x 500 2D convection-diffusion FDM
 problem (n = 250,000, 1,248,000 nonzeros, m = p = 5, Gaussian B and C from
-seed 1220, 16 log-spaced real shifts over the closed-form spectral interval,
-largest magnitude first).
+seed 1220, 12 Wachspress (minimax) real shifts for the closed-form spectral
+interval, largest magnitude first).
 
 Prints ONE JSON line (see the keys below).  A step is one full care_solve
 (initial NLR-ADI solve + refinement) with inputs resident in HBM.
@@ -143,7 +143,7 @@ def main():
         A = pk.DeviceCSR.from_scipy(P.A, dev)
         shifts = P.shifts
         wdesc = (f"2D convection-diffusion FDM {args.N}x{args.N} (n={P.n}, nnz={P.A.nnz}), m=p=5, "
-                 f"16 real shifts, FP32 inner / FP64 refine, tol {TOL:g}")
+                 f"{len(shifts)} Wachspress real shifts, FP32 inner / FP64 refine, tol {TOL:g}")
     else:
         # the paper generates its shifts from Krylov subspaces: one heuristic
         # set (GPU Arnoldi, before the timed region) serves both precisions

@@ -109,6 +109,7 @@ struct Ctx {
   int spmm_split = 0;               // BiCGStab products: 0 auto, 1 fused, 2 split
   int spmm_tune = 0;                // 1: time the panel widths of a product shape once, keep the faster
   int krylov_method = 0;            // shifted solves: 0 BiCGStab, 1 restarted GMRES (real shifts)
+  int krylov_patient = 0;           // BiCGStab stagnation window max(1000, it/2) (unshifted solves)
   int krylov_restart = 0;           // GMRES restart length (0: 30 in FP32, 50 in FP64)
   double t_spmm = 0.0;
   int64_t krylov_iters = 0;

@@ -28,9 +28,11 @@ enum { FLAG_NONE = 0, FLAG_CONVERGED = 1, FLAG_BREAKDOWN = 2, FLAG_NONFINITE = 3
 // 1e3 x the smallest residual met (divergence); it then returns the best
 // checkpointed iterate.  FP32 columns meet their precision's floor often (at
 // small shifts the floor lies above the requested tolerance), so their window
-// is shorter; FP64 keeps the longer one (the inverse Arnoldi of the shift
-// heuristic needs it to reach 1e-12).
+// is shorter; FP64 keeps the longer one.  The unshifted solves of the shift
+// heuristic's inverse Arnoldi (condition number up to kappa(A)) go through
+// long plateaus and use max(STALL_MAX_PATIENT, iterations / 2).
 constexpr int STALL_MAX = 150;
+constexpr int STALL_MAX_PATIENT = 1000;
 constexpr int STALL_MAX_F32 = 50;
 constexpr double DIVERGE_RR = 1e6;
 enum { UPD_INIT = 0, UPD_XR = 1 };
@@ -516,7 +518,11 @@ template <int PHASE>
 static void scalar(Ctx* ctx, bool cplx, double* sc, int* st, const double* part, int ncols, int nrb, double tol2,
                    bool fp32) {
   const int nl = cplx ? ncols / 2 : ncols;
-  const int smin = fp32 ? STALL_MAX_F32 : STALL_MAX, sdiv = fp32 ? 8 : 4;
+  int smin = fp32 ? STALL_MAX_F32 : STALL_MAX, sdiv = fp32 ? 8 : 4;
+  if (ctx->krylov_patient) {
+    smin = STALL_MAX_PATIENT;
+    sdiv = 2;
+  }
   if (cplx)
     hipLaunchKernelGGL((k_bicg_scalar<PHASE, true>), dim3(nl), dim3(SCALAR_THREADS), 0, ctx->stream, sc, st, part,
                        ncols, nrb, tol2, smin, sdiv);

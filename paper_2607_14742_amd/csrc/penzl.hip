@@ -12,6 +12,7 @@
 // host computations.
 #include <algorithm>
 #include <cfloat>
+#include <cstdio>
 #include <cmath>
 #include <complex>
 
@@ -186,18 +187,29 @@ static std::vector<cplx> arnoldi_ritz(Ctx* ctx, const SellOp& op, int k, bool in
   std::vector<double> Tinv((size_t)m * m);
   auto solve_m = [&](const double* rhs, int cols, double* out) {
     // BiCGStab whatever the context's choice for the ADI solves: the
-    // unshifted solves need 1e-12 and a long iteration budget
+    // unshifted solves need 1e-12, a long iteration budget and a long
+    // stagnation window
     const int method = ctx->krylov_method;
     ctx->krylov_method = 0;
+    ctx->krylov_patient = 1;
     KrylovResult kr;
     try {
       kr = bicgstab<double>(ctx, op, 0.0, 0.0, cols, rhs, ld, out, ld, 1e-12, 20000, 8);
     } catch (...) {
       ctx->krylov_method = method;
+      ctx->krylov_patient = 0;
       throw;
     }
     ctx->krylov_method = method;
-    if (!(kr.worst_relres < 1e-6)) fail(CARE_ERR_BREAKDOWN, "inverse Arnoldi solve with A^T did not converge");
+    ctx->krylov_patient = 0;
+    if (!(kr.worst_relres < 1e-6)) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg,
+                    "inverse Arnoldi solve with A^T did not converge (relative residual %.2e after %d iterations, "
+                    "%d restarts, %d breakdowns)",
+                    kr.worst_relres, kr.max_iters, kr.restarts, kr.breakdown);
+      fail(CARE_ERR_BREAKDOWN, msg);
+    }
   };
   if (inverse && m > 0) {
     // S = M^{-1} K, Tinv = (I - B^T S)^{-1} (host, m x m)

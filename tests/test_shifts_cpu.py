@@ -131,3 +131,28 @@ def test_library_rejects_all_unstable_candidates():
     import paper_2607_14742_amd as pk
     with pytest.raises(pk.CareError):
         pk.penzl_select([0.1, 2.0 + 1j, 2.0 - 1j], 4)
+
+
+# ------------------------------------------------- Wachspress real shift sets
+@pytest.mark.parametrize("lo,hi,J", [(69.74, 2.008e6, 12), (1.0, 1e3, 5), (3.0, 40.0, 3)])
+def test_wachspress_shifts_equioscillate(lo, hi, J):
+    # the minimax rational function prod (l - p)/(l + p) over [lo, hi] has
+    # |r| equal at its J + 1 extremal points: both ends and one point
+    # between each pair of neighbouring shifts (Chebyshev alternation)
+    p = -wl.wachspress_real_shifts(lo, hi, J).real
+    assert p.size == J and np.all(np.diff(p) < 0) and lo <= p.min() and p.max() <= hi
+    lam = np.geomspace(lo, hi, 400001)
+    r = np.ones_like(lam)
+    for pj in p:
+        r *= (lam - pj) / (lam + pj)
+    a = np.abs(r)
+    inner = np.nonzero((a[1:-1] > a[:-2]) & (a[1:-1] >= a[2:]))[0] + 1
+    ext = np.concatenate([[a[0]], a[inner], [a[-1]]])
+    assert ext.size == J + 1
+    assert ext.max() / ext.min() - 1 < 1e-4
+    # and a log-spaced set of the same size does worse
+    q = np.geomspace(lo, hi, J)
+    rq = np.ones_like(lam)
+    for qj in q:
+        rq *= (lam - qj) / (lam + qj)
+    assert np.abs(rq).max() > ext.max()

@@ -1,7 +1,9 @@
 """Seeded synthetic inputs shared by the CPU oracle and the HIP path.
 
 This module only builds problem data (sparse A, dense B and C, shift sets
-chosen from closed-form spectral bounds).  It holds none of the method's
+chosen from closed-form spectral bounds).  A shift set is an input of the
+method (the paper's heuristic is implemented on both sides separately); the
+real sets here only need the spectral interval.  It holds none of the method's
 arithmetic: no Riccati/Lyapunov algebra, no ADI, no factor decompositions.
 
 Problem families (the paper's workloads and the synthetic stand-ins for the
@@ -202,6 +204,25 @@ def logspaced_real_shifts(lo: float, hi: float, count: int, descending: bool = T
     return -s.astype(np.complex128)
 
 
+def wachspress_real_shifts(lo: float, hi: float, count: int) -> np.ndarray:
+    """`count` negative real ADI shifts for a real spectrum with magnitudes in
+    [lo, hi]: the parameters that minimise max over lambda in [lo, hi] of
+    prod_j |lambda - p_j| / |lambda + p_j| (Zolotarev's third problem, solved
+    by Wachspress with Jacobi elliptic functions):
+    p_j = hi dn((2j - 1) K / (2 count), k), j = 1..count, with modulus
+    k = sqrt(1 - (lo/hi)^2) and K = K(k) the complete elliptic integral of
+    the first kind.  dn falls from 1 at u = 0 to lo/hi at u = K, so the set
+    starts at the largest magnitude (the order used for the log-spaced sets).
+    Returned as complex128 (imaginary part 0)."""
+    from scipy.special import ellipj, ellipk   # parameter m = k^2
+    if not (0 < lo <= hi) or count < 1:
+        raise ValueError("need 0 < lo <= hi and count >= 1")
+    m = 1.0 - (lo / hi) ** 2
+    u = (2.0 * np.arange(1, count + 1) - 1.0) * ellipk(m) / (2.0 * count)
+    dn = ellipj(u, m)[2]
+    return -(hi * dn).astype(np.complex128)
+
+
 # ----------------------------------------------------------------------------
 # named configurations
 # ----------------------------------------------------------------------------
@@ -220,15 +241,21 @@ class Problem:
 
 
 def fdm2d_problem(N: int, m: int, p: int, nu: float = 10.0, seed: int = DEFAULT_SEED,
-                  nshifts: int = 16, name: str = None) -> Problem:
-    """2D FDM CARE with Gaussian B, C and log-spaced real shifts over the
-    closed-form spectral interval."""
+                  nshifts: int = 12, name: str = None, shift_set: str = "wachspress") -> Problem:
+    """2D FDM CARE with Gaussian B, C and real shifts for the closed-form
+    spectral interval: ``nshifts`` Wachspress (minimax) shifts by default,
+    or log-spaced ones (``shift_set="logspaced"``)."""
     A = fdm2d(N, nu)
     B, C = gaussian_factors(N * N, m, p, seed)
     lo, hi = fdm2d_spectral_bounds(N, nu)
-    return Problem(name or f"fdm2d_N{N}_m{m}_p{p}", A, B, C,
-                   logspaced_real_shifts(lo, hi, nshifts),
-                   dict(N=N, nu=nu, seed=seed, lam_lo=lo, lam_hi=hi))
+    if shift_set == "wachspress":
+        shifts = wachspress_real_shifts(lo, hi, nshifts)
+    elif shift_set == "logspaced":
+        shifts = logspaced_real_shifts(lo, hi, nshifts)
+    else:
+        raise ValueError(f"unknown shift set {shift_set!r}")
+    return Problem(name or f"fdm2d_N{N}_m{m}_p{p}", A, B, C, shifts,
+                   dict(N=N, nu=nu, seed=seed, lam_lo=lo, lam_hi=hi, shift_set=shift_set))
 
 
 def fdm3d_problem(N: int, m: int, p: int, nu: float = 100.0, field_kind: str = "rotating",
@@ -279,6 +306,6 @@ def fdm_batch_sizes(count: int = 32, seed: int = DEFAULT_SEED):
 
 def fdm_batch_problem(i: int, count: int = 32, seed: int = DEFAULT_SEED) -> Problem:
     """Instance i of the uneven FDM batch: grid N_i, (m_i, p_i) from
-    ``fdm_batch_sizes``, Gaussian factors from seed + i, 16 shifts."""
+    ``fdm_batch_sizes``, Gaussian factors from seed + i, 12 Wachspress shifts."""
     Ns, ms, ps = fdm_batch_sizes(count, seed)
     return fdm2d_problem(Ns[i], ms[i], ps[i], seed=seed + i, name=f"batch{i}_fdm2d_{Ns[i]}")
