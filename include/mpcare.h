@@ -150,6 +150,10 @@ typedef struct {
                              on BiCGStab); krylov_maxit then counts Arnoldi steps  */
   int32_t krylov_restart; /* GMRES restart length; <= 0 selects 30 (FP32) / 50 (FP64),
                              the values of Sec. 5                                   */
+  int32_t krylov_compact; /* BiCGStab: 1 (default) gathers the columns still
+                             iterating into fewer 16-column panels whenever they
+                             fit in fewer (same arithmetic per column, same
+                             results); 0: every column stays in place              */
 } care_opts;
 
 /* Statistics written by the solvers (host struct). */
@@ -169,6 +173,7 @@ typedef struct {
   int32_t hist_len;                   /* entries of res_hist used                      */
   double res_hist[48];                /* relative residual after each outer step      */
   int32_t inner_prec;                 /* inner precision used (CARE_AUTO resolved)     */
+  int32_t krylov_compactions;         /* BiCGStab column compactions (krylov_compact)  */
 } care_stats;
 
 /* ---------------------------------------------------------------------- */

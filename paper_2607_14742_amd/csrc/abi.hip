@@ -98,6 +98,7 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->shift_update = 0;
   o->krylov_method = 0;
   o->krylov_restart = 0;
+  o->krylov_compact = 1;
   o->profile = 0;
   o->Z_init = nullptr;
   o->ldz_init = 0;
@@ -176,6 +177,7 @@ care_status care_shifted_solve(care_ctx* cx, const care_csr* A, const double* B,
     const int64_t n = A->n, ld = pad_ld(n);
     if (w < 0 || m < 0) fail(CARE_ERR_ARG, "w and m must be >= 0");
     ctx->krylov_method = 0;   // this entry point documents BiCGStab
+    ctx->krylov_compact = 1;
     if (w == 0) return CARE_OK;
     if (!W || !V || ldw < n || ldv < n) fail(CARE_ERR_ARG, "invalid W / V");
     const bool smw = K != nullptr && m > 0;
@@ -279,6 +281,7 @@ care_status lyap_lradi(care_ctx* cx, const care_csr* A, const double* B, const d
     ctx->spmm_tune = o->spmm_tune;
     ctx->krylov_method = o->krylov_method;
     ctx->krylov_restart = o->krylov_restart;
+    ctx->krylov_compact = o->krylov_compact;
     const double t0 = now_s();
     SellOp op;
     build_sell(ctx, A, r.prec, op);
@@ -318,6 +321,7 @@ care_status lyap_lradi(care_ctx* cx, const care_csr* A, const double* B, const d
       stats->spmm_bytes = ctx->spmm_bytes;
       stats->t_spmm = ctx->t_spmm;
       stats->krylov_iters = ctx->krylov_iters;
+      stats->krylov_compactions = (int32_t)ctx->krylov_compactions;
       stats->hist_len = 1;
       stats->res_hist[0] = lo.res_rel;
     }

@@ -337,6 +337,7 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   ctx->spmm_tune = opts ? opts->spmm_tune : 1;
   ctx->krylov_method = opts ? opts->krylov_method : 0;
   ctx->krylov_restart = opts ? opts->krylov_restart : 0;
+  ctx->krylov_compact = opts ? opts->krylov_compact : 1;
   if (ctx->krylov_method < 0 || ctx->krylov_method > 1) fail(CARE_ERR_ARG, "krylov_method must be 0 or 1");
 
   SellOp A64, As;
@@ -541,6 +542,7 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   st->spmm_bytes = ctx->spmm_bytes;
   st->t_spmm = ctx->t_spmm;
   st->krylov_iters = ctx->krylov_iters;
+  st->krylov_compactions = (int32_t)ctx->krylov_compactions;
   (void)last_res;
   if (!converged) *warn = stagnated ? CARE_WARN_STAGNATED : CARE_WARN_MAXIT;
 }

@@ -110,9 +110,11 @@ struct Ctx {
   int spmm_tune = 0;                // 1: time the panel widths of a product shape once, keep the faster
   int krylov_method = 0;            // shifted solves: 0 BiCGStab, 1 restarted GMRES (real shifts)
   int krylov_patient = 0;           // BiCGStab stagnation window max(1000, it/2) (unshifted solves)
+  int krylov_compact = 1;           // BiCGStab: gather the still-active columns into fewer panels
   int krylov_restart = 0;           // GMRES restart length (0: 30 in FP32, 50 in FP64)
   double t_spmm = 0.0;
   int64_t krylov_iters = 0;
+  int64_t krylov_compactions = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_events;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
   void reset_counters() {
@@ -120,6 +122,7 @@ struct Ctx {
     spmm_bytes = 0;
     t_spmm = 0;
     krylov_iters = 0;
+    krylov_compactions = 0;
   }
   void* host_stage(size_t bytes);  // pinned buffer of at least `bytes`
   void sync();                     // stream synchronize + harvest profile events

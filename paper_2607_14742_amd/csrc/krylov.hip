@@ -544,7 +544,9 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
   const int64_t ld = pad_ld(n);
   const char* tr_env = std::getenv("MPCARE_TRACE");
   const bool trace = tr_env && std::atoi(tr_env) >= 2;
-  const int nl = cplx ? ncols / 2 : ncols;
+  int nl = cplx ? ncols / 2 : ncols;
+  const int per = cplx ? 2 : 1;
+  const int nl0 = nl;
   const int nrb = spmm_rowblocks(n);
   const size_t panel = (size_t)ld * ncols;
   DBuf<T> r(ctx, panel), P0(ctx, panel), P1(ctx, panel), V0(ctx, panel), V1(ctx, panel), S(ctx, panel),
@@ -556,6 +558,23 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
   T* Pb[2] = {P0.get(), P1.get()};
   T* Vb[2] = {V0.get(), V1.get()};
   const double tol2 = tol * tol;
+  // Column compaction: once the columns still iterating fit in fewer
+  // 16-column panels, they are gathered to the front of fresh panels and the
+  // solve continues on those alone (the sparse products and elementwise
+  // passes work in panels, and a panel with one active column costs nearly as
+  // much as a full one).  Every column's arithmetic is unchanged.  orig[c]: the caller's logical
+  // column of working column c; xcur / bcur: the working x and right-hand
+  // side (the caller's arrays until the first compaction); fsc / fst: final
+  // scalars and status of the columns that left the working set.
+  std::vector<int> orig(nl);
+  for (int c = 0; c < nl; ++c) orig[c] = c;
+  T* xcur = x;
+  int64_t ldxcur = ldx;
+  const T* bcur = b;
+  int64_t ldbcur = ldb;
+  DBuf<T> xw, bw;
+  std::vector<double> fsc((size_t)nl0 * KS);
+  std::vector<int> fst((size_t)nl0 * KI);
 
   ElemArgs<T> ea;
   ea.n = (int)n;
@@ -631,8 +650,8 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
     a1.vold = Vb[it & 1];
     a1.pnew = Pb[(it + 1) & 1];
     a1.vnew = Vb[(it + 1) & 1];
-    a1.rhat = b;
-    a1.ldrhat = ldb;
+    a1.rhat = bcur;
+    a1.ldrhat = ldbcur;
     a1.sc = sc.get();
     a1.st = st.get();
     a1.part = part.get();
@@ -691,12 +710,95 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
     first_chunk = false;
   };
   auto poll = [&]() {
-    ckpt<T, false>(ctx, cplx, (int)n, ncols, x, ldx, Xb.get(), ld, sc.get(), st.get());
+    ckpt<T, false>(ctx, cplx, (int)n, ncols, xcur, ldxcur, Xb.get(), ld, sc.get(), st.get());
     d2h(ctx, hst.data(), st.get(), hst.size() * sizeof(int));
     int active = 0;
     for (int c = 0; c < nl; ++c) active += hst[(size_t)c * KI + KI_ACTIVE];
     account(active);
     done = active == 0;
+  };
+  // Compaction at a poll (hst holds the status of the working columns; `it`
+  // iterations are done, so p and v live in Pb[it & 1], Vb[it & 1]).
+  auto compact = [&]() -> bool {
+    if (!ctx->krylov_compact) return false;
+    std::vector<int> keep;
+    for (int c = 0; c < nl; ++c)
+      if (hst[(size_t)c * KI + KI_ACTIVE]) keep.push_back(c);
+    const int na = (int)keep.size();
+    if (na == 0 || ceil_div(na * per, 16) >= ceil_div(nl * per, 16)) return false;   // no panel saved
+    std::vector<double> hs((size_t)nl * KS);
+    d2h(ctx, hs.data(), sc.get(), hs.size() * sizeof(double));
+    // columns leaving the working set are final: their scalars are kept, and
+    // x (or the better checkpoint, as the final restore would choose it) goes
+    // to the caller's column
+    for (int c = 0; c < nl; ++c) {
+      if (hst[(size_t)c * KI + KI_ACTIVE]) continue;
+      const int o = orig[c];
+      std::copy(hs.begin() + (size_t)c * KS, hs.begin() + (size_t)(c + 1) * KS, fsc.begin() + (size_t)o * KS);
+      std::copy(hst.begin() + (size_t)c * KI, hst.begin() + (size_t)(c + 1) * KI, fst.begin() + (size_t)o * KI);
+      const double* v = &hs[(size_t)c * KS];
+      const bool restore = hst[(size_t)c * KI + KI_FLAG] != FLAG_CONVERGED && v[KS_RCKPT] < v[KS_RNRM2];
+      for (int e = 0; e < per; ++e) {
+        const T* src = restore ? Xb.get() + (int64_t)(c * per + e) * ld : xcur + (int64_t)(c * per + e) * ldxcur;
+        d2d(ctx, x + (int64_t)(o * per + e) * ldx, src, (size_t)n * sizeof(T));
+      }
+    }
+    const int ncn = na * per;
+    std::vector<int> map(ncn);
+    for (int j = 0; j < na; ++j)
+      for (int e = 0; e < per; ++e) map[j * per + e] = keep[j] * per + e;
+    auto gather = [&](const T* src, int64_t lds) {
+      DBuf<T> t(ctx, (size_t)ld * ncn);
+      copy_cols<T, T>(ctx, n, ncn, src, lds, t.get(), ld, map.data());
+      return t;
+    };
+    const int cur = it & 1;
+    DBuf<T> nr = gather(r.get(), ld), np = gather(Pb[cur], ld), nv = gather(Vb[cur], ld);
+    DBuf<T> nxb = gather(Xb.get(), ld), nx = gather(xcur, ldxcur), nb = gather(bcur, ldbcur);
+    r = std::move(nr);
+    Xb = std::move(nxb);
+    xw = std::move(nx);
+    bw = std::move(nb);
+    if (cur == 0) {
+      P0 = std::move(np);
+      V0 = std::move(nv);
+    } else {
+      P1 = std::move(np);
+      V1 = std::move(nv);
+    }
+    Pb[0] = P0.get();
+    Pb[1] = P1.get();
+    Vb[0] = V0.get();
+    Vb[1] = V1.get();
+    xcur = xw.get();
+    ldxcur = ld;
+    bcur = bw.get();
+    ldbcur = ld;
+    std::vector<double> hs2((size_t)na * KS);
+    std::vector<int> hi2((size_t)na * KI);
+    std::vector<int> no(na);
+    for (int j = 0; j < na; ++j) {
+      std::copy(hs.begin() + (size_t)keep[j] * KS, hs.begin() + (size_t)(keep[j] + 1) * KS, hs2.begin() + (size_t)j * KS);
+      std::copy(hst.begin() + (size_t)keep[j] * KI, hst.begin() + (size_t)(keep[j] + 1) * KI,
+                hi2.begin() + (size_t)j * KI);
+      no[j] = orig[keep[j]];
+    }
+    h2d(ctx, sc.get(), hs2.data(), hs2.size() * sizeof(double));
+    h2d(ctx, st.get(), hi2.data(), hi2.size() * sizeof(int));
+    orig = no;
+    nl = na;
+    ncols = ncn;
+    hst.assign((size_t)nl * KI, 0);
+    std::copy(hi2.begin(), hi2.end(), hst.begin());
+    ea.ncols = ncols;
+    ea.b = bcur;
+    ea.ldb = ldbcur;
+    ea.x = xcur;
+    ea.ldx = ldxcur;
+    ea.r = r.get();
+    res.compactions += 1;
+    ctx->krylov_compactions += 1;
+    return true;
   };
   // first check_every iterations (and everything when profiling) launched
   // directly; the steady state replays a captured chunk of CHUNK iterations
@@ -712,6 +814,7 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
     if (it >= next_check || it >= maxit) {
       poll();
       next_check = it + check_every;
+      if (!done && it < maxit) compact();
     }
   }
   account(0);
@@ -721,40 +824,62 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
       iteration(it);
       ++it;
     }
-    const int64_t calls0 = ctx->spmm_calls;
-    const double bytes0 = ctx->spmm_bytes;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    HIP_CHECK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    for (int c = 0; c < CHUNK; ++c) iteration(it + c);
-    ckpt<T, false>(ctx, cplx, (int)n, ncols, x, ldx, Xb.get(), ld, sc.get(), st.get());
-    HIP_CHECK(hipStreamEndCapture(ctx->stream, &graph));
-    const int64_t dcalls = ctx->spmm_calls - calls0;
-    const double dbytes = ctx->spmm_bytes - bytes0;
-    ctx->spmm_calls = calls0;
-    ctx->spmm_bytes = bytes0;
-    HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    while (it < maxit && !done) {
-      HIP_CHECK(hipGraphLaunch(exec, ctx->stream));
-      it += CHUNK;
-      ctx->spmm_calls += dcalls;
-      ctx->spmm_bytes += dbytes;
-      d2h(ctx, hst.data(), st.get(), hst.size() * sizeof(int));
-      int active = 0;
-      for (int c = 0; c < nl; ++c) active += hst[(size_t)c * KI + KI_ACTIVE];
-      done = active == 0;
+    // a compaction changes the launches: the chunk is captured again (the
+    // polls stay every CHUNK iterations, so the checkpoints are those of an
+    // uncompacted solve)
+    bool recapture = true;
+    while (recapture && !done && it < maxit) {
+      recapture = false;
+      const int64_t calls0 = ctx->spmm_calls;
+      const double bytes0 = ctx->spmm_bytes;
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      HIP_CHECK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+      for (int c = 0; c < CHUNK; ++c) iteration(it + c);
+      ckpt<T, false>(ctx, cplx, (int)n, ncols, xcur, ldxcur, Xb.get(), ld, sc.get(), st.get());
+      HIP_CHECK(hipStreamEndCapture(ctx->stream, &graph));
+      const int64_t dcalls = ctx->spmm_calls - calls0;
+      const double dbytes = ctx->spmm_bytes - bytes0;
+      ctx->spmm_calls = calls0;
+      ctx->spmm_bytes = bytes0;
+      HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      while (it < maxit && !done) {
+        HIP_CHECK(hipGraphLaunch(exec, ctx->stream));
+        it += CHUNK;
+        ctx->spmm_calls += dcalls;
+        ctx->spmm_bytes += dbytes;
+        d2h(ctx, hst.data(), st.get(), hst.size() * sizeof(int));
+        int active = 0;
+        for (int c = 0; c < nl; ++c) active += hst[(size_t)c * KI + KI_ACTIVE];
+        done = active == 0;
+        if (!done && it < maxit && compact()) {
+          recapture = true;
+          break;
+        }
+      }
+      (void)hipGraphExecDestroy(exec);
+      (void)hipGraphDestroy(graph);
     }
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
   }
   // columns that stopped without converging fall back to their best checkpoint
-  ckpt<T, true>(ctx, cplx, (int)n, ncols, x, ldx, Xb.get(), ld, sc.get(), st.get());
-  std::vector<double> hsc((size_t)nl * KS);
-  d2h(ctx, hsc.data(), sc.get(), hsc.size() * sizeof(double));
-  d2h(ctx, hst.data(), st.get(), hst.size() * sizeof(int));
-  for (int c = 0; c < nl; ++c) {
-    const int* s = &hst[(size_t)c * KI];
-    const double* v = &hsc[(size_t)c * KS];
+  ckpt<T, true>(ctx, cplx, (int)n, ncols, xcur, ldxcur, Xb.get(), ld, sc.get(), st.get());
+  {
+    std::vector<double> hsc((size_t)nl * KS);
+    d2h(ctx, hsc.data(), sc.get(), hsc.size() * sizeof(double));
+    d2h(ctx, hst.data(), st.get(), hst.size() * sizeof(int));
+    for (int c = 0; c < nl; ++c) {
+      const int o = orig[c];
+      std::copy(hsc.begin() + (size_t)c * KS, hsc.begin() + (size_t)(c + 1) * KS, fsc.begin() + (size_t)o * KS);
+      std::copy(hst.begin() + (size_t)c * KI, hst.begin() + (size_t)(c + 1) * KI, fst.begin() + (size_t)o * KI);
+      if (xcur != x)
+        for (int e = 0; e < per; ++e)
+          d2d(ctx, x + (int64_t)(o * per + e) * ldx, xcur + (int64_t)(c * per + e) * ldxcur, (size_t)n * sizeof(T));
+    }
+    ctx->sync();
+  }
+  for (int c = 0; c < nl0; ++c) {
+    const int* s = &fst[(size_t)c * KI];
+    const double* v = &fsc[(size_t)c * KS];
     res.max_iters = std::max(res.max_iters, s[KI_ITERS]);
     ctx->krylov_iters += s[KI_ITERS];
     const double rfin = s[KI_FLAG] == FLAG_CONVERGED ? v[KS_RNRM2] : std::min(v[KS_RNRM2], v[KS_RCKPT]);

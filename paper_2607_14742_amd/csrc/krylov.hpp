@@ -15,6 +15,7 @@ struct KrylovResult {
   int unconverged = 0;      // columns that stopped above tol
   int breakdown = 0;        // columns stopped by a breakdown
   int restarts = 0;         // restart rounds performed
+  int compactions = 0;      // times the still-active columns were gathered into fewer panels
   double worst_relres = 0;  // largest ||r|| / ||b|| at exit (recursive residual)
   std::vector<int> col_ok;          // per logical column: reached its tolerance
   std::vector<double> col_relres;   // per logical column: ||r|| / ||b||
