@@ -154,6 +154,12 @@ typedef struct {
                              iterating into fewer 16-column panels whenever they
                              fit in fewer (same arithmetic per column, same
                              results); 0: every column stays in place              */
+  int32_t adi_rotate;     /* with adi_deflate: 1 (default) turns the active columns
+                             of the LR-ADI residual factor W (within the C+ and C-
+                             groups of a correction) to their principal directions
+                             each time the ADI residual has halved, so that the
+                             column freezing can take the directions the residual
+                             has left; 0: W is never rotated                       */
 } care_opts;
 
 /* Statistics written by the solvers (host struct). */
@@ -174,6 +180,7 @@ typedef struct {
   double res_hist[48];                /* relative residual after each outer step      */
   int32_t inner_prec;                 /* inner precision used (CARE_AUTO resolved)     */
   int32_t krylov_compactions;         /* BiCGStab column compactions (krylov_compact)  */
+  int32_t adi_rotations;              /* rotations of an LR-ADI residual factor group  */
 } care_stats;
 
 /* ---------------------------------------------------------------------- */

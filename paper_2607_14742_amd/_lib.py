@@ -40,6 +40,7 @@ class care_opts(C.Structure):
         ("spmm_split", C.c_int32), ("krylov_relax", C.c_int32), ("refine_forcing", C.c_double),
         ("tau_L0", C.c_double), ("spmm_tune", C.c_int32), ("shift_update", C.c_int32),
         ("krylov_method", C.c_int32), ("krylov_restart", C.c_int32), ("krylov_compact", C.c_int32),
+        ("adi_rotate", C.c_int32),
     ]
 
 
@@ -51,7 +52,7 @@ class care_stats(C.Structure):
         ("t_total", C.c_double), ("t_stage0", C.c_double), ("t_refine", C.c_double), ("t_setup", C.c_double),
         ("spmm_calls", C.c_int64), ("spmm_bytes", C.c_double), ("t_spmm", C.c_double),
         ("krylov_iters", C.c_int64), ("hist_len", C.c_int32), ("res_hist", C.c_double * 48),
-        ("inner_prec", C.c_int32), ("krylov_compactions", C.c_int32),
+        ("inner_prec", C.c_int32), ("krylov_compactions", C.c_int32), ("adi_rotations", C.c_int32),
     ]
 
     def to_dict(self):

@@ -99,6 +99,7 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->krylov_method = 0;
   o->krylov_restart = 0;
   o->krylov_compact = 1;
+  o->adi_rotate = 1;
   o->profile = 0;
   o->Z_init = nullptr;
   o->ldz_init = 0;
@@ -322,6 +323,7 @@ care_status lyap_lradi(care_ctx* cx, const care_csr* A, const double* B, const d
       stats->t_spmm = ctx->t_spmm;
       stats->krylov_iters = ctx->krylov_iters;
       stats->krylov_compactions = (int32_t)ctx->krylov_compactions;
+      stats->adi_rotations = (int32_t)ctx->adi_rotations;
       stats->hist_len = 1;
       stats->res_hist[0] = lo.res_rel;
     }

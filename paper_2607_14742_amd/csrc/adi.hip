@@ -103,6 +103,57 @@ __global__ void __launch_bounds__(256) k_adi_update(int64_t n, int w, int m, int
 }
 
 // ||W^T W||_F and the squared column norms of W
+// Eigenvectors of a small symmetric matrix A (k x k, column-major) by the
+// cyclic Jacobi method (Golub and Van Loan, Sec. 8.5): rotations J(p, q)
+// that zero a_pq are applied as A <- J^T A J and accumulated in Q <- Q J
+// until the off-diagonal part is below 1e-15 of the diagonal.  Q returns
+// the eigenvectors as columns (column-major); false if Q failed the
+// orthogonality check.
+static bool jacobi_eig(int k, std::vector<double> A, std::vector<double>& Q) {
+  auto a = [&](int r, int c) -> double& { return A[(size_t)c * k + r]; };
+  Q.assign((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) Q[(size_t)i * k + i] = 1.0;
+  auto q = [&](int r, int c) -> double& { return Q[(size_t)c * k + r]; };
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int c = 0; c < k; ++c)
+      for (int r = 0; r < k; ++r) (r == c ? dia : off) += a(r, c) * a(r, c);
+    if (off <= 1e-30 * dia) break;
+    for (int p = 0; p < k - 1; ++p)
+      for (int r = p + 1; r < k; ++r) {
+        const double apq = a(p, r);
+        if (apq == 0.0) continue;
+        const double tau = (a(r, r) - a(p, p)) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = t * cs;
+        for (int i = 0; i < k; ++i) {   // columns p and r: A J
+          const double x = a(i, p), y = a(i, r);
+          a(i, p) = cs * x - sn * y;
+          a(i, r) = sn * x + cs * y;
+        }
+        for (int i = 0; i < k; ++i) {   // rows p and r: J^T A
+          const double x = a(p, i), y = a(r, i);
+          a(p, i) = cs * x - sn * y;
+          a(r, i) = sn * x + cs * y;
+        }
+        for (int i = 0; i < k; ++i) {   // Q J
+          const double x = q(i, p), y = q(i, r);
+          q(i, p) = cs * x - sn * y;
+          q(i, r) = sn * x + cs * y;
+        }
+      }
+  }
+  for (int c = 0; c < k; ++c)
+    for (int d = 0; d <= c; ++d) {
+      double s = 0.0;
+      for (int i = 0; i < k; ++i) s += q(i, c) * q(i, d);
+      if (std::fabs(s - (c == d ? 1.0 : 0.0)) > 1e-12) return false;
+    }
+  return true;
+}
+
+constexpr int ROTATE_MIN_ITERS = 20;
+
 template <typename T>
 static double gram_stats(Ctx* ctx, int64_t n, const T* W, int64_t ld, int w, std::vector<double>& colnorm2,
                          std::vector<double>* full = nullptr) {
@@ -230,6 +281,7 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
 
   size_t idx = 0;
   LradiParams sp = prm;   // per-step copy (Krylov tolerance)
+  double rot_ref = 1.0;   // residual level of the last rotation of W
   while (out.steps < prm.jmax && wa > 0) {
     const Shift p = shifts[idx % shifts.size()];
     ShiftCache& sc = cache[idx % shifts.size()];
@@ -286,6 +338,51 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
                    kr.worst_relres, out.res_rel);
     if (out.res_rel > 1e8) fail(CARE_ERR_UNSTABLE, "LR-ADI diverged (is A - B K^T stable?)");
     if (out.res_rel <= prm.tol) break;
+    if (budget > 0.0 && prm.rotate && wa > 1 && out.res_rel <= 0.5 * rot_ref && kr.max_iters >= ROTATE_MIN_ITERS) {
+      // Rotation of W: any W Q with Q orthogonal is a residual factor of the
+      // same residual (W Q Q^T W^T = W W^T), so the next step may start from
+      // it.  Each time the ADI residual has halved, the active columns of
+      // each group (the factors of C+ and C- in a correction are not mixed)
+      // are turned to the eigenvectors of their Gram.  The residual's energy
+      // then sits in few columns that hold the slowly converging smooth
+      // modes; the other columns converge in few Krylov iterations even at
+      // the small shifts (and leave the block solve early, which the
+      // compaction turns into fewer panels), and the freezing below can
+      // take them once they are small enough.  Where the shifted solves
+      // converge in a few iterations anyway (well-conditioned shifted
+      // matrices) there is nothing to gain, so the rotation waits for a step
+      // whose solves took ROTATE_MIN_ITERS iterations or more.
+      rot_ref = out.res_rel;
+      bool rotated = false;
+      for (int g = 0; g < 2; ++g) {
+        std::vector<int> I;
+        for (int c = 0; c < wa; ++c)
+          if ((prm.group_split > 0 && perm[c] >= prm.group_split ? 1 : 0) == g) I.push_back(c);
+        const int k = (int)I.size();
+        if (k < 2) continue;
+        std::vector<double> Gg((size_t)k * k);
+        for (int j = 0; j < k; ++j)
+          for (int i = 0; i < k; ++i) Gg[(size_t)j * k + i] = gfull[(size_t)I[j] * w + I[i]];
+        DBuf<double> dG(ctx, (size_t)k * k);
+        if (k <= 32) {
+          // small groups: cyclic Jacobi on the host (no device round trip)
+          std::vector<double> Q;
+          if (!jacobi_eig(k, Gg, Q)) continue;
+          h2d(ctx, dG.get(), Q.data(), Q.size() * sizeof(double));
+        } else {
+          h2d(ctx, dG.get(), Gg.data(), Gg.size() * sizeof(double));
+          std::vector<double> ev;
+          dsyevd(ctx, k, dG.get(), k, ev);
+        }
+        DBuf<T> Wg(ctx, (size_t)ld * k), Wr(ctx, (size_t)ld * k);
+        copy_cols<T, T>(ctx, n, k, W, ld, Wg.get(), ld, I.data());
+        tsgemm<T, T>(ctx, n, Wg.get(), ld, k, dG.get(), k, k, 1.0, 0.0, Wr.get(), ld);
+        for (int j = 0; j < k; ++j) d2d(ctx, W + (int64_t)I[j] * ld, Wr.get() + (int64_t)j * ld, (size_t)n * sizeof(T));
+        rotated = true;
+        ctx->adi_rotations += 1;
+      }
+      if (rotated) gram_stats(ctx, n, W, ld, w, cn, &gfull);
+    }
     if (budget > 0.0) {
       // freeze the smallest active columns while the frozen budget allows
       std::vector<int> order(wa);

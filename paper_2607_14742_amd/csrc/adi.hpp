@@ -32,6 +32,8 @@ struct LradiParams {
   bool deflate = true;       // freeze converged columns of W (see lradi_run)
   bool group_tol = true;     // Krylov accuracy relative to the block's largest column
   bool relax = false;        // inexact ADI: looser solves as the ADI residual shrinks (lradi_run)
+  bool rotate = false;       // with deflate: rotate W to its principal directions (lradi_run)
+  int group_split = 0;       // W0 columns [0, group_split) and the rest form separate groups
 };
 
 struct LradiOut {

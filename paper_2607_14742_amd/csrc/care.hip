@@ -48,6 +48,7 @@ Resolved resolve_opts(const care_opts* o, double tol) {
   r.kmaxit = o->krylov_maxit > 0 ? o->krylov_maxit : 4000;
   r.check_every = o->check_every > 0 ? o->check_every : 8;
   r.deflate = o->adi_deflate != 0;
+  r.rotate = o->adi_rotate != 0;
   r.block_tol = o->krylov_block_tol != 0;
   r.relax = o->krylov_relax != 0;
   if (r.k_max < 1 || r.k0_max < 1 || r.j_max < 1) fail(CARE_ERR_ARG, "k_max, k0_max and j_max must be >= 1");
@@ -170,6 +171,7 @@ static void stage0(Ctx* ctx, SolveState& S, TruncResult& Zout, care_stats* st, s
   lp.kmaxit = S.prm.kmaxit;
   lp.check_every = S.prm.check_every;
   lp.deflate = S.prm.deflate;
+  lp.rotate = S.prm.deflate && S.prm.rotate && S.prm.prec != Prec::F64;
   lp.group_tol = S.prm.block_tol;
   lp.relax = S.prm.relax;
   double prev = 0.0;
@@ -254,6 +256,8 @@ static void correction(Ctx* ctx, SolveState& S, const TruncResult& Zk, const Res
   lp.kmaxit = S.prm.kmaxit;
   lp.check_every = S.prm.check_every;
   lp.deflate = S.prm.deflate;
+  lp.rotate = S.prm.deflate && S.prm.rotate && S.prm.prec != Prec::F64;
+  lp.group_split = rf.rp;
   lp.group_tol = S.prm.block_tol;
   lp.relax = S.prm.relax;
   const std::vector<Shift> sh = shifts_for(ctx, S, (m > 0 && Zk.r > 0) ? K64.get() : nullptr);
@@ -543,6 +547,7 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   st->t_spmm = ctx->t_spmm;
   st->krylov_iters = ctx->krylov_iters;
   st->krylov_compactions = (int32_t)ctx->krylov_compactions;
+  st->adi_rotations = (int32_t)ctx->adi_rotations;
   (void)last_res;
   if (!converged) *warn = stagnated ? CARE_WARN_STAGNATED : CARE_WARN_MAXIT;
 }

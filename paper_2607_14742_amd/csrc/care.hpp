@@ -12,7 +12,7 @@ struct Resolved {
   double tau_L = 1e-12, tau_L0 = 1e-12, tau_0 = 1e-10, ktol = 1e-10, theta = 0.25;
   double eta_r_rel = 1e-4, eta_s_rel = 1.1102230246251565e-15, stagnation = 0.999;
   int k_max = 20, k0_max = 20, j_max = 50, kmaxit = 4000, check_every = 8;
-  bool deflate = true, block_tol = false, relax = false;
+  bool deflate = true, block_tol = false, relax = false, rotate = true;
 };
 
 Resolved resolve_opts(const care_opts* o, double tol);

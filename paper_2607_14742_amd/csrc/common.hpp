@@ -115,6 +115,7 @@ struct Ctx {
   double t_spmm = 0.0;
   int64_t krylov_iters = 0;
   int64_t krylov_compactions = 0;
+  int64_t adi_rotations = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_events;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
   void reset_counters() {
@@ -123,6 +124,7 @@ struct Ctx {
     t_spmm = 0;
     krylov_iters = 0;
     krylov_compactions = 0;
+    adi_rotations = 0;
   }
   void* host_stage(size_t bytes);  // pinned buffer of at least `bytes`
   void sync();                     // stream synchronize + harvest profile events
