@@ -105,7 +105,7 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->ldz_init = 0;
   o->r_init = 0;
   o->adi_deflate = 1;
-  o->krylov_block_tol = 0;
+  o->krylov_block_tol = -1;
 }
 
 care_status care_ctx_create(care_ctx** out, int32_t device, void* stream) {

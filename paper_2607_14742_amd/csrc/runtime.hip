@@ -86,7 +86,12 @@ void Arena::put(void* p) {
 // ---------------------------------------------------------------------------
 void* Ctx::host_stage(size_t bytes) {
   if (bytes > pinned_bytes) {
-    if (pinned) HIP_CHECK(hipHostFree(pinned));
+    // an earlier asynchronous host-to-device copy (h2d returns before its
+    // copy has run) may still read the old buffer: wait before freeing it
+    if (pinned) {
+      HIP_CHECK(hipStreamSynchronize(stream));
+      HIP_CHECK(hipHostFree(pinned));
+    }
     pinned = nullptr;
     size_t nb = std::max(bytes, size_t(1) << 20);
     HIP_CHECK(hipHostMalloc(&pinned, nb, hipHostMallocDefault));

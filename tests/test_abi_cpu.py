@@ -79,7 +79,7 @@ def test_opts_defaults_follow_the_paper():
     assert o.tau_L0 == 0.0 and o.refine_forcing == 0.25
     # library choices outside the paper: panel autotuner and column compaction
     # on, BiCGStab inner solves, one shift set for the whole solve
-    assert o.spmm_tune == 1 and o.krylov_compact == 1 and o.adi_rotate == 1 and o.krylov_block_tol == 0
+    assert o.spmm_tune == 1 and o.krylov_compact == 1 and o.adi_rotate == 1 and o.krylov_block_tol == -1
     assert o.krylov_method == 0 and o.shift_update == 0
 
 
