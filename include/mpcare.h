@@ -119,9 +119,9 @@ typedef struct {
                              is negligible for the stopping test (default 1)       */
   int32_t krylov_block_tol; /* 1: Krylov accuracy relative to the largest column of
                              the right-hand side block instead of each column (0);
-                             -1 (default): 1 for FP32 / bf16 inner solves (their
-                             LR-ADI residual factor is rotated, so most columns
-                             are small), 0 for FP64                                */
+                             -1 (default): 1 for FP32 inner solves (their LR-ADI
+                             residual factor is rotated, so most columns are
+                             small), 0 for FP64 and bf16 products                  */
   int32_t penzl_real;     /* auto shifts: 1 keeps the real parts of the Ritz values */
   int32_t spmm_split;     /* BiCGStab products: 0 chooses by the L2 footprint of the
                              fused gathers, 1 fused, 2 split (update pass + product) */
