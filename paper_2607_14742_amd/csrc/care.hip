@@ -72,10 +72,11 @@ static double unit_roundoff(Prec p) { return p == Prec::F64 ? U64 : (p == Prec::
 // which spans the spectrum of A (heuristic shifts from Ritz values, or a
 // caller's log-spaced set over the spectral interval), stands in for kappa.
 // Thresholds, both measured here: with iterative shifted solves FP32 pays off
-// only for well-conditioned A.  On the Toeplitz example (spread ~3) FP32 is
-// 1.1x faster; the 3D problem (kappa ~1.7e3) is 1.4x slower and the 2D FDM
-// problem (2.9e4) 2.6x slower.  So FP32 for a spread <= 100.  With direct (LU)
-// shifted solves the paper's Table 1 shows FP32 gains up to kappa = 1e5.
+// clearly only for well-conditioned A.  On the Toeplitz example (spread ~3)
+// FP32 is 1.2-1.3x faster; on the 3D problem (kappa ~1.7e3) and the 2D FDM
+// problem (2.9e4) the two are about level (1.03x faster, 1.1x slower).  So
+// FP32 for a spread <= 100.  With direct (LU) shifted solves the paper's
+// Table 1 shows FP32 gains up to kappa = 1e5.
 double shift_spread(const std::vector<Shift>& shifts) {
   double lo = INFINITY, hi = 0.0;
   for (const Shift& p : shifts) {
