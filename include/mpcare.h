@@ -32,6 +32,7 @@
 #ifndef MPCARE_H
 #define MPCARE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -190,10 +191,30 @@ typedef struct {
 /* Context                                                                  */
 /* ---------------------------------------------------------------------- */
 
+/* Device-memory hooks of a context (the caller's allocator, e.g. a caching
+ * allocator of the framework that owns the device).  alloc returns `bytes`
+ * bytes of device memory of the context's device, usable in work queued on
+ * `stream` (the context's own stream, a hipStream_t passed as void*), or
+ * NULL when it cannot; dealloc returns a block obtained from alloc (same
+ * bytes and stream).  `user` is passed through unchanged.  The hooks may be
+ * called from the thread of any entry point taking the context, and from the
+ * worker threads of care_solve_batch (one call at a time per thread). */
+typedef void* (*care_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*care_dealloc_fn)(void* ptr, size_t bytes, void* stream, void* user);
+
 /* Create a context on `device` that orders all work on `stream` (a
  * hipStream_t passed as void*; NULL = the default stream).  *ctx receives a
- * handle owned by the caller, released with care_ctx_destroy. */
-care_status care_ctx_create(care_ctx** ctx, int32_t device, void* stream);
+ * handle owned by the caller, released with care_ctx_destroy.
+ * Workspace (the boundary passage of the problem statement: the caller owns
+ * inputs and outputs, the library only its workspace): with alloc = dealloc =
+ * NULL the library allocates its device workspace with hipMalloc; with both
+ * set, every device workspace block the library uses is drawn through alloc
+ * and handed back through dealloc (blocks are cached by the context between
+ * calls and all returned by care_ctx_destroy, or earlier when a solve trims
+ * its cache).  The vendor BLAS/LAPACK handle of the context keeps its own
+ * internal scratch.  Exactly one of alloc, dealloc NULL is CARE_ERR_ARG. */
+care_status care_ctx_create(care_ctx** ctx, int32_t device, void* stream, care_alloc_fn alloc,
+                            care_dealloc_fn dealloc, void* user);
 void care_ctx_destroy(care_ctx* ctx);
 
 /* Default options for inner precision `inner_prec`: the values of Sec. 5

@@ -18,6 +18,7 @@ the residual-based LR-ADI of that family, written from its mathematics:
 from __future__ import annotations
 
 import math
+import time
 
 import numpy as np
 import scipy.sparse as sp
@@ -45,10 +46,15 @@ class ShiftedSolver:
             self.K = None
         self._lu = {}
         self._smw = {}
+        # work counters (no effect on the arithmetic): factorizations done and
+        # columns solved, with the seconds spent in each
+        self.counts = dict(factorizations=0, factor_s=0.0, columns=0, solve_s=0.0)
 
     def _factor(self, p):
         key = complex(p)
         if key not in self._lu:
+            t0 = time.perf_counter()
+            self.counts["factorizations"] += 1
             if self.sparse:
                 dt = np.complex128 if key.imag != 0 else np.float64
                 pv = key if key.imag != 0 else key.real
@@ -61,16 +67,23 @@ class ShiftedSolver:
                 M = self.At + pv * np.eye(self.n)
                 f = sla.lu_factor(M)
                 self._lu[key] = lambda rhs, f=f: sla.lu_solve(f, rhs)
+            self.counts["factor_s"] += time.perf_counter() - t0
         return self._lu[key]
 
     def solve_base(self, p, W):
         """M^{-1} W with M = A^T + p I (no feedback term)."""
         solve = self._factor(p)
         Wd = np.asarray(W, dtype=np.complex128 if complex(p).imag != 0 else np.float64)
+        t0 = time.perf_counter()
         if Wd.ndim == 1:
-            return solve(Wd)
-        return np.column_stack([solve(Wd[:, j]) for j in range(Wd.shape[1])]) if Wd.shape[1] else \
-            np.zeros((self.n, 0), dtype=Wd.dtype)
+            out = solve(Wd)
+        elif Wd.shape[1]:
+            out = np.column_stack([solve(Wd[:, j]) for j in range(Wd.shape[1])])
+        else:
+            out = np.zeros((self.n, 0), dtype=Wd.dtype)
+        self.counts["columns"] += 1 if Wd.ndim == 1 else Wd.shape[1]
+        self.counts["solve_s"] += time.perf_counter() - t0
+        return out
 
     def solve(self, p, W):
         """(A_k^T + p I)^{-1} W via SMW."""
@@ -84,6 +97,95 @@ class ShiftedSolver:
             self._smw[key] = (S, T)
         S, T = self._smw[key]
         return Vh + S @ np.linalg.solve(T, self.B.T @ Vh)
+
+
+class KronZShiftedSolver(ShiftedSolver):
+    """The shifted solves of ShiftedSolver for an operator with the Kronecker
+    structure  A = I_Nz (x) A_p + T (x) I_Np  (plane operator A_p of order Np,
+    symmetric Nz x Nz coupling T between planes; planes are the slowest index):
+    the 3D convection-diffusion matrix with a field that has no z-component.
+
+    With T = S diag(mu) S^T (library eigh, S orthogonal),
+      (A^T + p I) = (S (x) I) (I (x) A_p^T + diag(mu) (x) I + p I) (S^T (x) I),
+    so one shifted solve is a transform along z, Nz independent sparse LU
+    solves of order Np with the shifts mu_k + p, and the inverse transform: an
+    exact direct solve (up to rounding) at a fraction of the fill of a 3D LU.
+    The per-plane factorizations are cached per shift in `cache` (a dict that
+    several solvers of one problem may share; they do not depend on K)."""
+
+    def __init__(self, A, B=None, K=None, planes=None, cache=None):
+        super().__init__(A, B, K)
+        self.Ap, self.T = kron_z_split(A, planes)
+        self.nz = self.T.shape[0]
+        self.npl = self.Ap.shape[0]
+        self.mu, self.S = np.linalg.eigh(self.T)
+        self.ApT = sp.csc_matrix(self.Ap.T)
+        self._plane_lu = {} if cache is None else cache
+
+    def _plane_factors(self, p):
+        key = complex(p)
+        if key not in self._plane_lu:
+            cplx = key.imag != 0
+            dt = np.complex128 if cplx else np.float64
+            pv = key if cplx else key.real
+            I = sp.identity(self.npl, dtype=dt, format="csc")
+            self._plane_lu[key] = [spl.splu((self.ApT.astype(dt) + (self.mu[k] + pv) * I).tocsc())
+                                   for k in range(self.nz)]
+        return self._plane_lu[key]
+
+    def solve_base(self, p, W):
+        lus = self._plane_factors(p)
+        cplx = complex(p).imag != 0
+        Wd = np.asarray(W, dtype=np.complex128 if cplx else np.float64)
+        one = Wd.ndim == 1
+        Wd = Wd.reshape(self.n, -1)
+        w = Wd.shape[1]
+        Y = np.einsum("zk,zpw->kpw", self.S, Wd.reshape(self.nz, self.npl, w))   # S^T along z
+        for k in range(self.nz):
+            Y[k] = lus[k].solve(np.ascontiguousarray(Y[k]))
+        V = np.einsum("zk,kpw->zpw", self.S, Y).reshape(self.n, w)              # S along z
+        return V[:, 0] if one else V
+
+
+def kron_z_split(A, planes=None):
+    """Split A = I_Nz (x) A_p + T (x) I_Np exactly (A sparse, planes = Np;
+    default: the plane size of a cubic grid, n^(2/3)).  A_p is the diagonal
+    block of the first plane minus T's diagonal; T holds the couplings
+    between planes, which must be multiples of the identity (checked: the
+    reassembled matrix must equal A entry for entry, else ValueError)."""
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    if planes is None:
+        N = int(round(n ** (1.0 / 3.0)))
+        planes = N * N
+    if n % planes:
+        raise ValueError("plane size does not divide n")
+    nz = n // planes
+    T = np.zeros((nz, nz))
+    for a in range(nz):
+        for b in range(max(0, a - 1), min(nz, a + 2)):
+            if a != b:
+                blk = A[a * planes:(a + 1) * planes, b * planes:(b + 1) * planes]
+                T[a, b] = blk[0, 0]
+    # the diagonal of T (the share of A's diagonal that belongs to the
+    # coupling between planes): the second difference along z has rows that
+    # sum to zero in the interior, T[a, a] = -(T[a, a-1] + T[a, a+1]), and the
+    # same value on the boundary planes (Dirichlet)
+    if nz > 2:
+        tdiag = -(T[1, 0] + T[1, 2])
+    elif nz == 2:
+        tdiag = -2.0 * T[0, 1]
+    else:
+        tdiag = 0.0
+    np.fill_diagonal(T, tdiag)
+    Ap = (A[:planes, :planes] - tdiag * sp.identity(planes)).tocsr()
+    R = (sp.kron(sp.identity(nz), Ap) + sp.kron(sp.csr_matrix(T), sp.identity(planes)) - A).tocsr()
+    R.eliminate_zeros()
+    if R.nnz and abs(R).max() > 1e-12 * abs(A).max():
+        raise ValueError("A is not of the form I (x) A_p + T (x) I")
+    if not np.allclose(T, T.T, rtol=0, atol=0):
+        raise ValueError("plane coupling T is not symmetric")
+    return Ap, T
 
 
 def check_shifts(shifts):

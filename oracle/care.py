@@ -12,7 +12,7 @@ U64 = np.finfo(np.float64).eps / 2      # FP64 unit roundoff (Table 1)
 
 
 def nlradi(A, B, C, shifts, tol=1e-13, kmax=20, adi_tol=1e-13, jmax=100, stagnation=0.999,
-           compress_rel=10 * U64):
+           compress_rel=10 * U64, solver_factory=None):
     """Initial CARE approximation by Newton-Kleinman with LR-ADI inner solves
     (NLR-ADI, Sec. 4):  with K_0 = 0 (A stable), step i solves
         A_i^T X_{i+1} + X_{i+1} A_i = -[C^T, K_i] [C^T, K_i]^T,  A_i = A - B K_i^T,
@@ -20,7 +20,8 @@ def nlradi(A, B, C, shifts, tol=1e-13, kmax=20, adi_tol=1e-13, jmax=100, stagnat
     ||R(Z)||_F <= tol ||C^T C||_F, when the residual ratio exceeds
     `stagnation`, or after kmax steps.  The final factor is compressed with
     Algorithm 2 (signature +I) at the relative threshold compress_rel.
-    Returns (Z, info)."""
+    solver_factory(A, B, K), if given, builds the shifted solver of each
+    Lyapunov equation (default: adi.ShiftedSolver).  Returns (Z, info)."""
     n = A.shape[0]
     m = B.shape[1]
     nrm = np.linalg.norm(C @ C.T, "fro")
@@ -30,7 +31,9 @@ def nlradi(A, B, C, shifts, tol=1e-13, kmax=20, adi_tol=1e-13, jmax=100, stagnat
     prev = None
     for i in range(kmax):
         W0 = C.T if i == 0 else np.hstack([C.T, K])
-        Z, _, info = adi.lradi(A, B, K if i else None, W0, shifts, adi_tol, jmax)
+        Ki = K if i else None
+        solver = solver_factory(A, B, Ki) if solver_factory else None
+        Z, _, info = adi.lradi(A, B, Ki, W0, shifts, adi_tol, jmax, solver=solver)
         inner += info["steps"]
         K = Z @ (Z.T @ B)
         res = lowrank.residual_norm(A, B, C, Z) / nrm
@@ -45,7 +48,7 @@ def nlradi(A, B, C, shifts, tol=1e-13, kmax=20, adi_tol=1e-13, jmax=100, stagnat
 
 
 def framework1(A, B, C, shifts, tol=1e-10, kmax=20, eta_r_rel=1e-4, eta_s_rel=10 * U64,
-               tau_L=1e-12, jmax=50, stagnation=0.999, Z1=None, stage0=None):
+               tau_L=1e-12, jmax=50, stagnation=0.999, Z1=None, stage0=None, solver_factory=None):
     """Framework 1 (Factorization-based Mixed Precision Newton Iterative
     Refinement), all precisions FP64 here:
 
@@ -55,10 +58,11 @@ def framework1(A, B, C, shifts, tol=1e-10, kmax=20, eta_r_rel=1e-4, eta_s_rel=10
         solve A_k^T X^+- + X^+- A_k + C+- C+-^T = 0 by one LR-ADI run on the
         combined right-hand side [C+, C-] (Sec. 4), A_k = A - B (Z_k Z_k^T B)^T;
         Z_{k+1} = Algorithm 2 (Z_k, Z+, Z-).
-    Returns (Z, info) with the paper's outer(inner) counts."""
+    solver_factory as in nlradi.  Returns (Z, info) with the paper's
+    outer(inner) counts."""
     nrm = np.linalg.norm(C @ C.T, "fro")      # = ||C^T C||_F
     if Z1 is None:
-        Z, info0 = nlradi(A, B, C, shifts, **(stage0 or {}))
+        Z, info0 = nlradi(A, B, C, shifts, solver_factory=solver_factory, **(stage0 or {}))
     else:
         Z, info0 = np.asarray(Z1, dtype=np.float64), dict(outer=0, inner=0, hist=[])
     hist, inner, outer = [], 0, 0
@@ -76,7 +80,8 @@ def framework1(A, B, C, shifts, tol=1e-10, kmax=20, eta_r_rel=1e-4, eta_s_rel=10
         prev = res
         K = Z @ (Z.T @ B)
         W0 = np.hstack([Cp, Cm])
-        Zpm, _, info = adi.lradi(A, B, K, W0, shifts, tau_L, jmax)
+        solver = solver_factory(A, B, K) if solver_factory else None
+        Zpm, _, info = adi.lradi(A, B, K, W0, shifts, tau_L, jmax, solver=solver)
         inner += info["steps"]
         Zp, Zm = adi.split_columns(Zpm, W0.shape[1], Cp.shape[1])
         Z = lowrank.solution_factor(Z, Zp, Zm, eta_s_rel)

@@ -74,3 +74,24 @@ def paper_res(A, B, C, Z, res_fro):
     ZtZ = np.linalg.norm(Z.T @ Z, "fro")
     den = 2 * nA * ZtZ + np.linalg.norm(B.T @ B, "fro") * ZtZ ** 2 + np.linalg.norm(C @ C.T, "fro")
     return res_fro / den
+
+
+def care_hamiltonian(A, B, C):
+    """Stabilizing solution from the stable invariant subspace of the
+    Hamiltonian matrix (Laub's Schur method, the family cited in Sec. 1):
+
+        H = [[A, -B B^T], [-C^T C, -A^T]],   H [I; X] = [I; X] (A - B B^T X),
+
+    so an ordered real Schur form H U = U T with the n eigenvalues of negative
+    real part first gives span [U11; U21] = span [I; X] and X = U21 U11^{-1}.
+    A library Schur decomposition of the 2n x 2n matrix (no generalized QZ):
+    much faster than ``care_schur`` at n in the thousands."""
+    A = _dense(A)
+    n = A.shape[0]
+    H = np.block([[A, -B @ B.T], [-C.T @ C, -A.T]])
+    _, U, sdim = sla.schur(H, output="real", sort="lhp")
+    if sdim != n:
+        raise ValueError(f"Hamiltonian has {sdim} stable eigenvalues, expected {n}")
+    U11, U21 = U[:n, :n], U[n:, :n]
+    X = np.linalg.solve(U11.T, U21.T).T
+    return 0.5 * (X + X.T)

@@ -46,15 +46,18 @@ def arnoldi(apply, b, k):
     return H[:k, :k]
 
 
-def ritz_candidates(A, kp=20, km=10, real_only=False):
+def ritz_candidates(A, kp=20, km=10, real_only=False, inv_apply=None):
     """Steps 1-3: stable Ritz values of A^T and inverted Ritz values of A^-T.
-    (A and A^T share their spectrum; the ADI operator is A^T.)"""
+    (A and A^T share their spectrum; the ADI operator is A^T.)  inv_apply(v),
+    if given, applies A^-T (default: a sparse LU of A^T)."""
     At = sp.csr_matrix(A.T) if sp.issparse(A) else np.asarray(A, dtype=np.float64).T
     n = At.shape[0]
     b0 = np.ones(n) / np.sqrt(n)
     R = list(np.linalg.eigvals(arnoldi(lambda v: At @ v, b0, kp)))
     if km > 0:
-        if sp.issparse(At):
+        if inv_apply is not None:
+            inv = inv_apply
+        elif sp.issparse(At):
             lu = spl.splu(sp.csc_matrix(At))
             inv = lu.solve
         else:
@@ -99,6 +102,6 @@ def penzl_select(R, l0):
     return np.array(P, dtype=np.complex128)
 
 
-def penzl_shifts(A, l0=16, kp=20, km=10, real_only=False):
+def penzl_shifts(A, l0=16, kp=20, km=10, real_only=False, inv_apply=None):
     """Penzl's heuristic shift set for the ADI operator A^T."""
-    return penzl_select(ritz_candidates(A, kp, km, real_only), l0)
+    return penzl_select(ritz_candidates(A, kp, km, real_only, inv_apply), l0)

@@ -77,8 +77,12 @@ I32, I64, DBL = C.c_int32, C.c_int64, C.c_double
 PI32 = C.POINTER(C.c_int32)
 PDBL = C.POINTER(C.c_double)
 
+# device-memory hooks of care_ctx_create
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
 SIGNATURES = {
-    "care_ctx_create": (I32, [C.POINTER(P), I32, P]),
+    "care_ctx_create": (I32, [C.POINTER(P), I32, P, ALLOC_FN, DEALLOC_FN, P]),
     "care_ctx_destroy": (None, [P]),
     "care_opts_default": (None, [C.POINTER(care_opts), I32]),
     "care_last_error": (C.c_char_p, []),

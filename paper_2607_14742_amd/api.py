@@ -86,15 +86,55 @@ class DeviceCSR:
         return C.byref(self._c)
 
 
+class TorchAllocator:
+    """Device-memory hooks that draw the library's workspace from PyTorch's
+    caching allocator (torch.cuda.caching_allocator_alloc / _delete), so the
+    library and torch share one pool.  Counts the calls (for tests)."""
+
+    def __init__(self, device: int):
+        self.device = device
+        self.allocs = 0
+        self.frees = 0
+        self.live = {}
+
+        def alloc(nbytes, stream, user):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
+            except Exception:      # out of memory: the library reports CARE_ERR_NOMEM
+                return None
+            self.allocs += 1
+            self.live[ptr] = int(nbytes)
+            return ptr
+
+        def dealloc(ptr, nbytes, stream, user):
+            self.frees += 1
+            self.live.pop(ptr, None)
+            torch.cuda.caching_allocator_delete(ptr)
+
+        # the ctypes callback objects must outlive the context
+        self.c_alloc = L.ALLOC_FN(alloc)
+        self.c_dealloc = L.DEALLOC_FN(dealloc)
+
+
 class Context:
     """A library context bound to one device and one HIP stream (torch's
-    current stream by default)."""
+    current stream by default).  allocator="torch" (default) backs the
+    library's device workspace with PyTorch's caching allocator through the
+    context's allocator hooks; allocator=None lets the library use hipMalloc."""
 
-    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None, allocator: str | None = "torch"):
         self.device = device
         self.stream = stream or torch.cuda.current_stream(device)
+        self.allocator = TorchAllocator(device) if allocator == "torch" else None
+        if allocator not in ("torch", None):
+            raise ValueError(f"unknown allocator {allocator!r}")
         h = C.c_void_p()
-        _check(_lib().care_ctx_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream)))
+        if self.allocator is not None:
+            _check(_lib().care_ctx_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream),
+                                          self.allocator.c_alloc, self.allocator.c_dealloc, None))
+        else:
+            _check(_lib().care_ctx_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream),
+                                          L.ALLOC_FN(), L.DEALLOC_FN(), None))
         self.h = h
 
     def close(self):

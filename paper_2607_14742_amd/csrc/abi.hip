@@ -108,16 +108,22 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->krylov_block_tol = -1;
 }
 
-care_status care_ctx_create(care_ctx** out, int32_t device, void* stream) {
+care_status care_ctx_create(care_ctx** out, int32_t device, void* stream, care_alloc_fn alloc,
+                            care_dealloc_fn dealloc, void* user) {
   return guarded([&]() -> care_status {
     if (!out) fail(CARE_ERR_ARG, "ctx output pointer is NULL");
     *out = nullptr;
+    if ((alloc == nullptr) != (dealloc == nullptr)) fail(CARE_ERR_ARG, "alloc and dealloc must both be set or both NULL");
+    AllocHooks hooks;
+    hooks.alloc = alloc;
+    hooks.dealloc = dealloc;
+    hooks.user = user;
     int count = 0;
     HIP_CHECK(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) fail(CARE_ERR_ARG, "device index out of range");
     care_ctx* c = new care_ctx();
     try {
-      ctx_init(c->c, device, (hipStream_t)stream);
+      ctx_init(c->c, device, (hipStream_t)stream, hooks);
     } catch (...) {
       delete c;
       throw;

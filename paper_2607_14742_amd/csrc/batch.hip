@@ -103,7 +103,7 @@ void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, con
   auto work = [&](int w) {
     Ctx wc;
     try {
-      ctx_init(wc, ctx->device, ctx->stream);
+      ctx_init(wc, ctx->device, ctx->stream, ctx->hooks);   // the caller's allocator hooks, if any
       // ordered after everything the caller queued (ctx->stream waits on it)
       HIP_CHECK(hipEventRecord(wc.order_event, wc.user_stream));
       HIP_CHECK(hipStreamWaitEvent(wc.stream, wc.order_event, 0));

@@ -67,9 +67,18 @@ inline size_t val_bytes(Prec p) { return p == Prec::F64 ? 8 : (p == Prec::F32 ? 
 // ----------------------------------------------------------------------------
 // device memory arena (grow-only caching allocator owned by a context)
 // ----------------------------------------------------------------------------
+// Device blocks come from hipMalloc, or from the caller's hooks when the
+// context was created with them (care_ctx_create).
+struct AllocHooks {
+  care_alloc_fn alloc = nullptr;
+  care_dealloc_fn dealloc = nullptr;
+  void* user = nullptr;
+  bool set() const { return alloc != nullptr; }
+};
+
 class Arena {
  public:
-  explicit Arena(hipStream_t s) : stream_(s) {}
+  Arena(hipStream_t s, const AllocHooks& h) : stream_(s), hooks_(h) {}
   ~Arena();
   void* get(size_t bytes);
   void put(void* p);
@@ -80,7 +89,10 @@ class Arena {
   size_t cached() const { return cached_; }
 
  private:
+  void* device_alloc(size_t bytes);
+  void device_free(void* p, size_t bytes);
   hipStream_t stream_;
+  AllocHooks hooks_;
   std::multimap<size_t, void*> free_;
   std::map<void*, size_t> live_;
   size_t in_use_ = 0;
@@ -96,6 +108,7 @@ struct Ctx {
   hipStream_t user_stream = nullptr;   // the caller's stream: calls are ordered after it
   hipEvent_t order_event = nullptr;
   rocblas_handle blas = nullptr;
+  AllocHooks hooks;                // the caller's device allocator (or none)
   Arena* arena = nullptr;
   void* pinned = nullptr;          // small pinned host staging buffer
   size_t pinned_bytes = 0;
@@ -134,7 +147,7 @@ struct Ctx {
 // Set up a context on `device`: its own non-blocking stream (default
 // priority), the ordering event, a rocBLAS handle and the workspace arena.
 // `user_stream` is the caller's stream the context's work is ordered after.
-void ctx_init(Ctx& c, int device, hipStream_t user_stream);
+void ctx_init(Ctx& c, int device, hipStream_t user_stream, const AllocHooks& hooks = AllocHooks());
 // Release everything ctx_init acquired (waits for the stream first).
 void ctx_release(Ctx& c);
 

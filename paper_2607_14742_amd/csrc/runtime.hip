@@ -21,9 +21,26 @@ static size_t round_bytes(size_t b) {
   return (b + g - 1) / g * g;
 }
 
+void* Arena::device_alloc(size_t bytes) {
+  if (hooks_.set()) return hooks_.alloc(bytes, (void*)stream_, hooks_.user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void Arena::device_free(void* p, size_t bytes) {
+  if (hooks_.set()) hooks_.dealloc(p, bytes, (void*)stream_, hooks_.user);
+  else (void)hipFree(p);
+}
+
 Arena::~Arena() {
-  for (auto& kv : free_) (void)hipFree(kv.second);
-  for (auto& kv : live_) (void)hipFree(kv.first);
+  // blocks may still be read by queued work: wait before handing them back
+  (void)hipStreamSynchronize(stream_);
+  for (auto& kv : free_) device_free(kv.second, kv.first);
+  for (auto& kv : live_) device_free(kv.first, kv.second);
 }
 
 void* Arena::get(size_t bytes) {
@@ -39,20 +56,15 @@ void* Arena::get(size_t bytes) {
     in_use_ += sz;
     return p;
   }
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, rb);
-  if (e != hipSuccess) {
+  void* p = device_alloc(rb);
+  if (!p) {
     // release the cache and retry once
-    (void)hipGetLastError();
     (void)hipStreamSynchronize(stream_);
-    for (auto& kv : free_) (void)hipFree(kv.second);
+    for (auto& kv : free_) device_free(kv.second, kv.first);
     free_.clear();
     cached_ = 0;
-    e = hipMalloc(&p, rb);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      fail(CARE_ERR_NOMEM, "device allocation of " + std::to_string(rb) + " bytes failed");
-    }
+    p = device_alloc(rb);
+    if (!p) fail(CARE_ERR_NOMEM, "device allocation of " + std::to_string(rb) + " bytes failed");
   }
   live_[p] = rb;
   in_use_ += rb;
@@ -66,7 +78,7 @@ void Arena::trim_to(size_t keep) {
   (void)hipStreamSynchronize(stream_);
   while (cached_ > keep && !free_.empty()) {
     auto it = std::prev(free_.end());   // largest cached block
-    (void)hipFree(it->second);
+    device_free(it->second, it->first);
     cached_ -= it->first;
     free_.erase(it);
   }
@@ -171,16 +183,17 @@ void dzero(Ctx* ctx, void* dst, size_t bytes) {
   }
 }
 
-void ctx_init(Ctx& c, int device, hipStream_t user_stream) {
+void ctx_init(Ctx& c, int device, hipStream_t user_stream, const AllocHooks& hooks) {
   HIP_CHECK(hipSetDevice(device));
   c.device = device;
   c.user_stream = user_stream;
+  c.hooks = hooks;
   HIP_CHECK(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));   // default priority
   HIP_CHECK(hipEventCreateWithFlags(&c.order_event, hipEventDisableTiming));
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c.num_cu = prop.multiProcessorCount;
-  c.arena = new Arena(c.stream);
+  c.arena = new Arena(c.stream, c.hooks);
   if (rocblas_create_handle(&c.blas) != rocblas_status_success) {
     c.blas = nullptr;
     ctx_release(c);

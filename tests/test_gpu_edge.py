@@ -158,3 +158,56 @@ def test_auto_precision_choice(pk, ctx, case, want):
     assert stats["inner_prec"] == {"fp64": pk.CARE_FP64, "fp32": pk.CARE_FP32}[want]
     rel = lowrank.residual_norm(A, B, Cm, Z.cpu().numpy()) / np.linalg.norm(Cm @ Cm.T)
     assert rel <= 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_res_paper_matches_oracle(pk, ctx, prec):
+    # the paper's "Res" (Sec. 5) reported by the solver against the oracle's
+    # definition: the denominator evaluated by the oracle from A, B, C and the
+    # returned Z, with the solver's own ||R||_F, must match to 1e-10; the
+    # oracle's own ||R(Z)||_F gives the same Res to the accuracy of the two
+    # residual evaluations
+    P = wl.fdm2d_problem(24, 3, 2)
+    print(f"res_paper fdm2d n={P.n} prec={prec}", flush=True)
+    Z, stats, st = pk.care_solve(ctx, pk.DeviceCSR.from_scipy(P.A), dev(P.B), dev(P.C), tol=1e-11,
+                                 shifts=P.shifts, prec=prec)
+    assert st == 0, stats
+    Z = Z.cpu().numpy()
+    nctc = np.linalg.norm(P.C @ P.C.T, "fro")
+    res_gpu = stats["res_rel"] * nctc
+    want = riccati.paper_res(P.A, P.B, P.C, Z, res_gpu)
+    print(f"  res_paper gpu {stats['res_paper']:.6e} oracle-denominator {want:.6e}", flush=True)
+    assert abs(stats["res_paper"] - want) <= 1e-10 * want
+    res_or = lowrank.residual_norm(P.A, P.B, P.C, Z)
+    assert abs(riccati.paper_res(P.A, P.B, P.C, Z, res_or) - want) <= 0.05 * want
+
+
+def test_res_paper_matches_oracle_dense(pk, ctx):
+    # the same check for the dense operator path (Example 1 of Sec. 5.1, n = 200)
+    A, B, C = wl.ex1(200, 10, 5, 2.0)
+    shifts = -np.logspace(0, 2, 12)
+    Z, stats, st = pk.care_solve_dense(ctx, dev(A), dev(B), dev(C), tol=1e-12, shifts=shifts, prec="fp64")
+    assert st in (0, 1), stats
+    Z = Z.cpu().numpy()
+    res_gpu = stats["res_rel"] * np.linalg.norm(C @ C.T, "fro")
+    want = riccati.paper_res(A, B, C, Z, res_gpu)
+    assert abs(stats["res_paper"] - want) <= 1e-10 * want
+
+
+def test_torch_allocator_hooks_balance(pk):
+    # the context's workspace drawn through PyTorch's caching allocator: every
+    # block handed out is handed back by care_ctx_destroy, none is leaked
+    P = wl.fdm2d_problem(20, 2, 2)
+    base = torch.cuda.memory_allocated()
+    ctx = pk.Context(0, allocator="torch")
+    alloc = ctx.allocator
+    Z, stats, st = pk.care_solve(ctx, pk.DeviceCSR.from_scipy(P.A), dev(P.B), dev(P.C), tol=1e-11,
+                                 shifts=P.shifts, prec="fp32")
+    assert st == 0, stats
+    assert alloc.allocs > 0
+    del Z
+    ctx.close()
+    print(f"  hook allocations {alloc.allocs}, frees {alloc.frees}", flush=True)
+    assert alloc.allocs == alloc.frees and not alloc.live
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() <= base + (1 << 20)

@@ -92,3 +92,44 @@ def test_complex_pair_pin_catches_missing_weight(monkeypatch):
     Zbad = Z.copy()
     Zbad[:, 2:] /= math.sqrt(delta * delta + 1.0)
     assert np.linalg.norm(Zbad @ Zbad.T - Xc) > 1e-3 * np.linalg.norm(Xc)
+
+
+def test_paper_res_pin_catches_dropped_term(monkeypatch):
+    """Drop the ||B^T B||_F ||Z^T Z||_F^2 term of the paper's Res denominator
+    (or square the wrong factor): the hand-worked example must fail."""
+    from tests.test_oracle_pins import hand_worked_res_example
+    A, B, C, Z, expected = hand_worked_res_example()
+
+    def dropped(A, B, C, Z, res_fro):
+        nA = sp.linalg.norm(A, "fro")
+        ZtZ = np.linalg.norm(Z.T @ Z, "fro")
+        return res_fro / (2 * nA * ZtZ + np.linalg.norm(C @ C.T, "fro"))
+
+    def unsquared(A, B, C, Z, res_fro):
+        nA = sp.linalg.norm(A, "fro")
+        ZtZ = np.linalg.norm(Z.T @ Z, "fro")
+        return res_fro / (2 * nA * ZtZ + np.linalg.norm(B.T @ B, "fro") * ZtZ + np.linalg.norm(C @ C.T, "fro"))
+    for bad in (dropped, unsquared):
+        monkeypatch.setattr(riccati, "paper_res", bad)
+        assert abs(riccati.paper_res(A, B, C, Z, 1.0) - expected) > 1e-3 * expected
+
+
+def test_check_shifts_pin_catches_lenient_sign(monkeypatch):
+    """A checker that lets Re p = 0 through (or skips the pairing rule) must
+    fail the rejection pins."""
+    import pytest as _pt
+
+    def lenient(shifts):
+        s = np.asarray(shifts, dtype=np.complex128)
+        if s.size == 0 or np.any(s.real > 0):
+            raise ValueError("bad")
+        return s
+    monkeypatch.setattr(adi, "check_shifts", lenient)
+    for bad in ([-1.0, 0.0], [-1.0 + 2.0j], [-1.0 - 2.0j, -1.0 + 2.0j]):
+        try:
+            adi.check_shifts(np.array(bad, dtype=np.complex128))
+            caught = False
+        except ValueError:
+            caught = True
+        assert not caught       # the lenient checker accepts what the pins reject
+    _pt.raises(ValueError, adi.check_shifts, np.array([1.0]))

@@ -380,3 +380,133 @@ def test_toeplitz5_definition_and_dissipativity():
     P = wl.toeplitz_problem(300)
     assert P.B.shape == (300, 10) and P.C.shape == (5, 300)
     assert np.isclose(np.linalg.norm(P.B), 1.0)
+
+
+# --------------------------------------------------------------------------
+# the paper's reported residual "Res" (Sec. 5) on a hand-worked example
+# --------------------------------------------------------------------------
+def hand_worked_res_example():
+    """A = diag(-1, -2), Z = [sqrt 2; 0], B = [1; 1], C = [3, 0].
+    By hand: X = Z Z^T = 2 e1 e1^T; A^T X + X A = -4 e1 e1^T;
+    X B B^T X = (X B)(X B)^T = 4 e1 e1^T; C^T C = 9 e1 e1^T; so
+    R(X) = e1 e1^T and ||R||_F = 1.  Norms: ||A||_F = sqrt 5,
+    ||Z^T Z||_F = 2, ||B^T B||_F = 2, ||C C^T||_F = 9.  The denominator of
+    Res is 2 sqrt5 2 + 2 2^2 + 9 = 17 + 4 sqrt 5."""
+    A = sp.csr_matrix(np.diag([-1.0, -2.0]))
+    Z = np.array([[math.sqrt(2.0)], [0.0]])
+    B = np.array([[1.0], [1.0]])
+    C = np.array([[3.0, 0.0]])
+    return A, B, C, Z, 1.0 / (17.0 + 4.0 * math.sqrt(5.0))
+
+
+def test_paper_res_hand_worked_example():
+    A, B, C, Z, expected = hand_worked_res_example()
+    R = riccati.riccati_residual(A, B, C, Z @ Z.T)
+    assert np.allclose(R, np.array([[1.0, 0.0], [0.0, 0.0]]), atol=1e-14, rtol=0)
+    res = np.linalg.norm(R, "fro")
+    # (Z holds sqrt 2 rounded, so ||R||_F carries a few ulps)
+    assert abs(riccati.paper_res(A, B, C, Z, res) - expected) <= 1e-13 * expected
+    # a dense A gives the same value
+    assert abs(riccati.paper_res(A.toarray(), B, C, Z, res) - expected) <= 1e-13 * expected
+
+
+def test_paper_res_scaling_law():
+    """Scaling C by t and Z by sqrt(t) scales the denominator's first and last
+    terms by t and the middle one by t^2; with B -> B / sqrt(t) every term
+    scales by t, and R(Z) scales by t (R is homogeneous of degree one in
+    (Z Z^T, C^T C) once B B^T is scaled by 1/t), so Res is unchanged."""
+    n, m, p, r = 12, 2, 3, 4
+    rng = np.random.default_rng(5)
+    A = random_stable_sparse(n, 0.3, rng)
+    B = rng.standard_normal((n, m))
+    C = rng.standard_normal((p, n))
+    Z = 0.2 * rng.standard_normal((n, r))
+    t = 7.0
+
+    def res(A, B, C, Z):
+        R = riccati.riccati_residual(A, B, C, Z @ Z.T)
+        return riccati.paper_res(A, B, C, Z, np.linalg.norm(R, "fro"))
+    r0 = res(A, B, C, Z)
+    r1 = res(A, B / math.sqrt(t), math.sqrt(t) * C, math.sqrt(t) * Z)
+    assert abs(r1 - r0) <= 1e-13 * r0
+
+
+# --------------------------------------------------------------------------
+# shift-set validation (Sec. 4: Re p < 0, conjugate pairs adjacent)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("shifts", [
+    [-1.0, -2.0],
+    [-1.0 + 2.0j, -1.0 - 2.0j],
+    [-3.0, -1.0 + 2.0j, -1.0 - 2.0j, -0.5],
+])
+def test_check_shifts_accepts_valid_sets(shifts):
+    s = adi.check_shifts(np.array(shifts))
+    assert s.dtype == np.complex128 and s.size == len(shifts)
+
+
+@pytest.mark.parametrize("shifts", [
+    [],                                    # empty set
+    [-1.0, 0.0],                           # Re p = 0 (the ADI factor (a - p)/(a + p) is not contractive)
+    [-1.0, 0.5],                           # Re p > 0
+    [0.5 + 1.0j, 0.5 - 1.0j],              # pair in the right half-plane
+    [-1.0 + 2.0j],                         # complex shift without its conjugate
+    [-1.0 + 2.0j, -2.0],                   # conjugate not adjacent
+    [-1.0 - 2.0j, -1.0 + 2.0j],            # Im < 0 first
+    [-1.0 + 2.0j, -1.0 - 3.0j],            # second entry is not the conjugate
+])
+def test_check_shifts_rejects_invalid_sets(shifts):
+    with pytest.raises(ValueError):
+        adi.check_shifts(np.array(shifts, dtype=np.complex128))
+
+
+# --------------------------------------------------------------------------
+# Hamiltonian-Schur CARE solver and the Kronecker plane-wise shifted solver
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("a,m,p", [(-2.0, 1, 1), (1.5, 2, 4)])
+def test_hamiltonian_scalar_closed_form(a, m, p):
+    B = RNG.standard_normal((1, m))
+    C = RNG.standard_normal((p, 1))
+    x = scalar_care(a, float((B @ B.T)[0, 0]), float((C.T @ C)[0, 0]))
+    assert abs(riccati.care_hamiltonian(np.array([[a]]), B, C)[0, 0] - x) <= 1e-12 * x
+
+
+def test_hamiltonian_decoupled_and_vs_library():
+    n = 6
+    a = -RNG.uniform(0.5, 5.0, n)
+    b = RNG.uniform(0.2, 2.0, n)
+    c = RNG.uniform(0.2, 2.0, n)
+    Xcf = np.diag([scalar_care(a[i], b[i] ** 2, c[i] ** 2) for i in range(n)])
+    X = riccati.care_hamiltonian(np.diag(a), np.diag(b), np.diag(c))
+    assert np.allclose(X, Xcf, rtol=0, atol=1e-12 * Xcf.max())
+    # a nonsymmetric 40 x 40 problem against the library's QZ-based routine
+    A = random_stable_sparse(40, 0.2, RNG).toarray()
+    B = RNG.standard_normal((40, 3))
+    C = RNG.standard_normal((2, 40))
+    Xh = riccati.care_hamiltonian(A, B, C)
+    Xs = riccati.care_schur(A, B, C)
+    assert np.linalg.norm(Xh - Xs) <= 1e-11 * np.linalg.norm(Xs)
+    assert np.all(np.linalg.eigvals(A - B @ (B.T @ Xh)).real < 0)
+
+
+@pytest.mark.parametrize("p", [-300.0, -150.0 + 400.0j])
+def test_kron_z_solver_matches_sparse_lu(p):
+    """The plane-wise solve of A^T + p I for the rotating-field 3D matrix
+    (no z-convection) against a sparse LU of the whole matrix, with and
+    without the SMW feedback term."""
+    A = wl.fdm3d(6, 100.0, "rotating")
+    n = A.shape[0]
+    Ap, T = adi.kron_z_split(A)
+    assert Ap.shape == (36, 36) and T.shape == (6, 6)
+    B = RNG.standard_normal((n, 2))
+    K = 0.01 * RNG.standard_normal((n, 2))
+    W = RNG.standard_normal((n, 3))
+    for b, k in ((None, None), (B, K)):
+        ref = adi.ShiftedSolver(A, b, k).solve(p, W)
+        got = adi.KronZShiftedSolver(A, b, k).solve(p, W)
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_kron_z_split_rejects_z_convection():
+    # a constant field has z-convection: the plane coupling is not symmetric
+    with pytest.raises(ValueError):
+        adi.kron_z_split(wl.fdm3d(5, 10.0, "constant"))
