@@ -196,9 +196,10 @@ typedef struct {
  * bytes of device memory of the context's device, usable in work queued on
  * `stream` (the context's own stream, a hipStream_t passed as void*), or
  * NULL when it cannot; dealloc returns a block obtained from alloc (same
- * bytes and stream).  `user` is passed through unchanged.  The hooks may be
- * called from the thread of any entry point taking the context, and from the
- * worker threads of care_solve_batch (one call at a time per thread). */
+ * bytes and stream).  `user` is passed through unchanged.  The hooks are
+ * only called from the thread that calls an entry point with the context
+ * (never from threads the library creates: the worker contexts of
+ * care_solve_batch allocate their workspace with hipMalloc). */
 typedef void* (*care_alloc_fn)(size_t bytes, void* stream, void* user);
 typedef void (*care_dealloc_fn)(void* ptr, size_t bytes, void* stream, void* user);
 

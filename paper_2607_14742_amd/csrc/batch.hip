@@ -103,7 +103,17 @@ void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, con
   auto work = [&](int w) {
     Ctx wc;
     try {
-      ctx_init(wc, ctx->device, ctx->stream, ctx->hooks);   // the caller's allocator hooks, if any
+      // the worker threads are the library's own: they allocate with hipMalloc
+      // rather than call the caller's allocator hooks from threads the caller
+      // did not create (the hooks' contract)
+      ctx_init(wc, ctx->device, ctx->stream);
+      // no HIP-graph capture in the workers: while one worker's stream is in
+      // capture, another worker's device-synchronising calls (hipFree in the
+      // per-instance cache trim, pinned staging reallocation, the vendor
+      // libraries' workspace allocations) would have to synchronise a
+      // capturing stream.  The concurrent workers hide the launch latency the
+      // graphs save in a single solve.
+      wc.krylov_graphs = 0;
       // ordered after everything the caller queued (ctx->stream waits on it)
       HIP_CHECK(hipEventRecord(wc.order_event, wc.user_stream));
       HIP_CHECK(hipStreamWaitEvent(wc.stream, wc.order_event, 0));

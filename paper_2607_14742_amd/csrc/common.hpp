@@ -118,11 +118,12 @@ struct Ctx {
   int64_t spmm_calls = 0;
   double spmm_bytes = 0.0;
   bool spmm_defer = false;          // bytes of sparse launches counted by the caller
-  int64_t spmm_pending[5] = {0, 0, 0, 0, 0};   // deferred launches per mode
+  int64_t spmm_pending[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // deferred launches per sparse-product mode
   int spmm_split = 0;               // BiCGStab products: 0 auto, 1 fused, 2 split
   int spmm_tune = 0;                // 1: time the panel widths of a product shape once, keep the faster
   int krylov_method = 0;            // shifted solves: 0 BiCGStab, 1 restarted GMRES (real shifts)
   int krylov_patient = 0;           // BiCGStab stagnation window max(1000, it/2) (unshifted solves)
+  int krylov_graphs = 1;            // 0: no HIP-graph capture of Krylov chunks (batch worker contexts)
   int krylov_compact = 1;           // BiCGStab: gather the still-active columns into fewer panels
   int krylov_restart = 0;           // GMRES restart length (0: 30 in FP32, 50 in FP64)
   double t_spmm = 0.0;

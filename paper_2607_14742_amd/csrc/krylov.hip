@@ -800,26 +800,32 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
     ctx->krylov_compactions += 1;
     return true;
   };
-  // first check_every iterations (and everything when profiling) launched
-  // directly; the steady state replays a captured chunk of CHUNK iterations
-  // plus the checkpoint kernel as one HIP graph (no memset nodes: the loop
-  // holds kernels only), with a host poll after each replay.
+  // The first check_every iterations (and everything when profiling) are
+  // launched directly, with polls after the first iteration and then every
+  // check_every iterations.  The steady state runs chunks of CHUNK iterations
+  // plus the checkpoint kernel, with a host poll after each chunk: replayed as
+  // one captured HIP graph (no memset nodes: the loop holds kernels only), or,
+  // where graphs are off (batch worker contexts), the same launches issued
+  // directly, so both give the same results.  A chunk never runs past maxit:
+  // the iterations left below a whole chunk are launched directly.
   const int CHUNK = 8;
-  const bool use_graph = !ctx->profile && !trace && maxit > 2 * CHUNK;
+  const bool chunked = !ctx->profile && !trace && maxit > 2 * CHUNK;
+  const bool graphs = chunked && ctx->krylov_graphs;
   ctx->spmm_defer = ctx->profile != 0;
   for (int md = 0; md < 5; ++md) ctx->spmm_pending[md] = 0;
-  while (it < maxit && !done && (!use_graph || it < check_every)) {
-    iteration(it);
-    ++it;
-    if (it >= next_check || it >= maxit) {
-      poll();
-      next_check = it + check_every;
-      if (!done && it < maxit) compact();
+  auto direct_until = [&](int limit, bool stop_at_check) {
+    while (it < limit && !done && (!stop_at_check || it < check_every)) {
+      iteration(it);
+      ++it;
+      if (it >= next_check || it >= limit) {
+        poll();
+        next_check = it + check_every;
+        if (!done && it < limit) compact();
+      }
     }
-  }
-  account(0);
-  ctx->spmm_defer = false;
-  if (!done && it < maxit && use_graph) {
+  };
+  direct_until(maxit, chunked);
+  if (!done && chunked && it + CHUNK + 1 <= maxit) {
     if (it % 2) {          // the ping-pong buffers repeat with period 2
       iteration(it);
       ++it;
@@ -828,26 +834,35 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
     // polls stay every CHUNK iterations, so the checkpoints are those of an
     // uncompacted solve)
     bool recapture = true;
-    while (recapture && !done && it < maxit) {
+    while (recapture && !done && it + CHUNK <= maxit) {
       recapture = false;
-      const int64_t calls0 = ctx->spmm_calls;
-      const double bytes0 = ctx->spmm_bytes;
       hipGraph_t graph = nullptr;
       hipGraphExec_t exec = nullptr;
-      HIP_CHECK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-      for (int c = 0; c < CHUNK; ++c) iteration(it + c);
-      ckpt<T, false>(ctx, cplx, (int)n, ncols, xcur, ldxcur, Xb.get(), ld, sc.get(), st.get());
-      HIP_CHECK(hipStreamEndCapture(ctx->stream, &graph));
-      const int64_t dcalls = ctx->spmm_calls - calls0;
-      const double dbytes = ctx->spmm_bytes - bytes0;
-      ctx->spmm_calls = calls0;
-      ctx->spmm_bytes = bytes0;
-      HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-      while (it < maxit && !done) {
-        HIP_CHECK(hipGraphLaunch(exec, ctx->stream));
+      int64_t dcalls = 0;
+      double dbytes = 0.0;
+      if (graphs) {
+        const int64_t calls0 = ctx->spmm_calls;
+        const double bytes0 = ctx->spmm_bytes;
+        HIP_CHECK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        for (int c = 0; c < CHUNK; ++c) iteration(it + c);
+        ckpt<T, false>(ctx, cplx, (int)n, ncols, xcur, ldxcur, Xb.get(), ld, sc.get(), st.get());
+        HIP_CHECK(hipStreamEndCapture(ctx->stream, &graph));
+        dcalls = ctx->spmm_calls - calls0;
+        dbytes = ctx->spmm_bytes - bytes0;
+        ctx->spmm_calls = calls0;
+        ctx->spmm_bytes = bytes0;
+        HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      }
+      while (it + CHUNK <= maxit && !done) {
+        if (graphs) {
+          HIP_CHECK(hipGraphLaunch(exec, ctx->stream));
+          ctx->spmm_calls += dcalls;
+          ctx->spmm_bytes += dbytes;
+        } else {
+          for (int c = 0; c < CHUNK; ++c) iteration(it + c);
+          ckpt<T, false>(ctx, cplx, (int)n, ncols, xcur, ldxcur, Xb.get(), ld, sc.get(), st.get());
+        }
         it += CHUNK;
-        ctx->spmm_calls += dcalls;
-        ctx->spmm_bytes += dbytes;
         d2h(ctx, hst.data(), st.get(), hst.size() * sizeof(int));
         int active = 0;
         for (int c = 0; c < nl; ++c) active += hst[(size_t)c * KI + KI_ACTIVE];
@@ -857,10 +872,16 @@ static KrylovResult bicgstab_core(Ctx* ctx, const SellOp& op, double pr, double 
           break;
         }
       }
-      (void)hipGraphExecDestroy(exec);
-      (void)hipGraphDestroy(graph);
+      if (graphs) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+      }
     }
+    next_check = it + check_every;
   }
+  direct_until(maxit, false);
+  account(0);
+  ctx->spmm_defer = false;
   // columns that stopped without converging fall back to their best checkpoint
   ckpt<T, true>(ctx, cplx, (int)n, ncols, xcur, ldxcur, Xb.get(), ld, sc.get(), st.get());
   {
@@ -981,6 +1002,9 @@ KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncol
     }
   }
   for (int round = 0; round < MAX_RESTARTS; ++round) {
+    // the restart rounds share the caller's iteration budget
+    const int left = maxit - res.max_iters;
+    if (left <= 0) break;
     std::vector<int> cols;
     for (int c = 0; c < nl; ++c)
       if (!res.col_ok[c] && res.col_relres[c] > floor_rel[c]) cols.push_back(c);
@@ -996,7 +1020,7 @@ KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncol
     axpby<T>(ctx, n, ncr, 1.0, Bc.get(), ld, -1.0, Rc.get(), ld);    // Rc = b - M x
     std::vector<double> ct2(nc);
     for (int j = 0; j < nc; ++j) ct2[j] = tgt2[cols[j]];
-    KrylovResult r2 = bicgstab_core<T>(ctx, op, pr, pi, ncr, Rc.get(), ld, D.get(), ld, tol, maxit, check_every,
+    KrylovResult r2 = bicgstab_core<T>(ctx, op, pr, pi, ncr, Rc.get(), ld, D.get(), ld, tol, left, check_every,
                                        nullptr, &ct2);
     for (int e = 0; e < ncr; ++e)
       axpby<T>(ctx, n, 1, 1.0, D.get() + (int64_t)e * ld, ld, 1.0, x + (int64_t)map[e] * ldx, ldx);

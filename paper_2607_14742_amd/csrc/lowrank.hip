@@ -308,6 +308,11 @@ double factor_lam_max(Ctx* ctx, int64_t n, const double* Z, int64_t ldz, int r) 
   if (r <= 0) return 0.0;
   DBuf<double> G(ctx, (size_t)r * r);
   gram(ctx, n, Z, ldz, r, Z, ldz, r, G.get(), r);
+  // a non-finite entry of Z shows in its Gram (the diagonal sums squares)
+  std::vector<double> hg((size_t)r * r);
+  d2h(ctx, hg.data(), G.get(), hg.size() * sizeof(double));
+  for (double g : hg)
+    if (!std::isfinite(g)) fail(CARE_ERR_NONFINITE, "the factor has non-finite entries");
   std::vector<double> lam;
   dsyevd(ctx, r, G.get(), r, lam);
   return std::max(lam.back(), 0.0);

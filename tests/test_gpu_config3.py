@@ -1,0 +1,87 @@
+"""The full 64^3 rotating-field workload (n = 262,144, m = 1, p = 10) against
+the FP64 oracle's solution: the oracle's shift set (complex-conjugate pairs)
+on both sides, FP32 and bf16-product inner solves with FP64 refinement.
+Each result's error is stated against sampled rows of the oracle's X
+(tests/golden/config3_x_samples.json: entries X[I, I] and a Gaussian sketch
+X[I, :] Omega) and the oracle evaluates the residual of each returned factor
+itself (Householder QR of [Z, A^T Z, C^T])."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import lowrank
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "config3_x_samples.json")))
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2607_14742_amd as pk
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pk.load()
+    return pk
+
+
+@pytest.fixture(scope="module")
+def ctx(pk):
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def prob():
+    return wl.config3()
+
+
+def sample_errors(Z):
+    rng = np.random.default_rng(GOLDEN["sample_seed"])
+    n = Z.shape[0]
+    rows = np.sort(rng.choice(n, len(GOLDEN["rows"]), replace=False))
+    assert list(rows) == GOLDEN["rows"]
+    omega = rng.standard_normal((n, len(GOLDEN["sketch"][0])))
+    Zi = Z[rows]
+    b0, s0 = np.asarray(GOLDEN["block"]), np.asarray(GOLDEN["sketch"])
+    eb = np.linalg.norm(Zi @ Zi.T - b0) / np.linalg.norm(b0)
+    es = np.linalg.norm(Zi @ (Z.T @ omega) - s0) / np.linalg.norm(s0)
+    return eb, es
+
+
+def test_golden_shift_set_has_conjugate_pairs():
+    s = np.array(GOLDEN["shifts"]["re"]) + 1j * np.array(GOLDEN["shifts"]["im"])
+    assert np.any(s.imag != 0) and np.all(s.real < 0)
+    assert GOLDEN["relres"] <= 1e-13
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,tol,xgate", [("fp32", 1e-10, False), ("fp32", 1e-12, True),
+                                            ("bf16", 1e-10, False)])
+def test_config3_vs_oracle(pk, ctx, prob, prec, tol, xgate):
+    P = prob
+    shifts = np.array(GOLDEN["shifts"]["re"]) + 1j * np.array(GOLDEN["shifts"]["im"])
+    print(f"config3 64^3 prec={prec} tol={tol:g}", flush=True)
+    dev = lambda x: torch.as_tensor(np.asarray(x, dtype=np.float64), device="cuda")  # noqa: E731
+    Z, stats, st = pk.care_solve(ctx, pk.DeviceCSR.from_scipy(P.A), dev(P.B), dev(P.C), tol=tol, shifts=shifts,
+                                 prec=prec, rmax=4000)
+    Z = Z.cpu().numpy()
+    eb, es = sample_errors(Z)
+    rel = lowrank.residual_norm(P.A, P.B, P.C, Z) / np.linalg.norm(P.C @ P.C.T)
+    print(f"  status {st} rank {Z.shape[1]} solver relres {stats['res_rel']:.2e} oracle relres {rel:.2e} "
+          f"X[I,I] err {eb:.2e} sketch err {es:.2e} iter0 {stats['iter0_outer']}({stats['iter0_inner']}) "
+          f"iter {stats['iter_outer']}({stats['iter_inner']}) t {stats['t_total']:.2f} s", flush=True)
+    assert st == 0, stats
+    assert rel <= tol
+    assert abs(rel - stats["res_rel"]) <= 0.05 * rel + 1e-15
+    if xgate:
+        assert eb <= 1e-8 and es <= 1e-8
+    else:
+        # first-order reach of the residual in X: well inside 1e-6 at tol 1e-10
+        assert eb <= 1e-6 and es <= 1e-6
