@@ -271,6 +271,21 @@ care_status care_shifted_solve(care_ctx* ctx, const care_csr* A, const double* B
 care_status care_gram(care_ctx* ctx, int64_t n, const double* X, int64_t ldx, int32_t a, const double* Y,
                       int64_t ldy, int32_t b, double* C, int64_t ldc);
 
+/* care_gram for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same product C = X^T Y with the library's own FP64 MFMA kernel only (no
+ * rocBLAS), its row-split partial sums kept in a fixed 32 MiB device array
+ * of the library (one per GPU, held until the process ends) instead of
+ * allocated workspace; no allocation of any kind.  Arguments as care_gram;
+ * limit: ceil(a/32) * ceil(b/32) <= 4096 (e.g. a = b = 2048), larger sizes
+ * return CARE_ERR_ARG; n = 0 returns CARE_ERR_ARG.  C is not exactly
+ * symmetric for X == Y (every tile is computed).  All calls on one GPU share
+ * the array: calls that overlap on one GPU (other threads, other contexts)
+ * race on it and must be serialised by the caller.  Returns after the
+ * product has completed. */
+care_status care_gram_noalloc(care_ctx* ctx, int64_t n, const double* X, int64_t ldx, int32_t a, const double* Y,
+                              int64_t ldy, int32_t b, double* C, int64_t ldc);
+
 /* Tall-skinny product Y = alpha X S + beta Y (FP64 matrix cores: rocBLAS
  * dgemm for q * k >= 4096, the library's own MFMA kernel below): X n x q
  * (ldx >= n), S q x k (lds >= q), Y n x k (ldy >= n); beta = 0 does not read

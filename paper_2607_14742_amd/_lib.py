@@ -92,6 +92,7 @@ SIGNATURES = {
     "care_shifted_solve": (I32, [P, C.POINTER(care_csr), P, I64, P, I64, I32, care_shift, P, I64, I32, I32, DBL,
                                  I32, P, I64, PI32]),
     "care_gram": (I32, [P, I64, P, I64, I32, P, I64, I32, P, I64]),
+    "care_gram_noalloc": (I32, [P, I64, P, I64, I32, P, I64, I32, P, I64]),
     "care_tsgemm": (I32, [P, I64, P, I64, I32, P, I64, I32, DBL, DBL, P, I64]),
     "lyap_lradi": (I32, [P, C.POINTER(care_csr), P, P, I32, P, I64, I32, C.POINTER(care_shift), I32, DBL,
                          C.POINTER(care_opts), P, I64, I32, PI32, C.POINTER(care_stats)]),

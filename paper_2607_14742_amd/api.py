@@ -203,6 +203,19 @@ def gram(ctx, X, Y):
     return C_
 
 
+def gram_noalloc(ctx, X, Y, C_=None):
+    """C = X^T Y through the allocation-free entry point (the library's own
+    MFMA kernel, partials in its fixed device array).  C_ (a x b, column-major
+    FP64) may be passed in, so that the call itself allocates nothing."""
+    X = colmajor(X)
+    Y = colmajor(Y)
+    if C_ is None:
+        C_ = empty_colmajor(X.shape[1], Y.shape[1], X.device)
+    _check(_lib().care_gram_noalloc(ctx.h, X.shape[0], _ptr(X), _ld(X), X.shape[1], _ptr(Y), _ld(Y), Y.shape[1],
+                                    _ptr(C_), _ld(C_)))
+    return C_
+
+
 def tsgemm(ctx, X, S, alpha=1.0, beta=0.0, Y=None):
     """Y = alpha X S + beta Y (FP64 matrix cores)."""
     X, S = colmajor(X), colmajor(S)

@@ -241,6 +241,24 @@ care_status care_gram(care_ctx* cx, int64_t n, const double* X, int64_t ldx, int
   });
 }
 
+care_status care_gram_noalloc(care_ctx* cx, int64_t n, const double* X, int64_t ldx, int32_t a, const double* Y,
+                              int64_t ldy, int32_t b, double* Cm, int64_t ldc) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    if (n < 0 || a < 0 || b < 0) fail(CARE_ERR_ARG, "negative size");
+    if (a == 0 || b == 0) return CARE_OK;
+    if (!X || !Y || !Cm || ldx < std::max<int64_t>(n, 1) || ldy < std::max<int64_t>(n, 1) || ldc < a)
+      fail(CARE_ERR_ARG, "invalid pointers or leading dimensions");
+    const int64_t tiles = (int64_t)((a + 31) / 32) * ((b + 31) / 32);
+    if (tiles * 1024 > (int64_t)scratch_doubles())
+      fail(CARE_ERR_ARG, "a x b beyond the fixed scratch array: ceil(a/32) ceil(b/32) must be <= " +
+                             std::to_string(scratch_doubles() / 1024));
+    gram_noalloc(ctx, n, X, ldx, a, Y, ldy, b, Cm, ldc);
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    return CARE_OK;
+  });
+}
+
 care_status care_tsgemm(care_ctx* cx, int64_t n, const double* X, int64_t ldx, int32_t q, const double* S,
                         int64_t lds, int32_t k, double alpha, double beta, double* Y, int64_t ldy) {
   return guarded([&]() -> care_status {

@@ -151,6 +151,10 @@ struct Ctx {
 void ctx_init(Ctx& c, int device, hipStream_t user_stream, const AllocHooks& hooks = AllocHooks());
 // Release everything ctx_init acquired (waits for the stream first).
 void ctx_release(Ctx& c);
+// Look up, once per device, the address of the allocation-free entry
+// point's fixed device array (called by ctx_init with the device current).
+void scratch_setup(int device);
+size_t scratch_doubles();
 
 
 // RAII device buffer from the context arena

@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(256) k_gram(int64_t n, const TX* __restrict__ 
                                               int64_t rows_per_split, const int* __restrict__ tile_list,
                                               double* __restrict__ part) {
   const int tl = blockIdx.x;
-  const int tcode = tile_list[tl];
+  const int tcode = tile_list ? tile_list[tl] : tl;   // no list: every tile, in order
   const int ti = tcode / tiles_j, tj = tcode % tiles_j;
   const int i0 = ti * 32, j0 = tj * 32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(256) k_gram(int64_t n, const TX* __restrict__ 
 __global__ void k_gram_reduce(const double* __restrict__ part, int ntl, int nsplit, const int* __restrict__ tile_list,
                               int tiles_j, int a, int b, int sym, double* __restrict__ C, int64_t ldc) {
   const int tl = blockIdx.x;
-  const int tcode = tile_list[tl];
+  const int tcode = tile_list ? tile_list[tl] : tl;
   const int ti = tcode / tiles_j, tj = tcode % tiles_j;
   for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
     const int ii = e >> 5, jj = e & 31;
@@ -221,6 +221,35 @@ void gram(Ctx* ctx, int64_t n, const TX* X, int64_t ldx, int a, const TY* Y, int
   hipLaunchKernelGGL(k_gram_reduce, dim3(ntl), dim3(256), 0, ctx->stream, part.get(), ntl, nsplit, dtl.get(), tiles_j,
                      a, b, sym ? 1 : 0, C, ldc);
   KERNEL_CHECK();
+}
+
+// The library's own FP64 MFMA Gram over every 32 x 32 output tile, with the
+// row-split partials in a caller-provided buffer of `part_doubles` doubles;
+// no allocation and no host-to-device copy.  Returns false (nothing
+// launched) when one row split of partials does not fit.
+bool gram_own_into(Ctx* ctx, int64_t n, const double* X, int64_t ldx, int a, const double* Y, int64_t ldy, int b,
+                   double* C, int64_t ldc, double* part, size_t part_doubles) {
+  const int tiles_i = (a + 31) / 32, tiles_j = (b + 31) / 32;
+  const int64_t ntl = (int64_t)tiles_i * tiles_j;
+  if (ntl * 1024 > (int64_t)part_doubles) return false;
+  // aim at ~4 workgroups per CU, at least 256 rows per split, within the buffer
+  const int64_t cap = (int64_t)part_doubles / (ntl * 1024);
+  int64_t want = std::max<int64_t>(1, std::min<int64_t>(cap, (int64_t)4 * ctx->num_cu / ntl));
+  int64_t rps = std::max<int64_t>(256, (n + want - 1) / want);
+  rps = (rps + 63) / 64 * 64;
+  int64_t nsplit = (n + rps - 1) / rps;
+  while (nsplit > cap) {           // rounding of rps up can leave one split too many
+    rps += 64;
+    nsplit = (n + rps - 1) / rps;
+  }
+  nsplit = std::max<int64_t>(nsplit, 1);
+  hipLaunchKernelGGL((k_gram<double, double>), dim3((unsigned)ntl, (unsigned)nsplit), dim3(256), 0, ctx->stream, n, X,
+                     ldx, a, Y, ldy, b, tiles_j, rps, (const int*)nullptr, part);
+  KERNEL_CHECK();
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)ntl), dim3(256), 0, ctx->stream, (const double*)part, (int)ntl,
+                     (int)nsplit, (const int*)nullptr, tiles_j, a, b, 0, C, ldc);
+  KERNEL_CHECK();
+  return true;
 }
 
 // ---------------------------------------------------------------------------

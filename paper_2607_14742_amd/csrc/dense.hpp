@@ -18,6 +18,18 @@ template <typename TX, typename TY>
 void gram(Ctx* ctx, int64_t n, const TX* X, int64_t ldx, int a, const TY* Y, int64_t ldy, int b, double* C,
           int64_t ldc);
 
+// The library's own MFMA Gram (every output tile, no symmetry shortcut) with
+// its row-split partials in `part` (part_doubles doubles, device memory of
+// the caller): allocates nothing.  false = the partials of one split do not
+// fit (ceil(a/32) ceil(b/32) 1024 > part_doubles); nothing is launched then.
+bool gram_own_into(Ctx* ctx, int64_t n, const double* X, int64_t ldx, int a, const double* Y, int64_t ldy, int b,
+                   double* C, int64_t ldc, double* part, size_t part_doubles);
+
+// care_gram_noalloc: gram_own_into with the partials in the library's fixed
+// device array (noalloc.hip)
+void gram_noalloc(Ctx* ctx, int64_t n, const double* X, int64_t ldx, int a, const double* Y, int64_t ldy, int b,
+                  double* C, int64_t ldc);
+
 // Y = alpha X S + beta Y  (beta == 0: Y is not read)
 template <typename TX, typename TY>
 void tsgemm(Ctx* ctx, int64_t n, const TX* X, int64_t ldx, int q, const double* S, int64_t lds, int k,

@@ -194,6 +194,7 @@ void ctx_init(Ctx& c, int device, hipStream_t user_stream, const AllocHooks& hoo
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c.num_cu = prop.multiProcessorCount;
   c.arena = new Arena(c.stream, c.hooks);
+  scratch_setup(device);
   if (rocblas_create_handle(&c.blas) != rocblas_status_success) {
     c.blas = nullptr;
     ctx_release(c);
