@@ -164,6 +164,14 @@ typedef struct {
                              each time the ADI residual has halved, so that the
                              column freezing can take the directions the residual
                              has left; 0: W is never rotated                       */
+  int32_t krylov_rb;      /* 1 (default): when the pattern of A is two-colourable and its
+                             diagonal one constant d (five- and seven-point stencils),
+                             each shifted solve eliminates one colour exactly and the
+                             Krylov method runs on the other: (G + p' I) x_b =
+                             F b_r - (d + p) b_b, G = F E, p' = -(d + p)^2, then
+                             x_r = (b_r - E x_b) / (d + p) (the red-black block
+                             factorisation behind a multicolour ILU of the stencil,
+                             with the black block's fill kept); 0: never        */
 } care_opts;
 
 /* Statistics written by the solvers (host struct). */

@@ -40,7 +40,7 @@ class care_opts(C.Structure):
         ("spmm_split", C.c_int32), ("krylov_relax", C.c_int32), ("refine_forcing", C.c_double),
         ("tau_L0", C.c_double), ("spmm_tune", C.c_int32), ("shift_update", C.c_int32),
         ("krylov_method", C.c_int32), ("krylov_restart", C.c_int32), ("krylov_compact", C.c_int32),
-        ("adi_rotate", C.c_int32),
+        ("adi_rotate", C.c_int32), ("krylov_rb", C.c_int32),
     ]
 
 

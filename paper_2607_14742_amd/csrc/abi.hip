@@ -106,6 +106,7 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->r_init = 0;
   o->adi_deflate = 1;
   o->krylov_block_tol = -1;
+  o->krylov_rb = 1;
 }
 
 care_status care_ctx_create(care_ctx** out, int32_t device, void* stream, care_alloc_fn alloc,
@@ -192,6 +193,8 @@ care_status care_shifted_solve(care_ctx* cx, const care_csr* A, const double* B,
     if (!(p.re < 0) || !std::isfinite(p.re) || !std::isfinite(p.im)) fail(CARE_ERR_ARG, "shift needs Re p < 0");
     SellOp op;
     build_sell(ctx, A, pr, op);
+    ctx->krylov_rb = 1;
+    rb_attach(ctx, rb_analyse(ctx, A), pr, op);
     care_opts d;
     care_opts_default(&d, prec);
     d.krylov_tol = tol;
@@ -307,9 +310,11 @@ care_status lyap_lradi(care_ctx* cx, const care_csr* A, const double* B, const d
     ctx->krylov_method = o->krylov_method;
     ctx->krylov_restart = o->krylov_restart;
     ctx->krylov_compact = o->krylov_compact;
+    ctx->krylov_rb = o->krylov_rb;
     const double t0 = now_s();
     SellOp op;
     build_sell(ctx, A, r.prec, op);
+    if (ctx->krylov_rb) rb_attach(ctx, rb_analyse(ctx, A), r.prec, op);
     LradiOut lo;
     const int zcap = lradi_capacity(w, lp.jmax);
     auto run = [&](auto tag) {
@@ -452,6 +457,8 @@ care_status care_penzl_shifts(care_ctx* cx, const care_csr* A, int32_t l0, int32
     if (!out || !count || l0 < 1 || kp < 1 || km < 0) fail(CARE_ERR_ARG, "invalid Penzl arguments");
     SellOp op;
     build_sell(ctx, A, Prec::F64, op);
+    ctx->krylov_rb = 1;
+    rb_attach(ctx, rb_analyse(ctx, A), Prec::F64, op);
     std::vector<Shift> s = penzl_shifts(ctx, op, l0, kp, km, real_only != 0);
     *count = (int)s.size();
     for (size_t i = 0; i < s.size(); ++i) out[i] = care_shift{s[i].re, s[i].im};

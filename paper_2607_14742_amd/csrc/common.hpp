@@ -124,6 +124,7 @@ struct Ctx {
   int krylov_method = 0;            // shifted solves: 0 BiCGStab, 1 restarted GMRES (real shifts)
   int krylov_patient = 0;           // BiCGStab stagnation window max(1000, it/2) (unshifted solves)
   int krylov_graphs = 1;            // 0: no HIP-graph capture of Krylov chunks (batch worker contexts)
+  int krylov_rb = 1;                // 1: shifted solves through the red-black reduction where it applies
   int krylov_compact = 1;           // BiCGStab: gather the still-active columns into fewer panels
   int krylov_restart = 0;           // GMRES restart length (0: 30 in FP32, 50 in FP64)
   double t_spmm = 0.0;

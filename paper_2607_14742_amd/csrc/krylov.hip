@@ -965,6 +965,8 @@ template <typename T>
 KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncols, const T* b, int64_t ldb, T* x,
                       int64_t ldx, double tol, int maxit, int check_every, const std::vector<int>* groups) {
   if (op.dense) return dense_solve<T>(ctx, op, pr, pi, ncols, b, ldb, x, ldx);
+  if (ctx->krylov_rb && rb_usable(op, pr, pi))
+    return bicgstab_rb<T>(ctx, op, pr, pi, ncols, b, ldb, x, ldx, tol, maxit, check_every, groups);
   if (ctx->krylov_method == 1 && pi == 0.0) {
     const int restart = ctx->krylov_restart > 0 ? ctx->krylov_restart : (sizeof(T) == 8 ? 50 : 30);
     return gmres<T>(ctx, op, pr, ncols, b, ldb, x, ldx, tol, maxit, restart, groups);

@@ -36,6 +36,16 @@ KrylovResult bicgstab(Ctx* ctx, const SellOp& op, double pr, double pi, int ncol
                       int64_t ldb, T* x, int64_t ldx, double tol, int maxit, int check_every,
                       const std::vector<int>* groups = nullptr);
 
+// The same solve through the red-black reduction of op (rb.hip): the
+// reduced system (G + p' I) x_b = F b_r - (d + p) b_b goes to bicgstab with
+// the operator G, then x_r = (b_r - E x_b) / (d + p).  Tolerances apply to
+// the reduced right-hand side.  bicgstab() dispatches here when the context
+// enables the reduction and rb_usable() holds.
+template <typename T>
+KrylovResult bicgstab_rb(Ctx* ctx, const SellOp& op, double pr, double pi, int ncols_real, const T* b, int64_t ldb,
+                         T* x, int64_t ldx, double tol, int maxit, int check_every, const std::vector<int>* groups);
+bool rb_usable(const SellOp& op, double pr, double pi);
+
 // Restarted GMRES(restart) for a real shift (gmres.hip): the same contract as
 // bicgstab (zero initial guess, per-column or per-group tolerance); maxit
 // counts Arnoldi steps over all cycles.  bicgstab() dispatches here when the

@@ -25,6 +25,8 @@
 
 namespace mpcare {
 
+struct RbOp;
+
 struct SellOp {
   int64_t n = 0, nnz = 0;          // of A
   int nslices = 0;
@@ -51,6 +53,9 @@ struct SellOp {
     DBuf<int> ipiv;
   };
   mutable std::map<double, std::shared_ptr<DenseLU>> lu;
+  // Red-black reduction of A^T + p I (rb.hip), present when A is two-colourable
+  // with a constant diagonal and the context enables it
+  std::shared_ptr<RbOp> rb;
   // algorithmic bytes of one product with k real columns: the CSR formula
   // nnz (s_v + 4) + 4 (n + 1) plus `passes` n-vectors per column (2 for
   // y = M x; the fused BiCGStab modes move more, see spmm_vec_passes)
@@ -62,6 +67,29 @@ struct SellOp {
 
 // Build A^T in SELL-64 form at precision `prec` from the caller's CSR(A).
 void build_sell(Ctx* ctx, const care_csr* A, Prec prec, SellOp& op);
+
+// Red-black reduction (rb.hip).  When the pattern of A is two-colourable
+// (red / black, every off-diagonal entry couples the two colours; five- and
+// seven-point stencils) and its diagonal is one constant d, the shifted solve
+//   (A^T + p I) x = b,   A^T = [[d I, E], [F, d I]] in red / black order,
+// eliminates the red unknowns exactly: with G = F E (black x black),
+//   (G + p' I) x_b = F b_r - (d + p) b_b,   p' = -(d + p)^2,
+//   x_r = (b_r - E x_b) / (d + p).
+// G + p' I has half the rows and about a quarter of the condition number of
+// A^T + p I.  The host analysis of CSR(A) (two-colouring, G) is done once and
+// attached to every operator built from the same A.
+struct RbHost;
+std::shared_ptr<RbHost> rb_analyse(Ctx* ctx, const care_csr* A);   // nullptr: not applicable
+void rb_attach(Ctx* ctx, const std::shared_ptr<RbHost>& h, Prec prec, SellOp& op);
+struct RbOp {
+  double d = 0.0;                  // the constant diagonal of A
+  int64_t nr = 0, nb = 0;          // red / black rows
+  DBuf<int> red, blk;              // original index of each red / black row
+  DBuf<int> frp, fci;              // F: rows of A^T at black rows, red columns (original indices)
+  DBuf<int> erp, eci;              // E: rows of A^T at red rows, black columns (reduced indices)
+  DBuf<uint8_t> fval, eval;        // values in the operator's vector precision
+  SellOp G;                        // G = F E over the black rows (SELL-64, diagonal kept apart)
+};
 
 // Y = (A^T + p I) X for k real columns (complex shift: k complex columns in
 // interleaved [re, im] column pairs, i.e. 2k real columns).  X, Y in the
