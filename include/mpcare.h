@@ -256,6 +256,23 @@ care_status care_struct_sizes(int64_t* sizes, int32_t count);
 care_status care_spmm(care_ctx* ctx, const care_csr* A, int32_t prec, care_shift p,
                       const double* X, int64_t ldx, int32_t k, double* Y, int64_t ldy);
 
+/* Timing of the shifted sparse product alone (the SpMM of the inner solves,
+ * Sec. 4): builds `nsets` copies of the SELL operator of A^T in precision
+ * `prec`, fills nsets input panels of k columns (complex shift: k complex
+ * columns), runs one warm-up round and then `reps` rounds of
+ * Y_s = (A^T + p I) X_s over the sets in turn (rotating the sets keeps the
+ * operands out of the caches once their total exceeds them), and returns the
+ * mean time per product in microseconds (HIP events on the context's stream)
+ * and the algorithmic bytes of one product, nnz (s_v + 4) + 4 (n + 1) +
+ * 2 n k s_x, in *bytes_per_product (both HOST).  panel = 8 or 16 fixes the
+ * column panel of products wider than 8 columns, 0 uses the default;
+ * panels_per_block > 0 fixes how many column panels one workgroup runs (the
+ * operator's entries are loaded once for all of them), 0 uses the default.
+ * The library allocates the operator copies and panels itself. */
+care_status care_spmm_timing(care_ctx* ctx, const care_csr* A, int32_t prec, care_shift p, int32_t k,
+                             int32_t nsets, int32_t reps, int32_t panel, int32_t panels_per_block,
+                             double* us_per_product, double* bytes_per_product);
+
 /* Shifted block solve (A_k^T + p I) V = W with A_k = A - B K^T, by the
  * Sherman-Morrison-Woodbury formula of Sec. 4: solve (A^T + p I)[Vh, S] = [W, K]
  * with column-batched BiCGStab in precision `prec`, then

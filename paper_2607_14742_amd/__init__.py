@@ -6,10 +6,11 @@ not load the library; the first call does, and fails loudly when the library
 has not been built.
 """
 from ._lib import (CARE_AUTO, CARE_BF16_SPMM, CARE_ERR_ARG, CARE_ERR_BREAKDOWN, CARE_ERR_CAPACITY,  # noqa: F401
-                   CARE_ERR_UNSTABLE, CARE_FP32, CARE_FP64, LIB_PATH, SIGNATURES, STATUS_NAMES, load)
+                   CARE_ERR_NONFINITE, CARE_ERR_UNSTABLE, CARE_FP32, CARE_FP64, LIB_PATH, SIGNATURES, STATUS_NAMES,
+                   load)
 
 __all__ = ["load", "LIB_PATH", "SIGNATURES", "STATUS_NAMES", "CARE_FP64", "CARE_FP32", "CARE_BF16_SPMM", "CARE_AUTO",
-           "CARE_ERR_ARG", "CARE_ERR_CAPACITY", "CARE_ERR_UNSTABLE", "CARE_ERR_BREAKDOWN"]
+           "CARE_ERR_ARG", "CARE_ERR_CAPACITY", "CARE_ERR_UNSTABLE", "CARE_ERR_BREAKDOWN", "CARE_ERR_NONFINITE"]
 
 
 def __getattr__(name):

@@ -89,6 +89,7 @@ SIGNATURES = {
     "care_version": (C.c_char_p, []),
     "care_struct_sizes": (I32, [C.POINTER(I64), I32]),
     "care_spmm": (I32, [P, C.POINTER(care_csr), I32, care_shift, P, I64, I32, P, I64]),
+    "care_spmm_timing": (I32, [P, C.POINTER(care_csr), I32, care_shift, I32, I32, I32, I32, I32, PDBL, PDBL]),
     "care_shifted_solve": (I32, [P, C.POINTER(care_csr), P, I64, P, I64, I32, care_shift, P, I64, I32, I32, DBL,
                                  I32, P, I64, PI32]),
     "care_gram": (I32, [P, I64, P, I64, I32, P, I64, I32, P, I64]),

@@ -191,6 +191,15 @@ def spmm(ctx: Context, A: DeviceCSR, X: torch.Tensor, shift=0.0, prec="fp64") ->
     return Y
 
 
+def spmm_timing(ctx: Context, A: DeviceCSR, k: int, shift=0.0, prec="fp32", nsets=4, reps=5, panel=0, pg=0):
+    """Mean microseconds per product Y = (A^T + p I) X over `nsets` rotated
+    operator / panel sets, and the algorithmic bytes of one product."""
+    us, nb = C.c_double(0), C.c_double(0)
+    _check(_lib().care_spmm_timing(ctx.h, A.c, PREC[prec], _shift(shift), k, nsets, reps, panel, pg, C.byref(us),
+                                   C.byref(nb)))
+    return us.value, nb.value
+
+
 def gram(ctx, X, Y):
     """C = X^T Y (FP64 matrix cores).  Passing the same tensor twice gives an
     exactly symmetric X^T X."""

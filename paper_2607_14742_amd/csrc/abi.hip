@@ -175,6 +175,59 @@ care_status care_spmm(care_ctx* cx, const care_csr* A, int32_t prec, care_shift 
   });
 }
 
+care_status care_spmm_timing(care_ctx* cx, const care_csr* A, int32_t prec, care_shift p, int32_t k, int32_t nsets,
+                             int32_t reps, int32_t panel, int32_t panels_per_block, double* us_per_product,
+                             double* bytes_per_product) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    check_csr_shape(A);
+    const Prec pr = prec_from_abi(prec);
+    if (k < 1 || nsets < 1 || reps < 1) fail(CARE_ERR_ARG, "k, nsets and reps must be >= 1");
+    if (panel != 0 && panel != 8 && panel != 16) fail(CARE_ERR_ARG, "panel must be 0, 8 or 16");
+    if (panels_per_block < 0) fail(CARE_ERR_ARG, "panels_per_block must be >= 0");
+    if (!us_per_product || !bytes_per_product) fail(CARE_ERR_ARG, "output pointer is NULL");
+    if (!std::isfinite(p.re) || !std::isfinite(p.im)) fail(CARE_ERR_ARG, "shift not finite");
+    const bool cp = p.im != 0.0;
+    const int kr = cp ? 2 * k : k;
+    std::vector<SellOp> ops(nsets);
+    for (auto& op : ops) build_sell(ctx, A, pr, op);
+    const int64_t n = A->n, ld = pad_ld(n);
+    const size_t vb = vec_bytes(pr);
+    DBuf<uint8_t> X(ctx, (size_t)nsets * ld * kr * vb), Y(ctx, (size_t)nsets * ld * kr * vb);
+    // inputs of ones (any finite values: the timing does not depend on them)
+    if (pr == Prec::F64) fill_const<double>(ctx, (double*)X.get(), (size_t)nsets * ld * kr, 1.0);
+    else fill_const<float>(ctx, (float*)X.get(), (size_t)nsets * ld * kr, 1.0);
+    ctx->spmm_tune = 0;
+    ctx->spmm_force_cp = panel;
+    ctx->spmm_force_pg = panels_per_block;
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    auto round = [&]() {
+      for (int sI = 0; sI < nsets; ++sI) {
+        void* xs = X.get() + (size_t)sI * ld * kr * vb;
+        void* ys = Y.get() + (size_t)sI * ld * kr * vb;
+        spmm_plain(ctx, ops[sI], p.re, p.im, xs, ld, kr, ys, ld);
+      }
+    };
+    round();   // warm-up (code objects, first touch)
+    HIP_CHECK(hipEventRecord(e0, ctx->stream));
+    for (int r = 0; r < reps; ++r) round();
+    HIP_CHECK(hipEventRecord(e1, ctx->stream));
+    HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->spmm_force_cp = 0;
+    ctx->spmm_force_pg = 0;
+    *us_per_product = 1e3 * (double)ms / ((double)reps * nsets);
+    *bytes_per_product = ops[0].bytes(kr, 2);
+    ctx->sync();
+    return CARE_OK;
+  });
+}
+
 care_status care_shifted_solve(care_ctx* cx, const care_csr* A, const double* B, int64_t ldb, const double* K,
                                int64_t ldk, int32_t m, care_shift p, const double* W, int64_t ldw, int32_t w,
                                int32_t prec, double tol, int32_t maxit, double* V, int64_t ldv, int32_t* iters) {

@@ -334,6 +334,22 @@ void tsgemm(Ctx* ctx, int64_t n, const TX* X, int64_t ldx, int q, const double* 
   KERNEL_CHECK();
 }
 
+template <typename T>
+__global__ void k_fill_const(T* __restrict__ p, size_t count, T v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename T>
+void fill_const(Ctx* ctx, T* p, size_t count, double v) {
+  if (!count) return;
+  const unsigned grid = (unsigned)std::min<size_t>((count + 255) / 256, 16384);
+  hipLaunchKernelGGL((k_fill_const<T>), dim3(grid), dim3(256), 0, ctx->stream, p, count, (T)v);
+  KERNEL_CHECK();
+}
+template void fill_const<double>(Ctx*, double*, size_t, double);
+template void fill_const<float>(Ctx*, float*, size_t, double);
+
 // ---------------------------------------------------------------------------
 // column copies
 // ---------------------------------------------------------------------------

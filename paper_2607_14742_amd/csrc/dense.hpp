@@ -41,6 +41,10 @@ template <typename TI, typename TO>
 void copy_cols(Ctx* ctx, int64_t n, int ncols, const TI* in, int64_t ldi, TO* out, int64_t ldo,
                const int* map = nullptr, const double* scale = nullptr);
 
+// p[0..count) = v
+template <typename T>
+void fill_const(Ctx* ctx, T* p, size_t count, double v);
+
 // Y = a X + b Y on n x ncols panels (same type)
 template <typename T>
 void axpby(Ctx* ctx, int64_t n, int ncols, double a, const T* X, int64_t ldx, double b, T* Y, int64_t ldy);

@@ -217,6 +217,11 @@ void build_sell(Ctx* ctx, const care_csr* A, Prec prec, SellOp& op) {
   exclusive_scan(ctx, width.get(), op.sptr.get(), nsl + 1);
   int total = 0;
   d2h(ctx, &total, op.sptr.get() + nsl, sizeof(int));
+  {
+    std::vector<int> hw(nsl);
+    d2h(ctx, hw.data(), width.get(), nsl * sizeof(int));
+    op.max_width = nsl ? *std::max_element(hw.begin(), hw.end()) : 0;
+  }
 
   op.n = n;
   op.nnz = nnz;
@@ -268,23 +273,36 @@ void build_sell(Ctx* ctx, const care_csr* A, Prec prec, SellOp& op) {
 // ---------------------------------------------------------------------------
 // launcher
 // ---------------------------------------------------------------------------
+template <typename TV, typename T, int CP, bool CPLX, int WMAX>
+static void launch_mode(hipStream_t st, dim3 g, int mode, const SpmmArgs<T>& a) {
+  if (mode == MODE_PLAIN) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_PLAIN, CPLX, WMAX>), g, dim3(256), 0, st, a);
+  else if (mode == MODE_DOT1) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_DOT1, CPLX, WMAX>), g, dim3(256), 0, st, a);
+  else if (mode == MODE_DOT2) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_DOT2, CPLX, WMAX>), g, dim3(256), 0, st, a);
+  // the fused BiCGStab modes stream their entries (one panel per workgroup)
+  else if (mode == MODE_BICG_P) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_P, CPLX, 0>), g, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_S, CPLX, 0>), g, dim3(256), 0, st, a);
+}
+
+// Row-width class: rows of at most 4 entries are preloaded at every panel
+// width; rows of at most 8 only for panels of at most 4 columns, since wider
+// panels then hold 8 x panel gathers in flight per thread and the register
+// cost (one or two waves per SIMD) outweighs the shorter load chain.
+template <typename TV, typename T, int CP, bool CPLX>
+static void launch_w(hipStream_t st, dim3 g, int mode, int wmax, const SpmmArgs<T>& a) {
+  if (wmax == 4) launch_mode<TV, T, CP, CPLX, 4>(st, g, mode, a);
+  else if (wmax == 8 && CP <= 4) launch_mode<TV, T, CP, CPLX, (CP <= 4 ? 8 : 0)>(st, g, mode, a);
+  else launch_mode<TV, T, CP, CPLX, 0>(st, g, mode, a);
+}
+
 template <typename TV, typename T, int CP>
-static void launch_cp(hipStream_t st, dim3 g, int mode, bool cplx, const SpmmArgs<T>& a) {
+static void launch_cp(hipStream_t st, dim3 g, int mode, bool cplx, int wmax, const SpmmArgs<T>& a) {
   if constexpr (CP >= 2) {
     if (cplx) {
-      if (mode == MODE_PLAIN) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_PLAIN, true>), g, dim3(256), 0, st, a);
-      else if (mode == MODE_BICG_P) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_P, true>), g, dim3(256), 0, st, a);
-      else if (mode == MODE_BICG_S) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_S, true>), g, dim3(256), 0, st, a);
-      else if (mode == MODE_DOT1) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_DOT1, true>), g, dim3(256), 0, st, a);
-      else hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_DOT2, true>), g, dim3(256), 0, st, a);
+      launch_w<TV, T, CP, true>(st, g, mode, wmax, a);
       return;
     }
   }
-  if (mode == MODE_PLAIN) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_PLAIN, false>), g, dim3(256), 0, st, a);
-  else if (mode == MODE_BICG_P) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_P, false>), g, dim3(256), 0, st, a);
-  else if (mode == MODE_BICG_S) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_S, false>), g, dim3(256), 0, st, a);
-  else if (mode == MODE_DOT1) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_DOT1, false>), g, dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_DOT2, false>), g, dim3(256), 0, st, a);
+  launch_w<TV, T, CP, false>(st, g, mode, wmax, a);
 }
 
 static int default_cp(int k, bool cplx) {
@@ -293,27 +311,42 @@ static int default_cp(int k, bool cplx) {
   return cp;
 }
 
+// Panels per workgroup: one where few row blocks exist (the grid needs the
+// panels for parallelism), else as many as keep about 1024 workgroups, in
+// groups of equal size; the fused modes keep one panel per workgroup.
+static int panels_per_block(int64_t nrb, int panels, int mode, int force) {
+  if (mode == MODE_BICG_P || mode == MODE_BICG_S || panels <= 1) return 1;
+  if (force > 0) return std::min(force, panels);
+  const int target = (int)std::max<int64_t>(1, std::min<int64_t>(panels, nrb * panels / 1024));
+  const int groups = (panels + target - 1) / target;
+  return (panels + groups - 1) / groups;
+}
+
 template <typename TV, typename T>
-static void launch_tv(hipStream_t st, int64_t n, int mode, bool cplx, const SpmmArgs<T>& a, int cp) {
+static void launch_tv(hipStream_t st, int64_t n, int mode, bool cplx, SpmmArgs<T> a, int cp, int wmax, int force_pg) {
   const int k = a.ncols;
-  dim3 g(spmm_rowblocks(n), ceil_div(k, cp));
+  const int panels = ceil_div(k, cp);
+  a.pg = panels_per_block(spmm_rowblocks(n), panels, mode, force_pg);
+  dim3 g(spmm_rowblocks(n), ceil_div(panels, a.pg));
   switch (cp) {
-    case 1: launch_cp<TV, T, 1>(st, g, mode, cplx, a); break;
-    case 2: launch_cp<TV, T, 2>(st, g, mode, cplx, a); break;
-    case 4: launch_cp<TV, T, 4>(st, g, mode, cplx, a); break;
-    case 8: launch_cp<TV, T, 8>(st, g, mode, cplx, a); break;
-    default: launch_cp<TV, T, 16>(st, g, mode, cplx, a); break;
+    case 1: launch_cp<TV, T, 1>(st, g, mode, cplx, wmax, a); break;
+    case 2: launch_cp<TV, T, 2>(st, g, mode, cplx, wmax, a); break;
+    case 4: launch_cp<TV, T, 4>(st, g, mode, cplx, wmax, a); break;
+    case 8: launch_cp<TV, T, 8>(st, g, mode, cplx, wmax, a); break;
+    default: launch_cp<TV, T, 16>(st, g, mode, cplx, wmax, a); break;
   }
 }
 
 template <typename T>
 static void launch_prec(Ctx* ctx, const SellOp& op, int mode, bool cplx, const SpmmArgs<T>& a, int cp) {
+  const int wmax = op.max_width <= 4 ? 4 : (op.max_width <= 8 ? 8 : 0);
+  const int fpg = ctx->spmm_force_pg;
   if constexpr (sizeof(T) == 8) {
     if (op.prec != Prec::F64) fail(CARE_ERR_ARG, "FP64 vectors need the FP64 operator");
-    launch_tv<double, double>(ctx->stream, op.n, mode, cplx, a, cp);
+    launch_tv<double, double>(ctx->stream, op.n, mode, cplx, a, cp, wmax, fpg);
   } else {
-    if (op.prec == Prec::F32) launch_tv<float, float>(ctx->stream, op.n, mode, cplx, a, cp);
-    else if (op.prec == Prec::BF16) launch_tv<bf16, float>(ctx->stream, op.n, mode, cplx, a, cp);
+    if (op.prec == Prec::F32) launch_tv<float, float>(ctx->stream, op.n, mode, cplx, a, cp, wmax, fpg);
+    else if (op.prec == Prec::BF16) launch_tv<bf16, float>(ctx->stream, op.n, mode, cplx, a, cp, wmax, fpg);
     else fail(CARE_ERR_ARG, "FP32 vectors need an FP32 or BF16 operator");
   }
   KERNEL_CHECK();
@@ -334,6 +367,7 @@ template <typename T>
 static int tuned_cp(Ctx* ctx, const SellOp& op, int mode, bool cplx, const SpmmArgs<T>& a) {
   const int k = a.ncols;
   const int cp0 = default_cp(k, cplx);
+  if (cp0 == 16 && ctx->spmm_force_cp) return ctx->spmm_force_cp;
   if (!ctx->spmm_tune || cp0 != 16 || !(mode == MODE_PLAIN || mode == MODE_DOT1 || mode == MODE_DOT2)) return cp0;
   const int key = mode | (cplx ? 8 : 0) | (std::min((int)ceil_div(k, 16), 64) << 4) | (sizeof(T) == 8 ? 1 << 12 : 0);
   auto it = op.cp_choice.find(key);

@@ -31,6 +31,7 @@ struct SellOp {
   int64_t n = 0, nnz = 0;          // of A
   int nslices = 0;
   int64_t width_total = 0;         // sum of slice widths
+  int max_width = 0;               // widest slice (off-diagonal entries per row)
   Prec prec = Prec::F64;
   DBuf<int> sptr;                  // nslices + 1
   DBuf<int> cols;                  // width_total * 64

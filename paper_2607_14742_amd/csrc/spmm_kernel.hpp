@@ -71,6 +71,7 @@ struct SpmmArgs {
   const int* st = nullptr;
   double* part = nullptr;        // [(dot * ncols + col) * nrb + rowblock]
   int nrb = 0;
+  int pg = 1;                    // column panels per workgroup (grid y = ceil(panels / pg))
 };
 
 template <typename T, typename TV>
@@ -112,22 +113,69 @@ __device__ __forceinline__ void block_reduce_to(const T (&v)[NV], Dst dst) {
   }
 }
 
-template <typename TV, typename T, int CP, int MODE, bool CPLX>
+// Complex products with their roundings fixed: re = fma(ar, br, -(ai bi)),
+// im = fma(ar, bi, ai br).
+template <typename T>
+__device__ __forceinline__ T cmul_re(T ar, T ai, T br, T bi) {
+#pragma clang fp contract(off)
+  return fma(ar, br, -(ai * bi));
+}
+template <typename T>
+__device__ __forceinline__ T cmul_im(T ar, T ai, T br, T bi) {
+#pragma clang fp contract(off)
+  return fma(ar, bi, ai * br);
+}
+
+template <typename TV, typename T, int CP, int MODE, bool CPLX, int WMAX>
 __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
+  // Every fused multiply-add below is written out and no other is formed, so
+  // a column's arithmetic is the same in every instance of the kernel (panel
+  // width, row-width class, panels per workgroup): results do not depend on
+  // how the columns are grouped into panels.
+#pragma clang fp contract(off)
   constexpr int NDOT = MODE == MODE_PLAIN ? 0 : ((MODE == MODE_BICG_P || MODE == MODE_DOT1) ? 1 : 2);
   constexpr bool XIN = MODE == MODE_PLAIN || MODE == MODE_DOT1 || MODE == MODE_DOT2;   // input read from X
   constexpr int NL = CPLX ? CP / 2 : CP;          // logical columns in the panel
   static_assert(!CPLX || (CP % 2 == 0), "complex panels hold column pairs");
 
-  // grid: (row block, panel); consecutive row blocks of a panel share an XCD
-  // (and the halo rows of the neighbouring blocks in its L2).  Running the
-  // panels of one row block back to back instead (to read the matrix once)
-  // was measured slower: the halo rows matter more than the matrix re-reads.
+  // grid: (row block, group of pg panels); consecutive row blocks share an
+  // XCD (and the halo rows of the neighbouring blocks in its L2)
   const int rb = (int)xcd_remap(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   const int i = rb * 256 + tid;
-  const int c0 = blockIdx.y * CP;                   // first real column of the panel
   const int64_t ld = a.ld;
+
+  // The row's off-diagonal entries.  With WMAX > 0 (operators whose slices
+  // hold at most WMAX entries per row) they are loaded once, before the
+  // panels, padded with zero entries at the row itself: every gather of a
+  // panel can then be issued at once (no chain of index loads), and the
+  // matrix is read once for all the workgroup's panels.  WMAX = 0 streams the
+  // entries panel by panel.
+  int sbeg = 0, send = 0;
+  if (i < a.n) {
+    sbeg = a.sptr[i >> 6];
+    send = a.sptr[(i >> 6) + 1];
+  }
+  int cj[WMAX > 0 ? WMAX : 1];
+  T cv[WMAX > 0 ? WMAX : 1];
+  if constexpr (WMAX > 0) {
+    const TV* vals = (const TV*)a.vals;
+    const int lane = i & 63;
+#pragma unroll
+    for (int t = 0; t < WMAX; ++t) {
+      cj[t] = i < a.n ? i : 0;
+      cv[t] = (T)0;
+      if (sbeg + t < send) {
+        const int64_t e = (int64_t)(sbeg + t) * 64 + lane;
+        cj[t] = a.cols[e];
+        cv[t] = load_val<T, TV>(vals, e);
+      }
+    }
+  }
+
+  for (int pgi = 0; pgi < a.pg; ++pgi) {
+  const int c0 = (blockIdx.y * a.pg + pgi) * CP;    // first real column of the panel
+  if (c0 >= a.ncols) break;                         // uniform over the workgroup
 
   bool act[NL];
   bool first[NL];
@@ -185,28 +233,28 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
       // the first iteration needs no branch (their contents are then unused)
       if (!CPLX) {
         const T rv = a.r[o];
-        const T upd = rv + sA_r[q] * (a.pold[o] - sB_r[q] * a.vold[o]);
+        const T upd = fma(sA_r[q], fma(-sB_r[q], a.vold[o], a.pold[o]), rv);
         xr = first[q] ? rv : upd;
         xi = (T)0;
       } else {
         const T rr = a.r[o], ri = a.r[o + ld];
         const T pr = a.pold[o], pi = a.pold[o + ld];
         const T vr = a.vold[o], vi = a.vold[o + ld];
-        const T ur = pr - (sB_r[q] * vr - sB_i[q] * vi);
-        const T ui = pi - (sB_r[q] * vi + sB_i[q] * vr);
-        const T ar = rr + (sA_r[q] * ur - sA_i[q] * ui);
-        const T ai = ri + (sA_r[q] * ui + sA_i[q] * ur);
+        const T ur = pr - cmul_re(sB_r[q], sB_i[q], vr, vi);
+        const T ui = pi - cmul_im(sB_r[q], sB_i[q], vr, vi);
+        const T ar = rr + cmul_re(sA_r[q], sA_i[q], ur, ui);
+        const T ai = ri + cmul_im(sA_r[q], sA_i[q], ur, ui);
         xr = first[q] ? rr : ar;
         xi = first[q] ? ri : ai;
       }
     } else {  // MODE_BICG_S
       if (!CPLX) {
-        xr = a.r[o] - sA_r[q] * a.vold[o];
+        xr = fma(-sA_r[q], a.vold[o], a.r[o]);
         xi = (T)0;
       } else {
         const T vr = a.vold[o], vi = a.vold[o + ld];
-        xr = a.r[o] - (sA_r[q] * vr - sA_i[q] * vi);
-        xi = a.r[o + ld] - (sA_r[q] * vi + sA_i[q] * vr);
+        xr = a.r[o] - cmul_re(sA_r[q], sA_i[q], vr, vi);
+        xi = a.r[o + ld] - cmul_im(sA_r[q], sA_i[q], vr, vi);
       }
     }
   };
@@ -233,25 +281,40 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
       if (!CPLX) {
         acc_r[q] = d0 * x0r;
       } else {
-        acc_r[q] = d0 * x0r - sim0 * x0i;
-        acc_i[q] = d0 * x0i + sim0 * x0r;
+        acc_r[q] = cmul_re(d0, sim0, x0r, x0i);
+        acc_i[q] = cmul_im(d0, sim0, x0r, x0i);
       }
     }
   }
   if (i < a.n && qa >= 0) {
-    const int s = i >> 6, lane = i & 63;
-    const int beg = a.sptr[s], end = a.sptr[s + 1];
+    const int lane = i & 63;
+    const int beg = sbeg, end = send;
     const TV* vals = (const TV*)a.vals;
+    if constexpr (WMAX > 0) {
+      // all entries' gathers issued without a branch (padding entries read
+      // the row itself, already fetched, with value zero)
+#pragma unroll
+      for (int t = 0; t < WMAX; ++t) {
+        T xr[NL], xi[NL];
+#pragma unroll
+        for (int q = 0; q < NL; ++q) input(q, cj[t], xr[q], xi[q]);
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+          acc_r[q] = fma(cv[t], xr[q], acc_r[q]);
+          if (CPLX) acc_i[q] = fma(cv[t], xi[q], acc_i[q]);
+        }
+      }
+    }
     // software pipeline: the next entry's column index and value are loaded
     // after this entry's gathers have been issued
     int jn = i;
     T avn = (T)0;
-    if (beg < end) {
+    if (WMAX == 0 && beg < end) {
       const int64_t e = (int64_t)beg * 64 + lane;
       jn = a.cols[e];
       avn = load_val<T, TV>(vals, e);
     }
-    for (int t = beg; t < end; ++t) {
+    for (int t = beg; WMAX == 0 && t < end; ++t) {
       const int j = jn;
       const T av = avn;
       T xr[NL], xi[NL];
@@ -264,8 +327,8 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
       }
 #pragma unroll
       for (int q = 0; q < NL; ++q) {
-        acc_r[q] += av * xr[q];
-        if (CPLX) acc_i[q] += av * xi[q];
+        acc_r[q] = fma(av, xr[q], acc_r[q]);
+        if (CPLX) acc_i[q] = fma(av, xi[q], acc_i[q]);
       }
     }
     const T d = a.diag[i] + (T)a.sr;
@@ -290,10 +353,10 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
         yr = acc_r[q];
         yi = CPLX ? acc_i[q] : (T)0;
       } else if (!CPLX) {
-        yr = acc_r[q] + d * xr[q];
+        yr = fma(d, xr[q], acc_r[q]);
       } else {
-        yr = acc_r[q] + d * xr[q] - sim * xi[q];
-        yi = acc_i[q] + d * xi[q] + sim * xr[q];
+        yr = fma(-sim, xi[q], fma(d, xr[q], acc_r[q]));
+        yi = fma(sim, xr[q], fma(d, xi[q], acc_i[q]));
       }
       const int cr = c0 + (CPLX ? 2 * q : q);
       const int64_t o = (int64_t)cr * ld + i;
@@ -315,8 +378,8 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
         if (!CPLX) {
           dots[q] = hr[q] * yr;                      // <rhat, v>
         } else {
-          dots[2 * q] = hr[q] * yr + hi[q] * yi;     // conj(rhat) v
-          dots[2 * q + 1] = hr[q] * yi - hi[q] * yr;
+          dots[2 * q] = fma(hr[q], yr, hi[q] * yi);       // conj(rhat) v
+          dots[2 * q + 1] = fma(hr[q], yi, -(hi[q] * yr));
         }
       } else {   // MODE_DOT2, MODE_BICG_S
         if (MODE == MODE_DOT2) {
@@ -334,9 +397,9 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
           dots[q] = yr * xr[q];                      // <t, s>
           dots[CP + q] = yr * yr;                    // <t, t>
         } else {
-          dots[2 * q] = yr * xr[q] + yi * xi[q];     // conj(t) s
-          dots[2 * q + 1] = yr * xi[q] - yi * xr[q];
-          dots[CP + 2 * q] = yr * yr + yi * yi;      // |t|^2
+          dots[2 * q] = fma(yr, xr[q], yi * xi[q]);       // conj(t) s
+          dots[2 * q + 1] = fma(yr, xi[q], -(yi * xr[q]));
+          dots[CP + 2 * q] = fma(yr, yr, yi * yi);        // |t|^2
           dots[CP + 2 * q + 1] = (T)0;
         }
       }
@@ -348,6 +411,7 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
       if (c < a.ncols) a.part[((int64_t)dot * a.ncols + c) * a.nrb + rb] = val;
     });
   }
+  }   // panels of the workgroup
 }
 
 }  // namespace mpcare
