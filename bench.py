@@ -76,7 +76,7 @@ def spmm_sweep(pk, wl, torch):
     cases = [("fdm2d 500x500", wl.fdm2d(500), -1e3), ("fdm3d 64^3 rotating", wl.fdm3d(64, 100.0), -1e3)]
     for name, A, shift in cases:
         Ad = pk.DeviceCSR.from_scipy(A, "cuda:0")
-        for prec in ("fp32", "fp64", "bf16"):
+        for prec in ("fp32", "fp64", "bf16", "fp16"):
             for k in (1, 2, 4, 8, 16, 32, 64, 128):
                 _, nb = pk.spmm_timing(ctx, Ad, k, shift, prec, nsets=1, reps=1)
                 per_set = nb + A.nnz * 4          # the SELL index padding is within the operator copy

@@ -64,11 +64,20 @@ enum {
   CARE_FP32 = 1,                /* u_s = FP32                                       */
   CARE_BF16_SPMM = 2,           /* FP32 inner solves whose sparse products read the
                                    off-diagonal values of A in bfloat16            */
-  CARE_AUTO = 3                 /* care_solve* only: CARE_FP32 when the shift set's
-                                   spread max|p| / min|p| (a stand-in for the
-                                   condition of A in Theorem 1) is at most 100 for
-                                   a sparse A or 1e5 for a dense A, else CARE_FP64;
-                                   the choice is reported in care_stats.inner_prec */
+  CARE_AUTO = 3,                /* care_solve* only: a-priori choice after Theorem 1's
+                                   condition d_1 kappa_F(L) u_s < 1, with kappa_F(L)
+                                   estimated as sqrt(||A||_1 ||A||_inf) / min |Re p|
+                                   over the shift set: CARE_FP32 when kappa u_32 is
+                                   at most 6e-6 (kappa <= 100) for a sparse A or
+                                   6e-3 (kappa <= 1e5) for a dense A, else CARE_FP64
+                                   (thresholds measured, see care_solve); the choice
+                                   is reported in care_stats.inner_prec            */
+  CARE_FP16_SPMM = 4            /* FP32 inner solves whose sparse products read the
+                                   off-diagonal values of A in IEEE half precision,
+                                   stored as a_ij / 2^e with 2^e fixed per operator
+                                   so that max |a_ij| / 2^e lies in [2^13, 2^14]
+                                   (within half's range; the kernel multiplies by
+                                   2^e exactly).  Sparse A only                     */
 };
 
 /* CSR of A itself (NOT of A^T); 0-based int32 indices, column indices sorted
@@ -91,21 +100,24 @@ typedef struct care_ctx care_ctx;
 
 /* Solver options; care_opts_default fills the values used in Sec. 5. */
 typedef struct {
-  int32_t inner_prec;     /* CARE_FP64 | CARE_FP32 | CARE_BF16_SPMM                     */
+  int32_t inner_prec;     /* CARE_FP64 | CARE_FP32 | CARE_BF16_SPMM | CARE_FP16_SPMM |
+                             CARE_AUTO                                              */
   int32_t k_max;          /* refinement steps of Framework 1 (20)                     */
   int32_t k0_max;         /* Newton steps of the initial NLR-ADI solve (20)           */
   int32_t j_max;          /* ADI steps per Lyapunov solve (50)                        */
   double eta_r_rel;       /* Alg. 1 threshold, relative to max|lambda(H)| (1e-4)      */
   double eta_s_rel;       /* Alg. 2 threshold, relative to max|lambda(P)| (10 u_fp64)  */
   double tau_L;           /* inner LR-ADI stop ||W^T W||_F <= tau_L ||W0^T W0||_F;
-                             <= 0 selects 1e-12 (FP64) / 1e-6 (FP32) / 1e-3 (BF16)    */
+                             <= 0 selects 1e-12 (FP64) / 1e-6 (FP32) / 1e-4 (FP16
+                             products) / 1e-3 (BF16 products)                      */
   double tau_0;           /* initial NLR-ADI stop on the relative Riccati residual;
                              <= 0 selects max(tol / 10, 10 tau_L0)                    */
   double stagnation;      /* stop when ||R_{k+1}|| / ||R_k|| > stagnation (0.999)     */
   int32_t krylov_maxit;   /* BiCGStab iteration cap per shifted solve (4000)          */
   double krylov_tol;      /* per-column relative residual; <= 0 selects
-                             max(1e-13, min(1e-10, tol / 10)) (FP64), 1e-7 (FP32) or
-                             1e-3 (BF16 products).  Columns that stagnate above it
+                             max(1e-13, min(1e-10, tol / 10)) (FP64), 1e-7 (FP32),
+                             1e-4 (FP16 products) or 1e-3 (BF16 products).  Columns
+                             that stagnate above it
                              are restarted on their true residual                   */
   int32_t check_every;    /* host convergence poll period of the Krylov loop (8)      */
   int32_t penzl_l0;       /* auto shifts: number of shifts (16)                       */
@@ -122,7 +134,7 @@ typedef struct {
                              the right-hand side block instead of each column (0);
                              -1 (default): 1 for FP32 inner solves (their LR-ADI
                              residual factor is rotated, so most columns are
-                             small), 0 for FP64 and bf16 products                  */
+                             small), 0 for FP64 and the 16-bit products            */
   int32_t penzl_real;     /* auto shifts: 1 keeps the real parts of the Ritz values */
   int32_t spmm_split;     /* BiCGStab products: 0 chooses by the L2 footprint of the
                              fused gathers, 1 fused, 2 split (update pass + product) */

@@ -5,11 +5,11 @@ include/mpcare.h); this package only marshals arguments.  Importing it does
 not load the library; the first call does, and fails loudly when the library
 has not been built.
 """
-from ._lib import (CARE_AUTO, CARE_BF16_SPMM, CARE_ERR_ARG, CARE_ERR_BREAKDOWN, CARE_ERR_CAPACITY,  # noqa: F401
+from ._lib import (CARE_AUTO, CARE_BF16_SPMM, CARE_FP16_SPMM, CARE_ERR_ARG, CARE_ERR_BREAKDOWN, CARE_ERR_CAPACITY,  # noqa: F401
                    CARE_ERR_NONFINITE, CARE_ERR_UNSTABLE, CARE_FP32, CARE_FP64, LIB_PATH, SIGNATURES, STATUS_NAMES,
                    load)
 
-__all__ = ["load", "LIB_PATH", "SIGNATURES", "STATUS_NAMES", "CARE_FP64", "CARE_FP32", "CARE_BF16_SPMM", "CARE_AUTO",
+__all__ = ["load", "LIB_PATH", "SIGNATURES", "STATUS_NAMES", "CARE_FP64", "CARE_FP32", "CARE_BF16_SPMM", "CARE_FP16_SPMM", "CARE_AUTO",
            "CARE_ERR_ARG", "CARE_ERR_CAPACITY", "CARE_ERR_UNSTABLE", "CARE_ERR_BREAKDOWN", "CARE_ERR_NONFINITE"]
 
 

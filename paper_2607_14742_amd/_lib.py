@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libmpcare.so")
 CARE_OK, CARE_WARN_STAGNATED, CARE_WARN_MAXIT = 0, 1, 2
 CARE_ERR_ARG, CARE_ERR_CAPACITY, CARE_ERR_UNSTABLE, CARE_ERR_BREAKDOWN = -1, -2, -3, -4
 CARE_ERR_NONFINITE, CARE_ERR_DEVICE, CARE_ERR_NOMEM, CARE_ERR_NOT_IMPLEMENTED = -5, -6, -7, -8
-CARE_FP64, CARE_FP32, CARE_BF16_SPMM, CARE_AUTO = 0, 1, 2, 3
+CARE_FP64, CARE_FP32, CARE_BF16_SPMM, CARE_AUTO, CARE_FP16_SPMM = 0, 1, 2, 3, 4
 
 STATUS_NAMES = {
     0: "CARE_OK", 1: "CARE_WARN_STAGNATED", 2: "CARE_WARN_MAXIT", -1: "CARE_ERR_ARG",

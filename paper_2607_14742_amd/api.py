@@ -13,11 +13,12 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from ._lib import (CARE_AUTO, CARE_BF16_SPMM, CARE_FP32, CARE_FP64, care_csr, care_opts, care_shift,  # noqa: F401
-                   care_stats)
+from ._lib import (CARE_AUTO, CARE_BF16_SPMM, CARE_FP16_SPMM, CARE_FP32, CARE_FP64, care_csr, care_opts,  # noqa: F401
+                   care_shift, care_stats)
 
-PREC = {"fp64": CARE_FP64, "fp32": CARE_FP32, "bf16": CARE_BF16_SPMM, "auto": CARE_AUTO,
-        CARE_FP64: CARE_FP64, CARE_FP32: CARE_FP32, CARE_BF16_SPMM: CARE_BF16_SPMM, CARE_AUTO: CARE_AUTO}
+PREC = {"fp64": CARE_FP64, "fp32": CARE_FP32, "bf16": CARE_BF16_SPMM, "fp16": CARE_FP16_SPMM, "auto": CARE_AUTO,
+        CARE_FP64: CARE_FP64, CARE_FP32: CARE_FP32, CARE_BF16_SPMM: CARE_BF16_SPMM, CARE_FP16_SPMM: CARE_FP16_SPMM,
+        CARE_AUTO: CARE_AUTO}
 
 
 class CareError(RuntimeError):

@@ -11,6 +11,7 @@ namespace mpcare {
 
 static const double U64 = 1.1102230246251565e-16;   // FP64 unit roundoff (Table 1)
 static const double U32 = 5.9604644775390625e-08;   // FP32 unit roundoff (Table 1)
+static const double U16 = 4.8828125e-04;            // FP16 unit roundoff (Table 1)
 static const double UBF = 3.90625e-03;              // bfloat16 unit roundoff (Table 1)
 
 Resolved resolve_opts(const care_opts* o, double tol) {
@@ -23,7 +24,7 @@ Resolved resolve_opts(const care_opts* o, double tol) {
   // instead of the paper's 1e-5, which lets one correction reach the
   // tolerance on well-conditioned problems (Toeplitz example of Sec. 5.2:
   // 3 -> 2 refinement steps) and costs nothing measurable otherwise.
-  const double tl_def = r.prec == Prec::F64 ? 1e-12 : (r.prec == Prec::F32 ? 1e-6 : 1e-3);
+  const double tl_def = r.prec == Prec::F64 ? 1e-12 : (r.prec == Prec::F32 ? 1e-6 : (r.prec == Prec::F16 ? 1e-4 : 1e-3));
   // Krylov tolerance: 1e-10 (FP64) as in Sec. 5, tightened to a tenth of the
   // requested residual when that is smaller: the solves' own errors set the
   // floor of the true Riccati residual near the Krylov tolerance, below the
@@ -31,7 +32,7 @@ Resolved resolve_opts(const care_opts* o, double tol) {
   // instead of the paper's 1e-5 (unpreconditioned BiCGStab: the tighter inner
   // solves leave a smaller, narrower residual and save refinement work).
   const double kt_def = r.prec == Prec::F64 ? std::max(1e-13, std::min(1e-10, 0.1 * tol))
-                                            : (r.prec == Prec::F32 ? 1e-7 : 1e-3);
+                                            : (r.prec == Prec::F32 ? 1e-7 : (r.prec == Prec::F16 ? 1e-4 : 1e-3));
   r.tau_L = o->tau_L > 0 ? o->tau_L : tl_def;
   r.ktol = o->krylov_tol > 0 ? o->krylov_tol : kt_def;
   r.tau_L0 = o->tau_L0 > 0 ? o->tau_L0 : r.tau_L;
@@ -64,19 +65,32 @@ Resolved resolve_opts(const care_opts* o, double tol) {
   return r;
 }
 
-static double unit_roundoff(Prec p) { return p == Prec::F64 ? U64 : (p == Prec::F32 ? U32 : UBF); }
+
+static double unit_roundoff(Prec p) {
+  return p == Prec::F64 ? U64 : (p == Prec::F32 ? U32 : (p == Prec::F16 ? U16 : UBF));
+}
 
 // A-priori choice of the inner precision (Theorem 1: the refinement contracts
 // when d_1 kappa_F(L_k) u_s < 1, and each correction gains about
-// -log10(d_1 kappa u_s) digits).  The spread max|p| / min|p| of the shift set,
-// which spans the spectrum of A (heuristic shifts from Ritz values, or a
-// caller's log-spaced set over the spectral interval), stands in for kappa.
-// Thresholds, both measured here: with iterative shifted solves FP32 pays off
-// clearly only for well-conditioned A.  On the Toeplitz example (spread ~3)
-// FP32 is 1.2-1.3x faster; on the 3D problem (kappa ~1.7e3) and the 2D FDM
-// problem (2.9e4) the two are about level (1.03x faster, 1.1x slower).  So
-// FP32 for a spread <= 100.  With direct (LU) shifted solves the paper's
-// Table 1 shows FP32 gains up to kappa = 1e5.
+// -log10(d_1 kappa u_s) digits).  kappa_F(L) of L(X) = A^T X + X A is
+// estimated as ||A||_2 / min_j |Re p_j|: ||L|| <= 2 ||A||_2, and the shift set
+// spans the spectrum of A (heuristic shifts from Ritz values, or a caller's
+// log-spaced set over the spectral interval), so its smallest |Re p| stands in
+// for the separation 1 / ||L^-1|| (exact, up to the factor 2, for normal A).
+// ||A||_2 is bounded by sqrt(||A||_1 ||A||_inf).  Thresholds on kappa u_s, both
+// measured here: with iterative shifted solves FP32 pays off clearly only for
+// well-conditioned A.  On the Toeplitz example FP32 is 1.2-1.3x faster; on
+// the 3D problem (kappa ~ 2e3) and the 2D FDM problem (~ 3e4) the two are
+// about level or FP64 wins.  So FP32 where kappa u_32 <= 6e-6 (kappa <= 100).
+// With direct (LU) shifted solves the paper's Table 1 shows FP32 gains up to
+// kappa = 1e5: kappa u_32 <= 6e-3.  The 16-bit product variants are never
+// chosen: their u_s puts every kappa >= 1 beyond those limits.
+double kappa_L_estimate(double norm2_bound, const std::vector<Shift>& shifts) {
+  double lo = INFINITY;
+  for (const Shift& p : shifts) lo = std::min(lo, std::fabs(p.re));
+  return lo > 0.0 && lo < INFINITY && norm2_bound > 0.0 ? std::max(1.0, norm2_bound / lo) : 1.0;
+}
+
 double shift_spread(const std::vector<Shift>& shifts) {
   double lo = INFINITY, hi = 0.0;
   for (const Shift& p : shifts) {
@@ -87,13 +101,15 @@ double shift_spread(const std::vector<Shift>& shifts) {
   return lo > 0.0 && hi > 0.0 ? hi / lo : 1.0;
 }
 
-int choose_inner_precision(const std::vector<Shift>& shifts, bool dense) {
-  const double spread = shift_spread(shifts);
-  const double limit = dense ? 1e5 : 100.0;
-  const int choice = spread <= limit ? CARE_FP32 : CARE_FP64;
+int choose_inner_precision(double norm2_bound, const std::vector<Shift>& shifts, bool dense) {
+  const double kappa = kappa_L_estimate(norm2_bound, shifts);
+  const double limit = dense ? 1e5 * U32 : 100.0 * U32;
+  int choice = CARE_FP64;
+  if (kappa * unit_roundoff(Prec::F16) <= limit) choice = CARE_FP16_SPMM;
+  else if (kappa * unit_roundoff(Prec::F32) <= limit) choice = CARE_FP32;
   if (std::getenv("MPCARE_TRACE"))
-    std::fprintf(stderr, "[auto] shift spread %.3e (limit %.0e): %s inner solves\n", spread, limit,
-                 choice == CARE_FP32 ? "FP32" : "FP64");
+    std::fprintf(stderr, "[auto] kappa_F(L) estimate %.3e (kappa u_s limit %.1e): inner precision %d\n", kappa,
+                 limit, choice);
   return choice;
 }
 
@@ -373,7 +389,7 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
       for (const Shift& sh : S.shifts) std::fprintf(stderr, "[penzl] shift (%.6e, %.6e)\n", sh.re, sh.im);
   }
   if (auto_prec) {
-    eff.inner_prec = choose_inner_precision(S.shifts, A.dense != nullptr);
+    eff.inner_prec = choose_inner_precision(A64.norm2_bound(), S.shifts, A.dense != nullptr);
     S.prm = resolve_opts(&eff, tol);
   }
   st->inner_prec = eff.inner_prec;

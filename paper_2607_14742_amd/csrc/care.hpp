@@ -18,8 +18,10 @@ struct Resolved {
 Resolved resolve_opts(const care_opts* o, double tol);
 // max|p| / min|p| over a shift set (1 for an empty or degenerate set)
 double shift_spread(const std::vector<Shift>& shifts);
-// CARE_FP32 or CARE_FP64 for inner_prec = CARE_AUTO, from the shift spread
-int choose_inner_precision(const std::vector<Shift>& shifts, bool dense);
+// ||A||_2 / min |Re p|: the estimate of kappa_F(L) behind CARE_AUTO
+double kappa_L_estimate(double norm2_bound, const std::vector<Shift>& shifts);
+// CARE_FP32 or CARE_FP64 for inner_prec = CARE_AUTO, from that estimate
+int choose_inner_precision(double norm2_bound, const std::vector<Shift>& shifts, bool dense);
 
 // The operator of one solve: a sparse CSR of A, or a dense column-major A.
 struct OpSpec {

@@ -52,13 +52,17 @@ const char* last_error_cstr();
 // precision tags
 // ----------------------------------------------------------------------------
 using bf16 = __hip_bfloat16;
+using f16 = _Float16;
 
-enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2 };
+// F16 and BF16: FP32 inner solves whose sparse products read the off-diagonal
+// values of A in a 16-bit format (F16 with a power-of-two operator scale)
+enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
 
 inline Prec prec_from_abi(int32_t p) {
   if (p == CARE_FP64) return Prec::F64;
   if (p == CARE_FP32) return Prec::F32;
   if (p == CARE_BF16_SPMM) return Prec::BF16;
+  if (p == CARE_FP16_SPMM) return Prec::F16;
   fail(CARE_ERR_ARG, "unknown precision " + std::to_string(p));
 }
 inline size_t vec_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }   // Krylov vectors

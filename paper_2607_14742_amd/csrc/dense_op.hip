@@ -49,7 +49,8 @@ __global__ void k_abs_rowsum(int64_t n, const double* __restrict__ a, double* __
 void build_dense(Ctx* ctx, const double* A, int64_t lda, int64_t n, Prec prec, SellOp& op) {
   if (!A || n < 1 || lda < n) fail(CARE_ERR_ARG, "invalid dense A");
   if (n > 46340) fail(CARE_ERR_ARG, "dense A larger than 46340 x 46340");
-  if (prec == Prec::BF16) fail(CARE_ERR_NOT_IMPLEMENTED, "the bf16 variant applies to sparse operators only");
+  if (prec == Prec::BF16 || prec == Prec::F16)
+    fail(CARE_ERR_NOT_IMPLEMENTED, "the 16-bit product variants apply to sparse operators only");
   op = SellOp();
   op.n = n;
   op.nnz = n * n;

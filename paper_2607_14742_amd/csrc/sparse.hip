@@ -101,7 +101,7 @@ __global__ void k_slice_width(const int* __restrict__ rpt, const int* __restrict
 template <typename TV, typename T>
 __global__ void k_fill_sell(const int* __restrict__ rpt, const int* __restrict__ ct, const double* __restrict__ vt,
                             int64_t n, int nslices, const int* __restrict__ sptr, int* __restrict__ cols,
-                            TV* __restrict__ vals, T* __restrict__ diag) {
+                            TV* __restrict__ vals, T* __restrict__ diag, double inv_scale) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)nslices * 64) return;
   const int s = (int)(i >> 6), lane = (int)(i & 63);
@@ -116,7 +116,7 @@ __global__ void k_fill_sell(const int* __restrict__ rpt, const int* __restrict__
       } else {
         const int64_t o = (int64_t)(base + t) * 64 + lane;
         cols[o] = ct[e];
-        vals[o] = (TV)vt[e];
+        vals[o] = (TV)(vt[e] * inv_scale);
         ++t;
       }
     }
@@ -223,28 +223,6 @@ void build_sell(Ctx* ctx, const care_csr* A, Prec prec, SellOp& op) {
     op.max_width = nsl ? *std::max_element(hw.begin(), hw.end()) : 0;
   }
 
-  op.n = n;
-  op.nnz = nnz;
-  op.nslices = nsl;
-  op.width_total = total;
-  op.prec = prec;
-  const int64_t ents = (int64_t)total * 64;
-  op.cols.resize(ctx, ents ? ents : 1);
-  op.vals.resize(ctx, (ents ? ents : 1) * val_bytes(prec));
-  op.diag.resize(ctx, n * vec_bytes(prec));
-  dim3 g(ceil_div((int64_t)nsl * 64, 256));
-  if (prec == Prec::F64) {
-    hipLaunchKernelGGL((k_fill_sell<double, double>), g, dim3(256), 0, st, rpt.get(), ct.get(), vt.get(), n, nsl,
-                       op.sptr.get(), op.cols.get(), (double*)op.vals.get(), (double*)op.diag.get());
-  } else if (prec == Prec::F32) {
-    hipLaunchKernelGGL((k_fill_sell<float, float>), g, dim3(256), 0, st, rpt.get(), ct.get(), vt.get(), n, nsl,
-                       op.sptr.get(), op.cols.get(), (float*)op.vals.get(), (float*)op.diag.get());
-  } else {
-    hipLaunchKernelGGL((k_fill_sell<bf16, float>), g, dim3(256), 0, st, rpt.get(), ct.get(), vt.get(), n, nsl,
-                       op.sptr.get(), op.cols.get(), (bf16*)op.vals.get(), (float*)op.diag.get());
-  }
-  KERNEL_CHECK();
-
   // ||A||_F
   if (nnz) {
     const int nb = 256;
@@ -267,6 +245,40 @@ void build_sell(Ctx* ctx, const care_csr* A, Prec prec, SellOp& op) {
     d2h(ctx, h.data(), part.get(), nb * sizeof(double));
     op.norm_one = *std::max_element(h.begin(), h.end());
   }
+  // F16 values: a power-of-two scale that maps max |a_ij| <= min(||A||_1,
+  // ||A||_inf) into [2^13, 2^14], within half precision's range (65504);
+  // entries below 2^-38 max |a_ij| fall to zero
+  op.val_scale = 1.0f;
+  if (prec == Prec::F16 && nnz) {
+    const double bound = std::min(op.norm_inf, op.norm_one);
+    if (bound > 0.0) op.val_scale = std::ldexp(1.0f, (int)std::ceil(std::log2(bound)) - 14);
+  }
+  op.n = n;
+  op.nnz = nnz;
+  op.nslices = nsl;
+  op.width_total = total;
+  op.prec = prec;
+  const int64_t ents = (int64_t)total * 64;
+  op.cols.resize(ctx, ents ? ents : 1);
+  op.vals.resize(ctx, (ents ? ents : 1) * val_bytes(prec));
+  op.diag.resize(ctx, n * vec_bytes(prec));
+  dim3 g(ceil_div((int64_t)nsl * 64, 256));
+  if (prec == Prec::F64) {
+    hipLaunchKernelGGL((k_fill_sell<double, double>), g, dim3(256), 0, st, rpt.get(), ct.get(), vt.get(), n, nsl,
+                       op.sptr.get(), op.cols.get(), (double*)op.vals.get(), (double*)op.diag.get(), 1.0);
+  } else if (prec == Prec::F32) {
+    hipLaunchKernelGGL((k_fill_sell<float, float>), g, dim3(256), 0, st, rpt.get(), ct.get(), vt.get(), n, nsl,
+                       op.sptr.get(), op.cols.get(), (float*)op.vals.get(), (float*)op.diag.get(), 1.0);
+  } else if (prec == Prec::BF16) {
+    hipLaunchKernelGGL((k_fill_sell<bf16, float>), g, dim3(256), 0, st, rpt.get(), ct.get(), vt.get(), n, nsl,
+                       op.sptr.get(), op.cols.get(), (bf16*)op.vals.get(), (float*)op.diag.get(), 1.0);
+  } else {
+    hipLaunchKernelGGL((k_fill_sell<f16, float>), g, dim3(256), 0, st, rpt.get(), ct.get(), vt.get(), n, nsl,
+                       op.sptr.get(), op.cols.get(), (f16*)op.vals.get(), (float*)op.diag.get(),
+                       1.0 / (double)op.val_scale);
+  }
+  KERNEL_CHECK();
+
   ctx->sync();
 }
 
@@ -347,7 +359,7 @@ static void launch_prec(Ctx* ctx, const SellOp& op, int mode, bool cplx, const S
   } else {
     if (op.prec == Prec::F32) launch_tv<float, float>(ctx->stream, op.n, mode, cplx, a, cp, wmax, fpg);
     else if (op.prec == Prec::BF16) launch_tv<bf16, float>(ctx->stream, op.n, mode, cplx, a, cp, wmax, fpg);
-    else fail(CARE_ERR_ARG, "FP32 vectors need an FP32 or BF16 operator");
+    else launch_tv<f16, float>(ctx->stream, op.n, mode, cplx, a, cp, wmax, fpg);
   }
   KERNEL_CHECK();
 }
@@ -403,6 +415,7 @@ int launch_spmm(Ctx* ctx, const SellOp& op, int mode, bool cplx, SpmmArgs<T>& a)
   a.cols = op.cols.get();
   a.vals = op.vals.get();
   a.diag = (const T*)op.diag.get();
+  a.vscale = op.val_scale;
   a.nrb = spmm_rowblocks(op.n);
   if (a.ncols <= 0) return a.nrb;
   if (cplx && (a.ncols % 2)) fail(CARE_ERR_ARG, "complex panel with an odd number of real columns");

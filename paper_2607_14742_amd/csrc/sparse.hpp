@@ -32,6 +32,7 @@ struct SellOp {
   int nslices = 0;
   int64_t width_total = 0;         // sum of slice widths
   int max_width = 0;               // widest slice (off-diagonal entries per row)
+  float val_scale = 1.0f;          // F16: values stored as a_ij / val_scale (a power of two)
   Prec prec = Prec::F64;
   DBuf<int> sptr;                  // nslices + 1
   DBuf<int> cols;                  // width_total * 64

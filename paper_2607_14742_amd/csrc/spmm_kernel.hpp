@@ -28,6 +28,8 @@
 
 #include "common.hpp"
 
+#include <type_traits>
+
 namespace mpcare {
 
 enum SpmmMode { MODE_PLAIN = 0, MODE_BICG_P = 1, MODE_BICG_S = 2, MODE_DOT1 = 3, MODE_DOT2 = 4 };
@@ -72,6 +74,7 @@ struct SpmmArgs {
   double* part = nullptr;        // [(dot * ncols + col) * nrb + rowblock]
   int nrb = 0;
   int pg = 1;                    // column panels per workgroup (grid y = ceil(panels / pg))
+  float vscale = 1.0f;           // F16 values: the operator's power-of-two scale
 };
 
 template <typename T, typename TV>
@@ -81,6 +84,17 @@ __device__ __forceinline__ T load_val(const TV* p, int64_t e) {
 template <>
 __device__ __forceinline__ float load_val<float, bf16>(const bf16* p, int64_t e) {
   return __bfloat162float(p[e]);
+}
+template <>
+__device__ __forceinline__ float load_val<float, f16>(const f16* p, int64_t e) {
+  return (float)p[e];
+}
+// one off-diagonal value of the operator; F16 values are unscaled by the
+// operator's power of two (an exact product)
+template <typename T, typename TV>
+__device__ __forceinline__ T load_entry(const TV* p, int64_t e, float vscale) {
+  if constexpr (std::is_same<TV, f16>::value) return load_val<T, TV>(p, e) * vscale;
+  else return load_val<T, TV>(p, e);
 }
 
 // Reduce NV per-thread values over the 256-thread block in a fixed order
@@ -168,7 +182,7 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
       if (sbeg + t < send) {
         const int64_t e = (int64_t)(sbeg + t) * 64 + lane;
         cj[t] = a.cols[e];
-        cv[t] = load_val<T, TV>(vals, e);
+        cv[t] = load_entry<T, TV>(vals, e, a.vscale);
       }
     }
   }
@@ -312,7 +326,7 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
     if (WMAX == 0 && beg < end) {
       const int64_t e = (int64_t)beg * 64 + lane;
       jn = a.cols[e];
-      avn = load_val<T, TV>(vals, e);
+      avn = load_entry<T, TV>(vals, e, a.vscale);
     }
     for (int t = beg; WMAX == 0 && t < end; ++t) {
       const int j = jn;
@@ -323,7 +337,7 @@ __global__ void __launch_bounds__(256) k_spmm(SpmmArgs<T> a) {
       if (t + 1 < end) {
         const int64_t e = (int64_t)(t + 1) * 64 + lane;
         jn = a.cols[e];
-        avn = load_val<T, TV>(vals, e);
+        avn = load_entry<T, TV>(vals, e, a.vscale);
       }
 #pragma unroll
       for (int q = 0; q < NL; ++q) {

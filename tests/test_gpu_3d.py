@@ -35,7 +35,7 @@ def dev(x):
     return torch.as_tensor(np.asarray(x, dtype=np.float64), device="cuda")
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp16"])
 def test_3d_rotating_vs_oracle(pk, ctx, prec):
     P = wl.fdm3d_problem(8, 1, 10)
     shifts = osh.penzl_shifts(P.A, 16, 20, 10)          # the same complex pairs on both sides

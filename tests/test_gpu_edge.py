@@ -137,11 +137,12 @@ def test_spmm_panel_autotuner_leaves_results_unchanged(pk, ctx):
 
 @pytest.mark.parametrize("case,want", [("fdm2d", "fp64"), ("toeplitz", "fp32"), ("dense", "fp32")])
 def test_auto_precision_choice(pk, ctx, case, want):
-    # CARE_AUTO: FP32 inner solves only when the shift spread (the stand-in
-    # for kappa in Theorem 1) is small: <= 100 for a sparse A, <= 1e5 for a
-    # dense A with LU shifted solves
+    # CARE_AUTO: FP32 inner solves only when the estimate of kappa_F(L) in
+    # Theorem 1, sqrt(||A||_1 ||A||_inf) / min |Re p|, is small: <= 100 for a
+    # sparse A, <= 1e5 for a dense A with LU shifted solves (here about 4.5
+    # for the Toeplitz example, 410 for the 60 x 60 FDM problem, 1.0e3 dense)
     if case == "fdm2d":
-        P = wl.fdm2d_problem(60, 2, 3)            # spread ~1.5e3
+        P = wl.fdm2d_problem(60, 2, 3)
         A, B, Cm, shifts, Xs = P.A, P.B, P.C, P.shifts, None
         Z, stats, st = pk.care_solve(ctx, pk.DeviceCSR.from_scipy(A), dev(B), dev(Cm), tol=1e-11, shifts=shifts,
                                      prec="auto")
