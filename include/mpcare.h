@@ -159,7 +159,11 @@ typedef struct {
   int32_t shift_update;   /* heuristic shifts only (nshifts = 0): 1 recomputes them
                              for every Lyapunov solve from its closed-loop operator
                              A - B K^T (Newton steps >= 1, corrections), the
-                             inverse Arnoldi through SMW; 0 (default): one set
+                             inverse Arnoldi through SMW; 2 projection shifts
+                             (care_projection_shifts): every LR-ADI run takes its
+                             first set from span(W0) and, whenever a set is used
+                             up, the next from the span of its latest blocks of Z,
+                             at most penzl_l0 per set; 0 (default): one Penzl set
                              from A for the whole solve                            */
   int32_t krylov_method;  /* shifted solves: 0 (default) column-batched BiCGStab;
                              1 restarted GMRES for real shifts (complex pairs stay
@@ -338,7 +342,8 @@ care_status care_tsgemm(care_ctx* ctx, int64_t n, const double* X, int64_t ldx, 
 /* LR-ADI for the Lyapunov equation  A_k^T X + X A_k + W W^T = 0,
  * A_k = A - B K^T (B, K: n x m; B = K = NULL or m = 0 means A_k = A), the
  * inner solver of Sec. 4 (residual-based LR-ADI; real shifts and
- * complex-conjugate pairs).  W: n x w.  Runs in opts->inner_prec until
+ * complex-conjugate pairs).  nshifts = 0 with opts->shift_update = 2 runs
+ * on projection shifts (see care_opts).  W: n x w.  Runs in opts->inner_prec until
  * ||W_j^T W_j||_F <= tol ||W^T W||_F (tol <= 0 selects opts' tau_L) or
  * opts->j_max steps.  Output Z: n x (*r_out) FP64, ldz >= n, capacity rmax
  * columns; block j of w columns keeps the column order of W (a complex pair
@@ -431,8 +436,8 @@ care_status care_solve_dense(care_ctx* ctx, const double* A, int64_t n, int64_t 
                              const care_opts* opts, double* Z, int64_t ldz, int32_t rmax, int32_t* r_out,
                              care_stats* stats);
 
-/* Penzl-type heuristic shifts (the "shifts from Krylov subspaces" of Sec. 5,
- * read as Penzl's procedure): Ritz values of kp Arnoldi steps with A^T and
+/* Penzl-type heuristic shifts (Sec. 5 takes its shifts from Krylov
+ * subspaces; one reading is Penzl's procedure): Ritz values of kp Arnoldi steps with A^T and
  * of km steps with A^-T (inverted), FP64 on the GPU from ones / sqrt(n);
  * those in the open left half-plane are the candidates of the greedy min-max
  * choice of care_penzl_select.  real_only = 1 replaces each Ritz value by its
@@ -442,6 +447,22 @@ care_status care_solve_dense(care_ctx* ctx, const double* A, int64_t n, int64_t 
  * CARE_ERR_BREAKDOWN if a solve with A^T fails. */
 care_status care_penzl_shifts(care_ctx* ctx, const care_csr* A, int32_t l0, int32_t kp, int32_t km,
                               int32_t real_only, care_shift* shifts_out, int32_t* count);
+
+/* Projection shifts (Benner, Kuerschner and Saak, ETNA 43, 2014; the other
+ * reading of the Krylov-subspace shifts of Sec. 5): the Ritz values of
+ * F = A^T - K B^T (K = NULL or m = 0: A^T) on span(V), V: n x s FP64
+ * (ldv >= n), restricted to the dominant directions of V (eigenvalues of
+ * V^T V above 1e-10 of the largest, at most 64), computed in precision
+ * `prec` (CARE_FP64, or an FP32 variant: V, B, K rounded to FP32 and the
+ * product in that variant); Ritz values in the right half-plane are
+ * mirrored into the left one, and at most l0 shifts are chosen among them
+ * by the greedy min-max rule of care_penzl_select.  B, K: n x m FP64 device
+ * (ld n).  shifts_out: HOST array with room for l0 + 1 entries; *count
+ * receives the number written.  Fails with CARE_ERR_UNSTABLE when no Ritz
+ * value has a nonzero real part. */
+care_status care_projection_shifts(care_ctx* ctx, const care_csr* A, const double* B, const double* K,
+                                   int32_t m, const double* V, int64_t ldv, int32_t s, int32_t l0, int32_t prec,
+                                   care_shift* shifts_out, int32_t* count);
 
 /* Host step of the shift heuristic: the eigenvalues (re[i], im[i]) of the
  * k x k upper Hessenberg matrix H (HOST, column-major, ldh >= k; entries

@@ -18,6 +18,10 @@ reading used here is Penzl's heuristic (Penzl, SIAM J. Sci. Comput. 21(4),
 The candidates are taken in lexicographic (Re, Im) order, so that ties (a
 Ritz value and its conjugate score alike) resolve the same way everywhere.
 A complex pair is stored with Im > 0 first.
+
+The other reading, projection shifts (Benner, Kuerschner and Saak, ETNA 43,
+2014), draws each set from a subspace the ADI run itself produces:
+projection_shifts below.
 """
 from __future__ import annotations
 
@@ -105,3 +109,30 @@ def penzl_select(R, l0):
 def penzl_shifts(A, l0=16, kp=20, km=10, real_only=False, inv_apply=None):
     """Penzl's heuristic shift set for the ADI operator A^T."""
     return penzl_select(ritz_candidates(A, kp, km, real_only, inv_apply), l0)
+
+
+def projection_shifts(A, V, l0, B=None, K=None, smax=64, rel=1e-10):
+    """Projection shifts: the Ritz values of F = A^T - K B^T on span(V).
+
+    1. Q: orthonormal basis of the dominant directions of span(V), the left
+       singular vectors of V with sigma^2 > rel * sigma_max^2 (at most smax);
+    2. H = Q^T F Q;
+    3. its eigenvalues, those in the right half-plane mirrored into the left
+       one (t -> -conj(t));
+    4. at most l0 of them by the greedy min-max rule (penzl_select).
+    B, K: n x m or None."""
+    At = A.T
+    V = np.asarray(V, dtype=np.float64)
+    U, s, _ = np.linalg.svd(V, full_matrices=False)
+    keep = s ** 2 > rel * s[0] ** 2
+    Q = U[:, keep][:, :smax]
+    Y = At @ Q
+    if sp.issparse(Y):
+        Y = Y.toarray()
+    Y = np.asarray(Y)
+    if B is not None and K is not None:
+        Y = Y - K @ (B.T @ Q)
+    H = Q.T @ Y
+    theta = np.linalg.eigvals(H).astype(np.complex128)
+    theta = np.where(theta.real > 0, -np.conj(theta), theta)
+    return penzl_select(theta, l0)

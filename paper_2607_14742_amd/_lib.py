@@ -107,6 +107,8 @@ SIGNATURES = {
                                C.POINTER(care_opts), P, I64, I32, PI32, C.POINTER(care_stats)]),
     "care_solve_batch": (I32, [P, I32, C.POINTER(care_instance), DBL, C.POINTER(care_opts), I32,
                                C.POINTER(care_instance_result)]),
+    "care_projection_shifts": (I32, [P, C.POINTER(care_csr), P, P, I32, P, I64, I32, I32, I32,
+                                     C.POINTER(care_shift), PI32]),
     "care_ritz_values": (I32, [PDBL, I32, I64, PDBL, PDBL]),
     "care_penzl_select": (I32, [PDBL, PDBL, I32, I32, C.POINTER(care_shift), PI32]),
 }

@@ -388,6 +388,21 @@ def penzl_shifts(ctx, A, l0=16, kp=20, km=10, real_only=False):
     return np.array([complex(out[i].re, out[i].im) for i in range(cnt.value)])
 
 
+def projection_shifts(ctx, A, V, l0=16, B=None, K=None, prec="fp64"):
+    """Projection shifts: Ritz values of A^T - K B^T on span(V) (n x s device
+    tensor), mirrored into the left half-plane, at most l0 chosen."""
+    V = colmajor(V.to(torch.float64))
+    smw = B is not None and K is not None and B.shape[1] > 0
+    Bt = tight(B) if smw else None
+    Kt = tight(K) if smw else None
+    m = Bt.shape[1] if smw else 0
+    out = (care_shift * (l0 + 1))()
+    cnt = C.c_int32(0)
+    _check(_lib().care_projection_shifts(ctx.h, A.c, _ptr(Bt) if smw else None, _ptr(Kt) if smw else None, m,
+                                         _ptr(V), _ld(V), V.shape[1], l0, PREC[prec], out, C.byref(cnt)))
+    return np.array([complex(out[i].re, out[i].im) for i in range(cnt.value)])
+
+
 def ritz_values(H):
     """Eigenvalues of a small upper Hessenberg matrix (host, no device work)."""
     H = np.asfortranarray(np.asarray(H, dtype=np.float64))

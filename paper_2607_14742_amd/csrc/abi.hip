@@ -343,12 +343,17 @@ care_status lyap_lradi(care_ctx* cx, const care_csr* A, const double* B, const d
     if (!Z || ldz < n || rmax < 0) fail(CARE_ERR_ARG, "invalid Z");
     const bool smw = K != nullptr && m > 0;
     if (smw && !B) fail(CARE_ERR_ARG, "B is NULL while K is given");
-    std::vector<Shift> sh = check_shifts(shifts, nshifts);
     care_opts d;
     care_opts_default(&d, CARE_FP64);
     const care_opts* o = opts ? opts : &d;
+    // nshifts = 0 with shift_update = 2: projection shifts (at most
+    // penzl_l0 per set) drawn from W and the run's own iterates
+    const bool proj = nshifts == 0 && o->shift_update == 2;
+    if (proj && o->penzl_l0 < 1) fail(CARE_ERR_ARG, "projection shifts need penzl_l0 >= 1");
+    std::vector<Shift> sh = proj ? std::vector<Shift>() : check_shifts(shifts, nshifts);
     Resolved r = resolve_opts(o, 1e-10);
     LradiParams lp;
+    lp.proj_shifts = proj ? o->penzl_l0 : 0;
     lp.tol = tol > 0 ? tol : r.tau_L;
     lp.jmax = r.j_max;
     lp.ktol = r.ktol;
@@ -515,6 +520,39 @@ care_status care_penzl_shifts(care_ctx* cx, const care_csr* A, int32_t l0, int32
     std::vector<Shift> s = penzl_shifts(ctx, op, l0, kp, km, real_only != 0);
     *count = (int)s.size();
     for (size_t i = 0; i < s.size(); ++i) out[i] = care_shift{s[i].re, s[i].im};
+    return CARE_OK;
+  });
+}
+
+care_status care_projection_shifts(care_ctx* cx, const care_csr* A, const double* B, const double* K, int32_t m,
+                                   const double* V, int64_t ldv, int32_t s, int32_t l0, int32_t prec,
+                                   care_shift* out, int32_t* count) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    check_csr_shape(A);
+    const int64_t n = A->n, ld = pad_ld(n);
+    if (!out || !count || l0 < 1 || s < 1 || m < 0) fail(CARE_ERR_ARG, "invalid projection-shift arguments");
+    if (!V || ldv < n) fail(CARE_ERR_ARG, "invalid V");
+    const bool smw = K != nullptr && m > 0;
+    if (smw && !B) fail(CARE_ERR_ARG, "B is NULL while K is given");
+    const Prec pr = prec_from_abi(prec);
+    SellOp op;
+    build_sell(ctx, A, pr, op);
+    std::vector<Shift> sh;
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      DBuf<T> Vs(ctx, (size_t)ld * s), Bs(ctx, (size_t)ld * std::max(m, 1)), Ks(ctx, (size_t)ld * std::max(m, 1));
+      copy_cols<double, T>(ctx, n, s, V, ldv, Vs.get(), ld);
+      if (smw) {
+        copy_cols<double, T>(ctx, n, m, B, n, Bs.get(), ld);
+        copy_cols<double, T>(ctx, n, m, K, n, Ks.get(), ld);
+      }
+      sh = projection_shifts<T>(ctx, op, Bs.get(), smw ? Ks.get() : nullptr, smw ? m : 0, Vs.get(), ld, s, l0);
+    };
+    if (pr == Prec::F64) run(double{});
+    else run(float{});
+    *count = (int)sh.size();
+    for (size_t i = 0; i < sh.size(); ++i) out[i] = care_shift{sh[i].re, sh[i].im};
     return CARE_OK;
   });
 }

@@ -252,16 +252,24 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
   const int64_t n = op.n;
   const int64_t ld = pad_ld(n);
   if (w <= 0) return out;
-  if (shifts.empty()) fail(CARE_ERR_ARG, "empty shift set");
+  const bool proj = prm.proj_shifts > 0;
+  if (shifts.empty() && !proj) fail(CARE_ERR_ARG, "empty shift set");
   const bool smw = K != nullptr && m > 0;
   std::vector<double> cn;
   out.res0 = gram_stats(ctx, n, W, ld, w, cn);
   if (!std::isfinite(out.res0)) fail(CARE_ERR_NONFINITE, "non-finite right-hand side factor");
   if (out.res0 == 0.0) return out;
+  // Projection shifts: the first set from span(W0) unless the caller gave
+  // one; each time a set is used up, the next from the span of the most
+  // recent blocks of Z (those of the last steps, until they hold l0
+  // columns).  A projection without a stable Ritz value keeps the set.
+  std::vector<Shift> cur = shifts;
+  if (cur.empty()) cur = projection_shifts<T>(ctx, op, B, smw ? K : nullptr, m, W, ld, w, prm.proj_shifts);
+  std::vector<int> step_col;   // first column of Z written by each step
 
   const int maxcols = smw ? w + m : w;
   DBuf<T> rhs(ctx, (size_t)ld * 2 * maxcols), sol(ctx, (size_t)ld * 2 * maxcols), tmp(ctx, (size_t)ld);
-  std::vector<ShiftCache> cache(shifts.size());
+  std::vector<ShiftCache> cache(cur.size());
   DBuf<double> dYr(ctx, (size_t)std::max(m, 1) * w), dYi(ctx, (size_t)std::max(m, 1) * w);
   std::vector<double> yr, yi;
   const bool trace = std::getenv("MPCARE_TRACE") != nullptr;
@@ -283,8 +291,28 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
   LradiParams sp = prm;   // per-step copy (Krylov tolerance)
   double rot_ref = 1.0;   // residual level of the last rotation of W
   while (out.steps < prm.jmax && wa > 0) {
-    const Shift p = shifts[idx % shifts.size()];
-    ShiftCache& sc = cache[idx % shifts.size()];
+    if (proj && idx >= cur.size() && out.zcols > 0) {
+      int c0 = out.zcols;
+      for (int t = (int)step_col.size() - 1; t >= 0; --t) {
+        c0 = step_col[t];
+        if (out.zcols - c0 >= prm.proj_shifts) break;
+      }
+      try {
+        std::vector<Shift> next =
+            projection_shifts<T>(ctx, op, B, smw ? K : nullptr, m, Z.get() + (int64_t)c0 * ld, ld, out.zcols - c0,
+                                 prm.proj_shifts);
+        cur = std::move(next);
+        std::vector<ShiftCache> fresh(cur.size());
+        cache.swap(fresh);
+      } catch (const CareError& e) {
+        if (e.status != CARE_ERR_UNSTABLE) throw;
+      }
+      idx = 0;
+      if (trace)
+        for (const Shift& q : cur) std::fprintf(stderr, "[lradi] projection shift (%.6e, %.6e)\n", q.re, q.im);
+    }
+    const Shift p = cur[idx % cur.size()];
+    ShiftCache& sc = cache[idx % cur.size()];
     // Inexact ADI (relaxation of the inner solves): an inner solve of
     // relative accuracy eps on W_{j-1} perturbs the Lyapunov residual by about
     // eps ||W_{j-1}||^2 = eps res_rel ||W0||^2, so once the residual has
@@ -306,6 +334,7 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
       if (cp) h2d(ctx, dYi.get(), yi.data(), (size_t)m * wa * sizeof(double));
     }
     T* Zb = Z.get() + (int64_t)out.zcols * ld;
+    step_col.push_back(out.zcols);
     dim3 g(ceil_div(n, 256), wa);
     const T* Sp = smw ? (const T*)sc.S.get() : nullptr;
     if (!cp) {

@@ -34,6 +34,7 @@ struct LradiParams {
   bool relax = false;        // inexact ADI: looser solves as the ADI residual shrinks (lradi_run)
   bool rotate = false;       // with deflate: rotate W to its principal directions (lradi_run)
   int group_split = 0;       // W0 columns [0, group_split) and the rest form separate groups
+  int proj_shifts = 0;       // > 0: projection shifts, at most this many per set (lradi_run)
 };
 
 struct LradiOut {
@@ -53,6 +54,17 @@ bool cinv(int m, std::vector<std::complex<double>>& A);
 
 // shift list checks: Re < 0, complex shifts as (p, conj p) with Im p > 0 first
 std::vector<Shift> check_shifts(const care_shift* s, int count);
+
+// Projection shifts (penzl.hip): the Ritz values of F = A^T - K B^T (K = NULL
+// or m = 0: A^T) on the span of the s columns of V (n x s, leading dimension
+// ldv; in the vector precision T of the operator's solves), restricted to
+// the dominant directions of V (eigenvalues of V^T V above 1e-10 of the
+// largest, at most 64 of them).  Ritz values in the right half-plane are
+// mirrored into the left one; at most l0 shifts are then chosen among them
+// by Penzl's greedy min-max rule.  B, K: n x m, ld pad_ld(n).
+template <typename T>
+std::vector<Shift> projection_shifts(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, const T* V,
+                                     int64_t ldv, int s, int l0);
 
 // Growable n x cap column buffer (ld pad_ld(n)) for the LR-ADI factor: the
 // factor's final width is known only at the end (column deflation), so the

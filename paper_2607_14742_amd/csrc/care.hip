@@ -151,6 +151,10 @@ struct SolveState {
   // shifts recomputed for each closed-loop operator A - B K^T (heuristic
   // mode with shift_update = 1)
   bool dyn_shifts = false;
+  // projection shifts drawn by each LR-ADI run from its own iterates
+  // (heuristic mode with shift_update = 2); shifts then holds the set of the
+  // projection onto span(C^T), for the a-priori choices that read it
+  bool proj_shifts = false;
   int l0 = 16, kp = 20, km = 10;
   bool real_only = false;
 };
@@ -158,6 +162,7 @@ struct SolveState {
 // the shift set for the operator A - B K^T of one Lyapunov solve: the fixed
 // set, or (dynamic shifts) the heuristic applied to that operator
 static std::vector<Shift> shifts_for(Ctx* ctx, const SolveState& S, const double* K64) {
+  if (S.proj_shifts) return {};
   if (!S.dyn_shifts || !K64 || S.m == 0) return S.shifts;
   std::vector<Shift> sh = penzl_shifts(ctx, *S.A64, S.l0, S.kp, S.km, S.real_only, S.B64.get(), K64, S.m);
   if (std::getenv("MPCARE_TRACE"))
@@ -198,13 +203,14 @@ static void stage0(Ctx* ctx, SolveState& S, TruncResult& Zout, care_stats* st, s
   lp.rotate = S.prm.deflate && S.prm.rotate && S.prm.prec != Prec::F64;
   lp.group_tol = S.prm.block_tol;
   lp.relax = S.prm.relax;
+  lp.proj_shifts = S.proj_shifts ? S.l0 : 0;
   double prev = 0.0;
   int zcols = 0;
   for (int i = 0; i < S.prm.k0_max; ++i) {
     const int w = (i == 0 || m == 0) ? p : p + m;
     d2d(ctx, W.get(), Cts.get(), (size_t)ld * p * sizeof(T));
     if (w > p) d2d(ctx, W.get() + (int64_t)p * ld, K.get(), (size_t)ld * m * sizeof(T));
-    std::vector<Shift> sh = S.shifts;
+    std::vector<Shift> sh = S.proj_shifts ? std::vector<Shift>() : S.shifts;
     if (S.dyn_shifts && i > 0 && m > 0) {
       DBuf<double> K64(ctx, (size_t)ld * m);
       copy_cols<T, double>(ctx, n, m, K.get(), ld, K64.get(), ld);
@@ -284,6 +290,7 @@ static void correction(Ctx* ctx, SolveState& S, const TruncResult& Zk, const Res
   lp.group_split = rf.rp;
   lp.group_tol = S.prm.block_tol;
   lp.relax = S.prm.relax;
+  lp.proj_shifts = S.proj_shifts ? S.l0 : 0;
   const std::vector<Shift> sh = shifts_for(ctx, S, (m > 0 && Zk.r > 0) ? K64.get() : nullptr);
   LradiOut lo = lradi_run<T>(ctx, *S.As, Bs.get(), (m > 0 && Zk.r > 0) ? Ks.get() : nullptr, m, W.get(), w, sh,
                              lp, Zb, zcap);
@@ -380,9 +387,17 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   S.kp = eff.penzl_kp;
   S.km = eff.penzl_km;
   S.real_only = eff.penzl_real != 0;
-  S.dyn_shifts = nshifts == 0 && eff.shift_update != 0;
+  if (eff.shift_update < 0 || eff.shift_update > 2) fail(CARE_ERR_ARG, "shift_update must be 0, 1 or 2");
+  S.dyn_shifts = nshifts == 0 && eff.shift_update == 1;
+  S.proj_shifts = nshifts == 0 && eff.shift_update == 2;
+  if (S.proj_shifts && eff.penzl_l0 < 1) fail(CARE_ERR_ARG, "projection shifts need penzl_l0 >= 1");
   if (nshifts > 0) {
     S.shifts = check_shifts(shifts, nshifts);
+  } else if (S.proj_shifts) {
+    // C is p x n row-major: the n x p matrix C^T, leading dimension n
+    S.shifts = projection_shifts<double>(ctx, A64, nullptr, nullptr, 0, C, n, p, eff.penzl_l0);
+    if (std::getenv("MPCARE_TRACE"))
+      for (const Shift& sh : S.shifts) std::fprintf(stderr, "[projection C^T] shift (%.6e, %.6e)\n", sh.re, sh.im);
   } else {
     S.shifts = penzl_shifts(ctx, A64, eff.penzl_l0, eff.penzl_kp, eff.penzl_km, eff.penzl_real != 0);
     if (std::getenv("MPCARE_TRACE"))

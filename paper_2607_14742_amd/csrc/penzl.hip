@@ -1,5 +1,7 @@
-// Heuristic ADI shifts from Ritz values: the "shifts generated from Krylov
-// subspaces" of Sec. 5, read as Penzl's procedure (Penzl 2000, Sec. 5):
+// Heuristic ADI shifts from Ritz values.  Sec. 5 says only that its shifts
+// come from Krylov subspaces, computed as the run goes; read here as Penzl's
+// procedure (Penzl 2000, Sec. 5) or as projection shifts (below,
+// projection_shifts).  Penzl's procedure:
 //   1. kp Arnoldi steps with F = A^T from b0 = ones / sqrt(n) -> Ritz values
 //   2. km Arnoldi steps with F^{-1} -> Ritz values, inverted
 //   3. candidates: the Ritz values in the open left half-plane
@@ -280,6 +282,100 @@ static std::vector<cplx> arnoldi_ritz(Ctx* ctx, const SellOp& op, int k, bool in
     for (cplx& t : ev) t = 1.0 / t;
   return ev;
 }
+
+// Reduction of a real k x k matrix (column-major, leading dimension k) to
+// upper Hessenberg form by Householder similarity transformations
+// (Golub & Van Loan, Sec. 7.4.3): the eigenvalues are unchanged.  Host.
+static void hessenberg_reduce(std::vector<double>& a, int k) {
+  auto A = [&](int i, int j) -> double& { return a[(size_t)j * k + i]; };
+  std::vector<double> v(k);
+  for (int c = 0; c + 2 < k; ++c) {
+    double alpha = 0.0;
+    for (int i = c + 1; i < k; ++i) alpha += A(i, c) * A(i, c);
+    alpha = std::sqrt(alpha);
+    if (alpha == 0.0) continue;
+    if (A(c + 1, c) > 0.0) alpha = -alpha;
+    const int len = k - c - 1;
+    double vn2 = 0.0;
+    for (int t = 0; t < len; ++t) {
+      v[t] = A(c + 1 + t, c) - (t == 0 ? alpha : 0.0);
+      vn2 += v[t] * v[t];
+    }
+    if (vn2 == 0.0) continue;
+    const double beta = 2.0 / vn2;
+    for (int j = c; j < k; ++j) {            // rows c+1.. from the left
+      double d = 0.0;
+      for (int t = 0; t < len; ++t) d += v[t] * A(c + 1 + t, j);
+      d *= beta;
+      for (int t = 0; t < len; ++t) A(c + 1 + t, j) -= d * v[t];
+    }
+    for (int i = 0; i < k; ++i) {            // columns c+1.. from the right
+      double d = 0.0;
+      for (int t = 0; t < len; ++t) d += A(i, c + 1 + t) * v[t];
+      d *= beta;
+      for (int t = 0; t < len; ++t) A(i, c + 1 + t) -= d * v[t];
+    }
+    for (int i = c + 2; i < k; ++i) A(i, c) = 0.0;
+  }
+}
+
+// Projection shifts (Benner, Kuerschner and Saak, ETNA 43, 2014): the other
+// reading of Sec. 5's Krylov-subspace shifts, in which each LR-ADI run draws
+// its shifts from its own iterates as it goes.  Steps:
+//   1. the dominant directions of span(V): V^T V = U L U^T,
+//      Q = V U_k L_k^{-1/2} over the eigenvalues above 1e-10 max L (<= 64);
+//   2. H = Q^T F Q with F = A^T - K B^T (sparse product, Gram);
+//   3. the eigenvalues of H (host: Hessenberg reduction, Francis QR);
+//   4. mirrored into the open left half-plane, Penzl's greedy choice of at
+//      most l0 among them.
+template <typename T>
+std::vector<Shift> projection_shifts(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, const T* V,
+                                     int64_t ldv, int s, int l0) {
+  const int64_t n = op.n, ld = pad_ld(n);
+  if (s < 1 || l0 < 1) fail(CARE_ERR_ARG, "projection shifts need s >= 1 and l0 >= 1");
+  if (!V || ldv < n) fail(CARE_ERR_ARG, "invalid projection basis");
+  if ((op.prec == Prec::F64) != (sizeof(T) == 8)) fail(CARE_ERR_ARG, "projection basis precision mismatch");
+  DBuf<double> G(ctx, (size_t)s * s);
+  gram<T, T>(ctx, n, V, ldv, s, V, ldv, s, G.get(), s);
+  std::vector<double> lam;
+  dsyevd(ctx, s, G.get(), s, lam);
+  const double lmax = lam.back();
+  if (!(lmax > 0.0) || !std::isfinite(lmax)) fail(CARE_ERR_BREAKDOWN, "projection basis is zero or not finite");
+  std::vector<int> sel;
+  std::vector<double> isq;
+  for (int i = s - 1; i >= 0 && (int)sel.size() < 64; --i)
+    if (lam[i] > 1e-10 * lmax) {
+      sel.push_back(i);
+      isq.push_back(1.0 / std::sqrt(lam[i]));
+    }
+  const int k = (int)sel.size();
+  DBuf<double> Uk(ctx, (size_t)s * k);
+  copy_cols<double, double>(ctx, s, k, G.get(), s, Uk.get(), s, sel.data(), isq.data());
+  DBuf<T> Q(ctx, (size_t)ld * k), Y(ctx, (size_t)ld * k);
+  tsgemm<T, T>(ctx, n, V, ldv, s, Uk.get(), s, k, 1.0, 0.0, Q.get(), ld);
+  spmm_plain(ctx, op, 0.0, 0.0, Q.get(), ld, k, Y.get(), ld);
+  if (B && K && m > 0) {   // Y -= K (B^T Q)
+    DBuf<double> Cq(ctx, (size_t)m * k);
+    gram<T, T>(ctx, n, B, ld, m, Q.get(), ld, k, Cq.get(), m);
+    tsgemm<T, T>(ctx, n, K, ld, m, Cq.get(), m, k, -1.0, 1.0, Y.get(), ld);
+  }
+  DBuf<double> H(ctx, (size_t)k * k);
+  gram<T, T>(ctx, n, Q.get(), ld, k, Y.get(), ld, k, H.get(), k);
+  std::vector<double> h((size_t)k * k);
+  d2h(ctx, h.data(), H.get(), h.size() * sizeof(double));
+  for (double x : h)
+    if (!std::isfinite(x)) fail(CARE_ERR_NONFINITE, "projected matrix is not finite");
+  hessenberg_reduce(h, k);
+  std::vector<cplx> ev = hessenberg_eigvals(h.data(), k, k);
+  for (cplx& t : ev)
+    if (t.real() > 0.0) t = -std::conj(t);
+  return penzl_select(ev, l0);
+}
+
+template std::vector<Shift> projection_shifts<double>(Ctx*, const SellOp&, const double*, const double*, int,
+                                                      const double*, int64_t, int, int);
+template std::vector<Shift> projection_shifts<float>(Ctx*, const SellOp&, const float*, const float*, int,
+                                                     const float*, int64_t, int, int);
 
 std::vector<Shift> penzl_shifts(Ctx* ctx, const SellOp& A64, int l0, int kp, int km, bool real_only, const double* B,
                                 const double* K, int m) {

@@ -94,3 +94,83 @@ def test_config1_newton_with_real_heuristic_shifts_vs_schur(pk, ctx):
     rel = lowrank.residual_norm(P.A, P.B, P.C, Z) / np.linalg.norm(P.C @ P.C.T)
     assert rel <= 1e-10
     assert np.linalg.norm(Z @ Z.T - Xs) <= 1e-8 * np.linalg.norm(Xs)
+
+
+# ---------------------------------------------------------------------------
+# projection shifts (NEXT 1): the building block against the oracle, and
+# solves that draw their shifts from their own LR-ADI iterates
+# ---------------------------------------------------------------------------
+def _sorted(z):
+    z = np.asarray(z)
+    return z[np.lexsort((z.imag, z.real))]
+
+
+@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-8), ("fp32", 2e-3)])
+@pytest.mark.parametrize("smw", [False, True])
+@pytest.mark.parametrize("s", [1, 7, 90])      # 90: more columns than the 64 dominant directions kept
+def test_projection_shifts_match_oracle(pk, ctx, prec, rtol, smw, s):
+    A = wl.fdm2d(18, 40.0)
+    n = A.shape[0]
+    rng = np.random.default_rng(17 + s)
+    V = rng.standard_normal((n, s)) @ np.diag(np.geomspace(1.0, 1e-3, s))
+    B = rng.standard_normal((n, 2)) if smw else None
+    K = 30.0 * rng.standard_normal((n, 2)) if smw else None
+    print(f"projection shifts n={n} s={s} smw={smw} {prec}", flush=True)
+    got = pk.projection_shifts(ctx, pk.DeviceCSR.from_scipy(A), dev(V), l0=10,
+                               B=dev(B) if smw else None, K=dev(K) if smw else None, prec=prec)
+    ref = osh.projection_shifts(A, V, 10, B=B, K=K)
+    assert len(got) == len(ref)
+    g, r = _sorted(got), _sorted(ref)
+    assert np.all(g.real < 0)
+    assert np.abs(g - r).max() <= rtol * np.abs(r).max(), (g, r)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_care_solve_with_projection_shifts(pk, ctx, prec):
+    # no shift set given, shift_update = 2: every LR-ADI run (Newton steps
+    # and corrections) draws its own shifts; the solution must be the CARE's
+    # (20 x 20 grid: the dense Schur oracle below is O(n^3) on the host)
+    P = wl.fdm2d_problem(20, 2, 3)
+    Z, stats, st = pk.care_solve(ctx, pk.DeviceCSR.from_scipy(P.A), dev(P.B), dev(P.C), tol=1e-11, shifts=None,
+                                 prec=prec, shift_update=2, penzl_l0=10)
+    print(f"projection-shift solve {prec}: status {st} iter0 {stats['iter0_outer']}({stats['iter0_inner']}) "
+          f"iter {stats['iter_outer']}({stats['iter_inner']}) rank {stats['rank']}", flush=True)
+    assert st == 0, stats
+    Z = Z.cpu().numpy()
+    rel = lowrank.residual_norm(P.A, P.B, P.C, Z) / np.linalg.norm(P.C @ P.C.T)
+    assert rel <= 1e-11
+    print(f"  relres {rel:.2e}; dense Schur oracle at n = {P.n}", flush=True)
+    Xs = riccati.care_schur(P.A.toarray(), P.B, P.C)
+    assert np.linalg.norm(Z @ Z.T - Xs) <= 1e-8 * np.linalg.norm(Xs)
+
+
+def test_care_solve_with_projection_shifts_complex(pk, ctx):
+    # rotating 3D field: the projected operators have complex Ritz values;
+    # a 40 x 40 2D problem as well, checked by the oracle's factored residual
+    P2 = wl.fdm2d_problem(40, 2, 3)
+    Z2, s2, st2 = pk.care_solve(ctx, pk.DeviceCSR.from_scipy(P2.A), dev(P2.B), dev(P2.C), tol=1e-11, shifts=None,
+                                prec="fp32", shift_update=2, penzl_l0=10)
+    assert st2 == 0, s2
+    rel2 = lowrank.residual_norm(P2.A, P2.B, P2.C, Z2.cpu().numpy()) / np.linalg.norm(P2.C @ P2.C.T)
+    print(f"projection-shift solve fdm2d 40x40 fp32: relres {rel2:.2e} iter0 {s2['iter0_outer']}"
+          f"({s2['iter0_inner']}) iter {s2['iter_outer']}({s2['iter_inner']})", flush=True)
+    assert rel2 <= 1e-11
+    P = wl.fdm3d_problem(8, 1, 10)
+    Z, stats, st = pk.care_solve(ctx, pk.DeviceCSR.from_scipy(P.A), dev(P.B), dev(P.C), tol=1e-11, shifts=None,
+                                 prec="fp32", shift_update=2, penzl_l0=12)
+    assert st == 0, stats
+    rel = lowrank.residual_norm(P.A, P.B, P.C, Z.cpu().numpy()) / np.linalg.norm(P.C @ P.C.T)
+    assert rel <= 1e-11
+
+
+def test_lyap_lradi_with_projection_shifts(pk, ctx):
+    A = wl.fdm2d(30)
+    n = A.shape[0]
+    W = np.random.default_rng(2).standard_normal((n, 3))
+    Z, stats, st = pk.lyap_lradi(ctx, pk.DeviceCSR.from_scipy(A), dev(W), shifts=[], tol=1e-10,
+                                 opts=pk.default_opts("fp64", shift_update=2, penzl_l0=8))
+    assert st == 0, stats
+    Z = Z.cpu().numpy()
+    X = Z @ Z.T
+    R = A.T @ X + X @ A + W @ W.T
+    assert np.linalg.norm(R) <= 1e-8 * np.linalg.norm(W @ W.T)

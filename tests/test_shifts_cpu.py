@@ -1,7 +1,7 @@
-"""Shift heuristic (Ritz values + greedy min-max, the reading of the Sec. 5
-"shifts generated from Krylov subspaces"): the oracle pinned to closed
-forms, and the library's host steps (Hessenberg eigenvalues, greedy choice)
-checked against the oracle and LAPACK.  No GPU work."""
+"""Shift heuristic (Ritz values + greedy min-max, one reading of the
+Krylov-subspace shifts of Sec. 5): the oracle pinned to closed forms, and
+the library's host steps (Hessenberg eigenvalues, greedy choice) checked
+against the oracle and LAPACK.  No GPU work."""
 import os
 
 import numpy as np
@@ -156,3 +156,57 @@ def test_wachspress_shifts_equioscillate(lo, hi, J):
     for qj in q:
         rq *= (lam - qj) / (lam + qj)
     assert np.abs(rq).max() > ext.max()
+
+
+# ---------------------------------------------------------------------------
+# projection shifts (oracle): pinned to hand-computed Ritz values
+# ---------------------------------------------------------------------------
+def _as_set(z):
+    return sorted(np.round(np.asarray(z), 12), key=lambda t: (t.real, t.imag))
+
+
+def test_projection_shifts_on_an_invariant_subspace_are_its_eigenvalues():
+    # span(V) = span(e2, e5, e7) is invariant under a diagonal A: the Ritz
+    # values are A's eigenvalues there, whatever basis V holds
+    A = sp.diags(-np.arange(1.0, 11.0)).tocsr()
+    V = np.zeros((10, 3))
+    V[2, 0], V[5, 1], V[2, 1], V[7, 2] = 3.0, 1.0, 1.0, 0.5
+    got = osh.projection_shifts(A, V, l0=5)
+    assert _as_set(got) == _as_set([-3.0, -6.0, -8.0])
+
+
+def test_projection_shifts_of_a_rotation_block_are_a_conjugate_pair():
+    a, b = -2.0, 3.0
+    A = np.diag([-5.0, 0.0, 0.0, -7.0])
+    A[1:3, 1:3] = [[a, b], [-b, a]]
+    V = np.zeros((4, 2))
+    V[1, 0] = V[2, 1] = 1.0
+    got = osh.projection_shifts(A, V, l0=4)
+    assert len(got) == 2
+    assert np.allclose(got, [complex(a, b), complex(a, -b)], atol=1e-12)   # Im > 0 first
+
+
+def test_projection_shifts_mirror_unstable_ritz_values():
+    A = sp.diags([2.0, -3.0, -4.0]).tocsr()
+    V = np.eye(3)[:, :2]
+    assert _as_set(osh.projection_shifts(A, V, l0=4)) == _as_set([-2.0, -3.0])
+
+
+def test_projection_shifts_use_the_closed_loop_operator():
+    # F = A^T - K B^T with B = e1, K = c e1: F = diag(-1 - c, -2, -3)
+    c = 4.0
+    A = sp.diags([-1.0, -2.0, -3.0]).tocsr()
+    B = np.array([[1.0], [0.0], [0.0]])
+    K = c * B
+    V = np.eye(3)[:, :2]
+    assert _as_set(osh.projection_shifts(A, V, l0=4, B=B, K=K)) == _as_set([-1.0 - c, -2.0])
+
+
+def test_projection_shifts_depend_on_the_subspace_only():
+    A = wl.fdm2d(9)
+    rng = np.random.default_rng(5)
+    V = rng.standard_normal((81, 5))
+    R = rng.standard_normal((5, 5)) + 5.0 * np.eye(5)
+    s1 = osh.projection_shifts(A, V, l0=8)
+    s2 = osh.projection_shifts(A, np.hstack([V @ R, V[:, :2]]), l0=8)   # another basis, with repeated columns
+    assert np.allclose(_as_set(s1), _as_set(s2), rtol=1e-9, atol=0)
