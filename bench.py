@@ -22,6 +22,11 @@ of the Krylov chunks).  After them:
 (B n x 10 with ||B||_F = 1, C 5 x n, one heuristic shift set shared by both
 precisions); its line carries no CPU baseline, no oracle X samples and no
 counter traffic.
+
+`--workload fdm_batch` times the uneven batch of 32 2D FDM CAREs (grids
+N = 100 ... 632, n = 1e4 ... 4e5, (m, p) from {1..8}) solved in one batched
+call on concurrent worker streams, FP32 inner vs FP64, and prints its own
+line (a step is one batched solve of all 32).
 """
 from __future__ import annotations
 
@@ -51,8 +56,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("fdm2d", "toeplitz"), default="fdm2d",
-                    help="fdm2d: the 2D FDM problem (default); toeplitz: the Toeplitz example of Sec. 5.2")
+    ap.add_argument("--workload", choices=("fdm2d", "toeplitz", "fdm_batch"), default="fdm2d",
+                    help="fdm2d: the 2D FDM problem (default); toeplitz: the Toeplitz example of Sec. 5.2; "
+                         "fdm_batch: the 32-instance uneven FDM batch")
     ap.add_argument("--N", type=int, default=500, help="fdm2d grid size (500 -> n = 250000)")
     ap.add_argument("--n", type=int, default=131072, help="toeplitz matrix size")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison solves")
@@ -89,6 +95,52 @@ def spmm_sweep(pk, wl, torch):
         del Ad
     ctx.close()
     return rows
+
+
+def fdm_batch_bench(args, pk, wl, torch, np):
+    """One JSON line for the 32-instance uneven FDM batch: wall time of one
+    batched care_solve_batch call (4 worker streams) per precision."""
+    count = 32
+    probs = [wl.fdm_batch_problem(i, count) for i in range(count)]
+    dev = "cuda:0"
+    items = [(pk.DeviceCSR.from_scipy(P.A, dev), torch.as_tensor(P.B, device=dev), torch.as_tensor(P.C, device=dev),
+              P.shifts) for P in probs]
+    ctx = pk.Context(0)
+
+    def run(prec):
+        times, last = [], None
+        for it in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = pk.care_solve_batch(ctx, items, tol=TOL, prec=prec, workers=4)
+            torch.cuda.synchronize()
+            if it >= args.warmup:
+                times.append(time.perf_counter() - t)
+            last = out
+        worst = max(s["res_rel"] for _, s, _, _ in last)
+        bad = sum(1 for _, _, st, _ in last if st != 0)
+        its = sum(s["krylov_iters"] for _, s, _, _ in last)
+        print(f"[bench] fdm_batch {prec}: {np.mean(times):.3f} s, worst relres {worst:.2e}", file=sys.stderr,
+              flush=True)
+        return {"mean_s": round(float(np.mean(times)), 4), "solve_s": [round(t, 4) for t in times],
+                "worst_relres": worst, "failed_instances": bad, "krylov_column_iters": its}
+
+    r32 = run("fp32")
+    res = {"metric": "CARE batch solve time, 32 uneven FDM instances, at rel residual <=1e-10",
+           "value": r32["mean_s"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * r32["mean_s"], 2), "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"uneven 2D FDM batch: {count} instances, n {probs[0].n}..{probs[-1].n}, "
+                                  f"{sum(P.A.nnz for P in probs)} nonzeros in all, (m, p) in 1..8, "
+                                  "12 Wachspress shifts each, 4 worker streams, FP32 inner / FP64 refine, "
+                                  f"tol {TOL:g}"},
+           "fp32_inner": r32}
+    if not args.no_fp64:
+        r64 = run("fp64")
+        res["fp64"] = r64
+        res["speedup_fp32_inner_vs_fp64"] = round(r64["mean_s"] / r32["mean_s"], 3)
+    ctx.close()
+    print(json.dumps(res))
 
 
 def measured_traffic():
@@ -201,6 +253,10 @@ def main():
         print(json.dumps({"metric": "SpMM HBM GB/s (standalone, rotated operands > 1 GiB)", "value": best["GB/s"],
                           "unit": "GB/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
                           "peak": HBM_PEAK_GBS, "rows": rows}))
+        return
+
+    if args.workload == "fdm_batch":
+        fdm_batch_bench(args, pk, wl, torch, np)
         return
 
     dev = "cuda:0"

@@ -242,10 +242,28 @@ care_status care_ctx_create(care_ctx** ctx, int32_t device, void* stream, care_a
                             care_dealloc_fn dealloc, void* user);
 void care_ctx_destroy(care_ctx* ctx);
 
-/* Default options for inner precision `inner_prec`: the values of Sec. 5
- * (eta_r = 1e-4 max|lambda(H)|, eta_s = 10 u max|lambda(P)|, tau_L = 1e-12
- * for FP64, k_max = 20, j_max = 50), except tau_L = 1e-6 for FP32 (paper:
- * 1e-5) and the refinement forcing theta = 0.25 (paper: none). */
+/* Default options for inner precision `inner_prec`.  Taken from Sec. 5:
+ * eta_r = 1e-4 max|lambda(H)|, eta_s = 10 u max|lambda(P)|, tau_L = 1e-12
+ * for FP64, k_max = 20, j_max = 50, stagnation ratio 0.999, GMRES restart
+ * 30 (FP32) / 50 (FP64) when krylov_method = 1.  Departures from Sec. 5:
+ *   - tau_L = 1e-6 for FP32 (paper 1e-5), 1e-4 / 1e-3 for FP16 / BF16
+ *     products (not in the paper);
+ *   - inner solver: column-batched BiCGStab on the red-black reduced
+ *     operator where A is two-colourable with a constant diagonal
+ *     (krylov_rb = 1), unpreconditioned BiCGStab otherwise (paper:
+ *     ILU(0)-preconditioned restarted GMRES); Krylov tolerance 1e-7 for
+ *     FP32 (paper 1e-5), max(1e-13, min(1e-10, tol / 10)) for FP64 (paper
+ *     1e-10); iteration cap 4000 (paper 100 / 200 GMRES steps);
+ *   - refinement forcing theta = 0.25 (refine_forcing; paper: fixed
+ *     tolerances) with residual-budget truncation in Algorithms 1 and 2;
+ *   - inexact LR-ADI (krylov_relax = 1), column deflation (adi_deflate = 1),
+ *     rotation of the FP32 residual factor (adi_rotate = 1), block-relative
+ *     Krylov accuracy for FP32 (krylov_block_tol = -1), column compaction
+ *     (krylov_compact = 1), panel-width autotuning (spmm_tune = 1): none is
+ *     in the paper, each leaves the solution within the tolerance;
+ *   - heuristic shifts (nshifts = 0): Penzl's procedure with l0 = 16,
+ *     kp = 20, km = 10 computed once from A (shift_update = 0); the paper
+ *     says only that its shifts come from Krylov subspaces. */
 void care_opts_default(care_opts* opts, int32_t inner_prec);
 
 /* Message describing the last error of the calling thread ("" if none). */

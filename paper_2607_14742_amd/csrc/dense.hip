@@ -626,22 +626,34 @@ void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out
   }
   DBuf<double> csq(ctx, q);
   std::vector<double> hcsq(q);
-  for (int pass = 0; pass < 5; ++pass) {
+  // Frobenius norm of the scaled Gram of the current remainder (G holds
+  // the Gram afterwards); it bounds the remainder's largest eigenvalue
+  auto remainder_fro = [&]() {
+    gram(ctx, n, Ecur, lde, q, Ecur, lde, q, G.get(), q);
+    hipLaunchKernelGGL(k_scaled_colsq, dim3(q), dim3(256), 0, ctx->stream, G.get(), (int64_t)q, q, ds.get(),
+                       csq.get());
+    KERNEL_CHECK();
+    d2h(ctx, hcsq.data(), csq.get(), (size_t)q * sizeof(double));
+    double fro2 = 0.0;
+    for (double v : hcsq) fro2 += v;
+    return std::sqrt(fro2);
+  };
+  // Each pass resolves about eleven decades of the scaled Gram's spectrum
+  // and the noise floor lies about 28 decades down, so three passes
+  // normally suffice; the loop ends earlier when the remainder reaches the
+  // noise level or F's rank is exhausted.
+  const int max_passes = 6;
+  bool complete = false;
+  for (int pass = 0; pass < max_passes; ++pass) {
     if (pass > 0 || k0 > 0) {
-      gram(ctx, n, Ecur, lde, q, Ecur, lde, q, G.get(), q);
-      // the scaled Gram's Frobenius norm bounds its largest eigenvalue: a
-      // remainder at the noise level ends the loop here, as the eigen-
+      // a remainder at the noise level ends the loop here, as the eigen-
       // decomposition below would (it selects nothing when lmax <= noise)
-      hipLaunchKernelGGL(k_scaled_colsq, dim3(q), dim3(256), 0, ctx->stream, G.get(), (int64_t)q, q, ds.get(),
-                         csq.get());
-      KERNEL_CHECK();
-      d2h(ctx, hcsq.data(), csq.get(), (size_t)q * sizeof(double));
-      double fro2 = 0.0;
-      for (double v : hcsq) fro2 += v;
-      if (std::sqrt(fro2) <= noise) {
+      const double fro = remainder_fro();
+      if (fro <= noise) {
         if (trace)
           std::fprintf(stderr, "[rr_orth] n %lld q %d pass %d ||G||_F %.3e at noise: done\n", (long long)n, q, pass,
-                       std::sqrt(fro2));
+                       fro);
+        complete = true;
         break;
       }
     }
@@ -659,7 +671,10 @@ void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out
         sel.push_back(i);
         isq.push_back(1.0 / std::sqrt(lam[i]));
       }
-    if (sel.empty()) break;
+    if (sel.empty()) {
+      complete = true;
+      break;
+    }
     const int kk = (int)sel.size();
     // B = S W_sel L_sel^{-1/2}
     copy_cols<double, double>(ctx, q, kk, W.get(), q, B.get(), q, sel.data(), isq.data());
@@ -678,11 +693,22 @@ void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out
       std::fprintf(stderr, "[rr_orth] n %lld q %d pass %d lmax %.3e thr %.3e new %d\n", (long long)n, q, pass, lmax,
                    thr, kk);
     const int kept = polish(ctx, n, Unew, ld, kk, trace);
-    if (kept == 0) break;
+    if (kept == 0) {
+      complete = true;      // what is left projects to noise (polish dropped it)
+      break;
+    }
     out.k += kept;
     project();
-    if (out.k >= kcap) break;
+    if (out.k >= kcap) {
+      complete = true;      // the basis spans [U0, F]
+      break;
+    }
   }
+  // The pass cap must not leave a part of F above the noise level out of T:
+  // Algorithm 1 would then underestimate ||R||_F, Framework 1's stop test.
+  if (!complete && remainder_fro() > noise)
+    fail(CARE_ERR_BREAKDOWN, "rank-revealing orthogonalisation left a remainder above the noise level after " +
+                                 std::to_string(max_passes) + " passes");
   if (out.k == 0) return;
   ctx->sync();
 }
