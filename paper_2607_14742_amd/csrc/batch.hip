@@ -10,9 +10,12 @@
 // last.  A memory budget (60 % of the device memory free at the start) caps
 // the estimated peak workspace of the instances running at once: a worker
 // takes the largest waiting instance that fits, or waits; an instance runs
-// alone when nothing else does.  Running out of device memory mid-solve can
-// also starve the runtime's own allocations (kernel scratch), which is not an
-// error the library could catch.
+// alone when nothing else does.  The estimate can fall short (factor widths
+// depend on the problem, and other users of the device hold memory too): an
+// instance whose device allocation fails is queued again once, to run alone
+// when the other workers are idle.  Running out of device
+// memory mid-solve can also starve the runtime's own allocations (kernel
+// scratch), which is not an error the library could catch.
 #include <algorithm>
 #include <condition_variable>
 #include <cstring>
@@ -66,7 +69,7 @@ void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, con
   const double budget = 0.6 * (double)mem_free;
   std::mutex mu;
   std::condition_variable cv;
-  std::vector<char> taken(count, 0);
+  std::vector<char> taken(count, 0), alone(count, 0);
   int remaining = count, running = 0;
   double in_use = 0.0;
   // next instance for a worker (largest waiting one that fits), or -1 when
@@ -78,6 +81,7 @@ void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, con
       for (int i = 0; i < count; ++i) {
         const int k = order[i];
         if (taken[k]) continue;
+        if (alone[k] && running > 0) continue;
         const double e = estimate(k);
         if (running == 0 || in_use + e <= budget) {
           taken[k] = 1;
@@ -91,11 +95,22 @@ void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, con
       cv.wait(lk);
     }
   };
-  auto release = [&](double est) {
+  // requeue: an instance that ran out of device memory runs again alone
+  // (once); its result is reset under the lock, before another worker can
+  // take it
+  auto release = [&](double est, int k, bool requeue) {
     {
       std::lock_guard<std::mutex> lk(mu);
       --running;
       in_use -= est;
+      if (requeue && !alone[k]) {
+        std::memset(&res[k], 0, sizeof(res[k]));
+        res[k].status = CARE_ERR_DEVICE;
+        std::strncpy(res[k].message, "not run", sizeof(res[k].message) - 1);
+        alone[k] = 1;
+        taken[k] = 0;
+        ++remaining;
+      }
     }
     cv.notify_all();
   };
@@ -156,7 +171,7 @@ void solve_batch(Ctx* ctx, int count, const care_instance* inst, double tol, con
       // concurrent workers share the device memory: hand this instance's
       // cached workspace back before the next one
       wc.arena->trim();
-      release(est);
+      release(est, k, R.status == CARE_ERR_NOMEM);
     }
     ctx_release(wc);
   };

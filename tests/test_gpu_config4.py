@@ -75,6 +75,7 @@ def solve_all(pk, ctx, prec):
         items.append((dev(A), dev(B), dev(C), wl.logspaced_real_shifts(1.0, 10.0 ** q, 16)))
         qs.append(q)
     print(f"dense batch of {len(items)} instances, {prec} inner", flush=True)
+    torch.cuda.empty_cache()      # the batch's workers allocate beside this process's cached blocks
     return pk.care_solve_batch(ctx, items, tol=TOL, prec=prec, workers=4), qs
 
 

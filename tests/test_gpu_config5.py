@@ -42,6 +42,7 @@ def test_fdm_batch_all_instances_meet_the_gate_by_the_oracle_residual(pk, ctx):
     print(f"FDM batch of {COUNT}: n from {probs[0].n} to {probs[-1].n}, "
           f"{sum(P.A.nnz for P in probs)} nonzeros in all", flush=True)
     items = [(pk.DeviceCSR.from_scipy(P.A), dev(P.B), dev(P.C), P.shifts) for P in probs]
+    torch.cuda.empty_cache()      # the batch's workers allocate beside this process's cached blocks
     out = pk.care_solve_batch(ctx, items, tol=TOL, prec="fp32", workers=4)
     worst = 0.0
     for i, (P, (Z, s, st, msg)) in enumerate(zip(probs, out)):
