@@ -543,8 +543,7 @@ static int polish(Ctx* ctx, int64_t n, double* U, int64_t ldu, int k, bool trace
   copy_cols<double, double>(ctx, k, kk, G.get(), k, B.get(), k, sel.data(), isq.data());
   DBuf<double> tmp(ctx, (size_t)pad_ld(n) * kk);
   tsgemm(ctx, n, U, ldu, k, B.get(), k, kk, 1.0, 0.0, tmp.get(), pad_ld(n));
-  for (int j = 0; j < kk; ++j)
-    d2d(ctx, U + (int64_t)j * ldu, tmp.get() + (int64_t)j * pad_ld(n), n * sizeof(double));
+  copy_cols<double, double>(ctx, n, kk, tmp.get(), pad_ld(n), U, ldu);
   return kk;
 }
 
@@ -601,28 +600,40 @@ void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out
   DBuf<double> ds(ctx, q);
   h2d(ctx, ds.get(), s.data(), q * sizeof(double));
 
+  // E: the remainder F - U (U^T F), updated in place block by block
   DBuf<double> E(ctx, (size_t)ld * q);
-  const double* Ecur = F;
-  int64_t lde = ldf;
+  copy_cols<double, double>(ctx, n, q, F, ldf, E.get(), ld);
+  const double* Ecur = E.get();
+  const int64_t lde = ld;
   const double noise = (64.0 * u) * (64.0 * u) * q;
   DBuf<double> W(ctx, (size_t)q * q), B(ctx, (size_t)q * q), Tf(ctx, (size_t)kcap * q), T2(ctx, (size_t)kcap * q);
+  // search-space bases of the passes (see below) and their work space
+  DBuf<double> Rest(ctx, (size_t)q * q), RestNext(ctx, (size_t)q * q), Tmp(ctx, (size_t)q * q),
+      Hred(ctx, (size_t)q * q);
+  bool have_rest = false;
+  int nrest = 0;
+  // T = U^T F with rows added block by block (leading dimension kcap)
+  DBuf<double> Tacc(ctx, (size_t)kcap * q);
+  dzero(ctx, Tacc.get(), (size_t)kcap * q * sizeof(double));
   std::vector<double> lam;
-  // E = F - U (U^T F), twice; T = U^T F accumulated over both projections
-  auto project = [&]() {
-    gram(ctx, n, out.U.get(), ld, out.k, F, ldf, q, Tf.get(), out.k);
-    copy_cols<double, double>(ctx, n, q, F, ldf, E.get(), ld);
-    tsgemm(ctx, n, out.U.get(), ld, out.k, Tf.get(), out.k, q, -1.0, 1.0, E.get(), ld);
-    gram(ctx, n, out.U.get(), ld, out.k, E.get(), ld, q, T2.get(), out.k);
-    tsgemm(ctx, n, out.U.get(), ld, out.k, T2.get(), out.k, q, -1.0, 1.0, E.get(), ld);
-    const double one = 1.0;
-    ROCBLAS_CHECK(rocblas_dgeam(ctx->blas, rocblas_operation_none, rocblas_operation_none, out.k, q, &one, Tf.get(),
-                                out.k, &one, T2.get(), out.k, out.T.get(), out.k));
-    Ecur = E.get();
-    lde = ld;
+  // For the block U_b = U(:, c0:c1) just added: E -= U_b (U_b^T E), twice
+  // (block classical Gram-Schmidt with reorthogonalisation), and its rows of
+  // T are U_b^T E summed over both sweeps.  E is already orthogonal to the
+  // earlier columns and so is U_b, so U_b^T F = U_b^T E to rounding, and the
+  // earlier blocks need no second look.
+  auto project_block = [&](int c0, int c1) {
+    const int kb = c1 - c0;
+    if (kb <= 0) return;
+    const double* Ub = out.U.get() + (int64_t)c0 * ld;
+    for (int rep = 0; rep < 2; ++rep) {
+      gram(ctx, n, Ub, ld, kb, E.get(), ld, q, Tf.get(), kb);
+      tsgemm(ctx, n, Ub, ld, kb, Tf.get(), kb, q, -1.0, 1.0, E.get(), ld);
+      axpby<double>(ctx, kb, q, 1.0, Tf.get(), kb, 1.0, Tacc.get() + c0, kcap);
+    }
   };
   if (k0 > 0) {
     out.k = k0;
-    project();
+    project_block(0, k0);
   }
   DBuf<double> csq(ctx, q);
   std::vector<double> hcsq(q);
@@ -661,23 +672,57 @@ void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out
     dim3 gs(ceil_div(q, 64), q);
     hipLaunchKernelGGL(k_scale_sym, gs, dim3(64), 0, ctx->stream, W.get(), (int64_t)q, q, ds.get());
     KERNEL_CHECK();
-    dsyevd(ctx, q, W.get(), q, lam);
+    // Search space of this pass, in the scaled coordinates of F's columns:
+    // all of R^q, or, after a pass whose new columns were all kept, the
+    // directions that pass left unselected (Rest, q x nrest, orthonormal).
+    // The remainder E S then lies in span(Rest) up to rounding: the pass took
+    // out exactly span(E S W_sel), and E S = (E S W_sel) W_sel^T +
+    // (E S Rest) Rest^T.  The eigen-decomposition then has order nrest
+    // instead of q.
+    const bool reduced = have_rest;
+    const int nb = reduced ? nrest : q;
+    if (reduced && nb == 0) {
+      complete = true;
+      break;
+    }
+    double* Hm = W.get();
+    if (reduced) {
+      dgemm(ctx, false, false, q, nb, q, 1.0, W.get(), q, Rest.get(), q, 0.0, Tmp.get(), q);
+      dgemm(ctx, true, false, nb, nb, q, 1.0, Rest.get(), q, Tmp.get(), q, 0.0, Hred.get(), nb);
+      Hm = Hred.get();
+    }
+    dsyevd(ctx, nb, Hm, nb, lam);
     const double lmax = *std::max_element(lam.begin(), lam.end());
     const double thr = std::max(1e-11 * lmax, noise);
-    std::vector<int> sel;
+    std::vector<int> sel, rest;
     std::vector<double> isq;
-    for (int i = q - 1; i >= 0; --i)
+    for (int i = nb - 1; i >= 0; --i) {
       if (lam[i] > thr && out.k + (int)sel.size() < kcap) {
         sel.push_back(i);
         isq.push_back(1.0 / std::sqrt(lam[i]));
+      } else {
+        rest.push_back(i);
       }
+    }
     if (sel.empty()) {
       complete = true;
       break;
     }
     const int kk = (int)sel.size();
-    // B = S W_sel L_sel^{-1/2}
-    copy_cols<double, double>(ctx, q, kk, W.get(), q, B.get(), q, sel.data(), isq.data());
+    // the next search space and B = S W_sel L_sel^{-1/2}, with W_sel the
+    // selected eigenvectors in R^q (Rest times those of the reduced matrix)
+    const int nr = (int)rest.size();
+    if (reduced) {
+      copy_cols<double, double>(ctx, nb, kk, Hm, nb, Tmp.get(), nb, sel.data(), isq.data());
+      dgemm(ctx, false, false, q, kk, nb, 1.0, Rest.get(), q, Tmp.get(), nb, 0.0, B.get(), q);
+      if (nr > 0) {
+        copy_cols<double, double>(ctx, nb, nr, Hm, nb, Tmp.get(), nb, rest.data());
+        dgemm(ctx, false, false, q, nr, nb, 1.0, Rest.get(), q, Tmp.get(), nb, 0.0, RestNext.get(), q);
+      }
+    } else {
+      copy_cols<double, double>(ctx, q, kk, W.get(), q, B.get(), q, sel.data(), isq.data());
+      if (nr > 0) copy_cols<double, double>(ctx, q, nr, W.get(), q, RestNext.get(), q, rest.data());
+    }
     dim3 gr(ceil_div(q, 64), kk);
     hipLaunchKernelGGL(k_scale_rows, gr, dim3(64), 0, ctx->stream, B.get(), (int64_t)q, q, kk, ds.get());
     KERNEL_CHECK();
@@ -690,15 +735,21 @@ void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out
       }
     }
     if (trace)
-      std::fprintf(stderr, "[rr_orth] n %lld q %d pass %d lmax %.3e thr %.3e new %d\n", (long long)n, q, pass, lmax,
-                   thr, kk);
+      std::fprintf(stderr, "[rr_orth] n %lld q %d pass %d search %d lmax %.3e thr %.3e new %d\n", (long long)n, q,
+                   pass, nb, lmax, thr, kk);
     const int kept = polish(ctx, n, Unew, ld, kk, trace);
     if (kept == 0) {
       complete = true;      // what is left projects to noise (polish dropped it)
       break;
     }
+    // a polish that dropped columns leaves part of span(E S W_sel) in the
+    // remainder: the next pass searches all of R^q again
+    have_rest = kept == kk;
+    nrest = nr;
+    if (have_rest) std::swap(Rest, RestNext);
+    const int kold = out.k;
     out.k += kept;
-    project();
+    project_block(kold, out.k);
     if (out.k >= kcap) {
       complete = true;      // the basis spans [U0, F]
       break;
@@ -710,6 +761,7 @@ void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out
     fail(CARE_ERR_BREAKDOWN, "rank-revealing orthogonalisation left a remainder above the noise level after " +
                                  std::to_string(max_passes) + " passes");
   if (out.k == 0) return;
+  copy_cols<double, double>(ctx, out.k, q, Tacc.get(), kcap, out.T.get(), out.k);
   ctx->sync();
 }
 

@@ -51,10 +51,9 @@ void residual_factor(Ctx* ctx, const SellOp& A64, const double* B, int m, const 
   out.res_fro = 0.0;
   if (q == 0) return;
   DBuf<double> F(ctx, (size_t)ld * q);
-  for (int j = 0; j < r; ++j) d2d(ctx, F.get() + (int64_t)j * ld, Z + (int64_t)j * ldz, n * sizeof(double));
+  if (r > 0) copy_cols<double, double>(ctx, n, r, Z, ldz, F.get(), ld);
   if (r > 0) spmm_plain(ctx, A64, 0.0, 0.0, Z, ldz, r, F.get() + (int64_t)r * ld, ld);
-  for (int j = 0; j < p; ++j)
-    d2d(ctx, F.get() + (int64_t)(2 * r + j) * ld, Ct + (int64_t)j * ld, n * sizeof(double));
+  if (p > 0) copy_cols<double, double>(ctx, n, p, Ct, ld, F.get() + (int64_t)(2 * r) * ld, ld);
 
   // M'
   std::vector<double> Mh((size_t)q * q, 0.0);
