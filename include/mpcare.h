@@ -123,7 +123,9 @@ typedef struct {
   int32_t penzl_l0;       /* auto shifts: number of shifts (16)                       */
   int32_t penzl_kp;       /* auto shifts: Arnoldi steps on A^T (20)                   */
   int32_t penzl_km;       /* auto shifts: Arnoldi steps on A^-T (10)                  */
-  int32_t profile;        /* 1: time every sparse-product launch with HIP events      */
+  int32_t profile;        /* 1: time every sparse-product launch with HIP events that
+                             the launch records at the kernel's start and end
+                             (care_stats.t_spmm); graph replay is then off         */
   const double* Z_init;   /* optional FP64 start factor Z_1 (device, n x r_init);
                              skips the initial NLR-ADI solve (resume)               */
   int64_t ldz_init;

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstdio>
 
+#include <hip/hip_ext.h>
 #include <hipcub/hipcub.hpp>
 
 namespace mpcare {
@@ -285,14 +286,28 @@ void build_sell(Ctx* ctx, const care_csr* A, Prec prec, SellOp& op) {
 // ---------------------------------------------------------------------------
 // launcher
 // ---------------------------------------------------------------------------
+// Launch target of the sparse products: the stream and, in profile mode, the
+// events the kernel records at its own start and end (hipExtLaunchKernelGGL:
+// the timestamps are the kernel's, without the gaps between launches).
+struct LaunchAt {
+  hipStream_t st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+template <typename K, typename T>
+static void launch_one(K kernel, const LaunchAt& at, dim3 g, const SpmmArgs<T>& a) {
+  if (at.e0) hipExtLaunchKernelGGL(kernel, g, dim3(256), 0, at.st, at.e0, at.e1, 0, a);
+  else hipLaunchKernelGGL(kernel, g, dim3(256), 0, at.st, a);
+}
+
 template <typename TV, typename T, int CP, bool CPLX, int WMAX>
-static void launch_mode(hipStream_t st, dim3 g, int mode, const SpmmArgs<T>& a) {
-  if (mode == MODE_PLAIN) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_PLAIN, CPLX, WMAX>), g, dim3(256), 0, st, a);
-  else if (mode == MODE_DOT1) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_DOT1, CPLX, WMAX>), g, dim3(256), 0, st, a);
-  else if (mode == MODE_DOT2) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_DOT2, CPLX, WMAX>), g, dim3(256), 0, st, a);
+static void launch_mode(const LaunchAt& at, dim3 g, int mode, const SpmmArgs<T>& a) {
+  if (mode == MODE_PLAIN) launch_one(k_spmm<TV, T, CP, MODE_PLAIN, CPLX, WMAX>, at, g, a);
+  else if (mode == MODE_DOT1) launch_one(k_spmm<TV, T, CP, MODE_DOT1, CPLX, WMAX>, at, g, a);
+  else if (mode == MODE_DOT2) launch_one(k_spmm<TV, T, CP, MODE_DOT2, CPLX, WMAX>, at, g, a);
   // the fused BiCGStab modes stream their entries (one panel per workgroup)
-  else if (mode == MODE_BICG_P) hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_P, CPLX, 0>), g, dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((k_spmm<TV, T, CP, MODE_BICG_S, CPLX, 0>), g, dim3(256), 0, st, a);
+  else if (mode == MODE_BICG_P) launch_one(k_spmm<TV, T, CP, MODE_BICG_P, CPLX, 0>, at, g, a);
+  else launch_one(k_spmm<TV, T, CP, MODE_BICG_S, CPLX, 0>, at, g, a);
 }
 
 // Row-width class: rows of at most 4 entries are preloaded at every panel
@@ -300,21 +315,21 @@ static void launch_mode(hipStream_t st, dim3 g, int mode, const SpmmArgs<T>& a) 
 // panels then hold 8 x panel gathers in flight per thread and the register
 // cost (one or two waves per SIMD) outweighs the shorter load chain.
 template <typename TV, typename T, int CP, bool CPLX>
-static void launch_w(hipStream_t st, dim3 g, int mode, int wmax, const SpmmArgs<T>& a) {
-  if (wmax == 4) launch_mode<TV, T, CP, CPLX, 4>(st, g, mode, a);
-  else if (wmax == 8 && CP <= 4) launch_mode<TV, T, CP, CPLX, (CP <= 4 ? 8 : 0)>(st, g, mode, a);
-  else launch_mode<TV, T, CP, CPLX, 0>(st, g, mode, a);
+static void launch_w(const LaunchAt& at, dim3 g, int mode, int wmax, const SpmmArgs<T>& a) {
+  if (wmax == 4) launch_mode<TV, T, CP, CPLX, 4>(at, g, mode, a);
+  else if (wmax == 8 && CP <= 4) launch_mode<TV, T, CP, CPLX, (CP <= 4 ? 8 : 0)>(at, g, mode, a);
+  else launch_mode<TV, T, CP, CPLX, 0>(at, g, mode, a);
 }
 
 template <typename TV, typename T, int CP>
-static void launch_cp(hipStream_t st, dim3 g, int mode, bool cplx, int wmax, const SpmmArgs<T>& a) {
+static void launch_cp(const LaunchAt& at, dim3 g, int mode, bool cplx, int wmax, const SpmmArgs<T>& a) {
   if constexpr (CP >= 2) {
     if (cplx) {
-      launch_w<TV, T, CP, true>(st, g, mode, wmax, a);
+      launch_w<TV, T, CP, true>(at, g, mode, wmax, a);
       return;
     }
   }
-  launch_w<TV, T, CP, false>(st, g, mode, wmax, a);
+  launch_w<TV, T, CP, false>(at, g, mode, wmax, a);
 }
 
 static int default_cp(int k, bool cplx) {
@@ -335,17 +350,18 @@ static int panels_per_block(int64_t nrb, int panels, int mode, int force) {
 }
 
 template <typename TV, typename T>
-static void launch_tv(hipStream_t st, int64_t n, int mode, bool cplx, SpmmArgs<T> a, int cp, int wmax, int force_pg) {
+static void launch_tv(const LaunchAt& at, int64_t n, int mode, bool cplx, SpmmArgs<T> a, int cp, int wmax,
+                      int force_pg) {
   const int k = a.ncols;
   const int panels = ceil_div(k, cp);
   a.pg = panels_per_block(spmm_rowblocks(n), panels, mode, force_pg);
   dim3 g(spmm_rowblocks(n), ceil_div(panels, a.pg));
   switch (cp) {
-    case 1: launch_cp<TV, T, 1>(st, g, mode, cplx, wmax, a); break;
-    case 2: launch_cp<TV, T, 2>(st, g, mode, cplx, wmax, a); break;
-    case 4: launch_cp<TV, T, 4>(st, g, mode, cplx, wmax, a); break;
-    case 8: launch_cp<TV, T, 8>(st, g, mode, cplx, wmax, a); break;
-    default: launch_cp<TV, T, 16>(st, g, mode, cplx, wmax, a); break;
+    case 1: launch_cp<TV, T, 1>(at, g, mode, cplx, wmax, a); break;
+    case 2: launch_cp<TV, T, 2>(at, g, mode, cplx, wmax, a); break;
+    case 4: launch_cp<TV, T, 4>(at, g, mode, cplx, wmax, a); break;
+    case 8: launch_cp<TV, T, 8>(at, g, mode, cplx, wmax, a); break;
+    default: launch_cp<TV, T, 16>(at, g, mode, cplx, wmax, a); break;
   }
 }
 
@@ -353,13 +369,17 @@ template <typename T>
 static void launch_prec(Ctx* ctx, const SellOp& op, int mode, bool cplx, const SpmmArgs<T>& a, int cp) {
   const int wmax = op.max_width <= 4 ? 4 : (op.max_width <= 8 ? 8 : 0);
   const int fpg = ctx->spmm_force_pg;
+  LaunchAt at;
+  at.st = ctx->stream;
+  at.e0 = ctx->spmm_ev0;
+  at.e1 = ctx->spmm_ev1;
   if constexpr (sizeof(T) == 8) {
     if (op.prec != Prec::F64) fail(CARE_ERR_ARG, "FP64 vectors need the FP64 operator");
-    launch_tv<double, double>(ctx->stream, op.n, mode, cplx, a, cp, wmax, fpg);
+    launch_tv<double, double>(at, op.n, mode, cplx, a, cp, wmax, fpg);
   } else {
-    if (op.prec == Prec::F32) launch_tv<float, float>(ctx->stream, op.n, mode, cplx, a, cp, wmax, fpg);
-    else if (op.prec == Prec::BF16) launch_tv<bf16, float>(ctx->stream, op.n, mode, cplx, a, cp, wmax, fpg);
-    else launch_tv<f16, float>(ctx->stream, op.n, mode, cplx, a, cp, wmax, fpg);
+    if (op.prec == Prec::F32) launch_tv<float, float>(at, op.n, mode, cplx, a, cp, wmax, fpg);
+    else if (op.prec == Prec::BF16) launch_tv<bf16, float>(at, op.n, mode, cplx, a, cp, wmax, fpg);
+    else launch_tv<f16, float>(at, op.n, mode, cplx, a, cp, wmax, fpg);
   }
   KERNEL_CHECK();
 }
@@ -433,14 +453,16 @@ SpmmTimer::SpmmTimer(Ctx* c, const SellOp& op, int k_real, int mode) : ctx(c) {
   if (ctx->spmm_defer && mode >= 0 && mode < 5) ctx->spmm_pending[mode] += 1;
   else ctx->spmm_bytes += op.bytes(k_real, spmm_vec_passes(mode));
   if (ctx->profile) {
+    // recorded by the launch itself, at the kernel's start and end
     ev = ctx->event_pair();
-    HIP_CHECK(hipEventRecord(ev.first, ctx->stream));
+    ctx->spmm_ev0 = ev.first;
+    ctx->spmm_ev1 = ev.second;
   }
 }
 
 SpmmTimer::~SpmmTimer() {
   if (ctx->profile && ev.first) {
-    (void)hipEventRecord(ev.second, ctx->stream);
+    ctx->spmm_ev0 = ctx->spmm_ev1 = nullptr;
     ctx->pending_events.push_back(ev);
   }
 }
