@@ -63,7 +63,7 @@ def test_golden_shift_set_has_conjugate_pairs():
 
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("prec,tol,xgate", [("fp32", 1e-10, False), ("fp32", 1e-12, True),
-                                            ("bf16", 1e-10, False)])
+                                            ("bf16", 1e-10, False), ("fp16", 1e-10, False)])
 def test_config3_vs_oracle(pk, ctx, prob, prec, tol, xgate):
     P = prob
     shifts = np.array(GOLDEN["shifts"]["re"]) + 1j * np.array(GOLDEN["shifts"]["im"])
