@@ -120,7 +120,10 @@ def test_dense_batch_fp32_inner_matches_oracle_where_fp32_suffices(pk, ctx):
             # kappa_2(A) <= 10^6.5: both precisions reach tol 1e-10
             assert st == 0, (g["i"], q)
         if q < 8.0:
-            # kappa_2(A) < 1e8: FP32 corrections still contract (Theorem 1)
-            assert st in (0, 1) and reached_oracle_level(s, g), (g["i"], q, st, s["res_rel"], g["relres"])
+            # kappa_2(A) < 1e8: FP32 corrections still contract (Theorem 1),
+            # ever more slowly towards kappa u_32 ~ 1, so the refinement may
+            # end on stagnation or on its step cap (status 1 or 2); either way
+            # at the oracle's residual level and with X matching the oracle
+            assert st in (0, 1, 2) and reached_oracle_level(s, g), (g["i"], q, st, s["res_rel"], g["relres"])
             assert max(eb, es) <= 1e-8, (g["i"], q, eb, es)
     print(f"fp32 inner: {ok} of {len(qs)} instances converged", flush=True)

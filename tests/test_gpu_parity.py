@@ -316,3 +316,22 @@ def test_care_solve_fdm_vs_oracle(ctx, pk, prec, split):
     # closed-loop stability of A - B B^T X
     Acl = P.A.toarray() - P.B @ ((P.B.T @ Z) @ Z.T)
     assert np.linalg.eigvals(Acl).real.max() < 0
+
+
+def test_spmm_fp16_entries_over_nine_decades(ctx, pk):
+    # entries from 1e-3 to 1e6 in one operator: the power-of-two scale keeps
+    # the largest within half's range, the smallest fall to half's subnormal
+    # range, where they carry little weight in any row's sum
+    rng = np.random.default_rng(23)
+    n = 3000
+    A = sp.random(n, n, density=0.003, random_state=np.random.RandomState(4), format="csr")
+    A.data = np.sign(rng.standard_normal(A.nnz)) * 10.0 ** rng.uniform(-3.0, 6.0, A.nnz)
+    A = (A - 2e6 * sp.identity(n)).tocsr()
+    X = rng.standard_normal((n, 6))
+    Y = host(pk.spmm(ctx, pk.DeviceCSR.from_scipy(A), dev(X), -5.0, "fp16"))
+    ref = A.T @ X - 5.0 * X
+    scale = abs(A.T) @ abs(X) + 5.0 * abs(X)
+    assert np.all(np.isfinite(Y))
+    assert np.abs(Y - ref).max() <= 2e-3 * scale.max()
+    # row by row: each within half's relative accuracy of its own magnitude sum
+    assert np.all(np.abs(Y - ref) <= 2e-3 * scale + 1e-12)
