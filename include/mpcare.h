@@ -323,6 +323,33 @@ care_status care_shifted_solve(care_ctx* ctx, const care_csr* A, const double* B
                                const double* W, int64_t ldw, int32_t w, int32_t prec,
                                double tol, int32_t maxit, double* V, int64_t ldv, int32_t* iters);
 
+/* Batched LU factorisation with partial pivoting of M_s = M0 + p_s I,
+ * s < nshifts: the direct shifted solves of the dense problems (Sec. 5.1
+ * solves its dense examples with LU; under the Sherman-Morrison-Woodbury form
+ * of Sec. 4 the factors of A^T + p I serve every Newton step).  One launch,
+ * one workgroup per matrix, matrix-core updates.  prec: CARE_FP32 or
+ * CARE_FP64, the element type of M0 and F.  M0: device, n x n column-major,
+ * leading dimension n.  shifts: HOST, real, rounded to prec before they are
+ * added to the diagonal.  F: device, nshifts consecutive n x n matrices
+ * (leading dimension n, not overlapping M0) receiving the LAPACK getrf layout
+ * (unit lower L strictly below the diagonal, U on and above it).  perm:
+ * device, nshifts x n int32 with (P M_s)[i] = M_s[perm[s n + i]] (the row
+ * exchanges composed).  info: HOST, nshifts entries: 0, or the 1-based index
+ * of the first zero pivot (the factorisation still completes, as getrf's).
+ * 1 <= n <= 2048.  Errors: CARE_ERR_ARG. */
+care_status care_shifted_lu_factor(care_ctx* ctx, int32_t prec, int64_t n, const void* M0, const double* shifts,
+                                   int32_t nshifts, void* F, int32_t* perm, int32_t* info);
+
+/* X = M_s^{-1} B with one matrix's factors from care_shifted_lu_factor
+ * (F: n x n, perm: n entries, both device): the permuted right-hand sides,
+ * then the unit lower and the upper triangular solves, in prec (CARE_FP32 or
+ * CARE_FP64, the element type of F, B and X).  B, X: device, n x k column-
+ * major (ldb, ldx >= n); X may be B (same leading dimension).  One workgroup
+ * per 4 (FP32) or 2 (FP64) columns.  1 <= n <= 2048, k >= 0.  Errors:
+ * CARE_ERR_ARG. */
+care_status care_shifted_lu_solve(care_ctx* ctx, int32_t prec, int64_t n, const void* F, const int32_t* perm,
+                                  int32_t k, const void* B, int64_t ldb, void* X, int64_t ldx);
+
 /* Gram product C = X^T Y of tall-skinny FP64 panels (FP64 matrix cores:
  * rocBLAS dgemm over row chunks for a * b >= 1024, the library's own MFMA
  * kernel below), the Gram step of the thin QR of F in Algorithm 1 and of G in
@@ -447,8 +474,10 @@ care_status care_solve_batch(care_ctx* ctx, int32_t count, const care_instance* 
 /* care_solve for a dense A (device, n x n column-major, leading dimension
  * lda >= n), e.g. the dense test CAREs of Sec. 5.1.  The shifted solves
  * factor A^T + p I once per real shift (partially pivoted LU in the inner
- * precision, rocSOLVER getrf) and reuse the factors for every right-hand
- * side block; products with A^T are GEMMs.  Real shifts only
+ * precision: for n <= 2048 every shift of a set in one launch of
+ * care_shifted_lu_factor's kernel, solved by care_shifted_lu_solve's; beyond,
+ * rocSOLVER getrf / getrs) and reuse the factors for every right-hand side
+ * block; products with A^T are GEMMs.  Real shifts only
  * (CARE_ERR_NOT_IMPLEMENTED for complex ones) and inner precision FP64 or
  * FP32.  Other arguments, outputs and statuses as care_solve. */
 care_status care_solve_dense(care_ctx* ctx, const double* A, int64_t n, int64_t lda, const double* B, int32_t m,

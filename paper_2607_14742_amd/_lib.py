@@ -109,6 +109,8 @@ SIGNATURES = {
                                C.POINTER(care_instance_result)]),
     "care_projection_shifts": (I32, [P, C.POINTER(care_csr), P, P, I32, P, I64, I32, I32, I32,
                                      C.POINTER(care_shift), PI32]),
+    "care_shifted_lu_factor": (I32, [P, I32, I64, P, PDBL, I32, P, P, PI32]),
+    "care_shifted_lu_solve": (I32, [P, I32, I64, P, P, I32, P, I64, P, I64]),
     "care_ritz_values": (I32, [PDBL, I32, I64, PDBL, PDBL]),
     "care_penzl_select": (I32, [PDBL, PDBL, I32, I32, C.POINTER(care_shift), PI32]),
 }

@@ -428,3 +428,41 @@ def penzl_select(candidates, l0):
     _check(_lib().care_penzl_select(re.ctypes.data_as(dp), im.ctypes.data_as(dp), R.size, l0, out,
                                     C.byref(cnt)))
     return np.array([complex(out[i].re, out[i].im) for i in range(cnt.value)])
+
+
+def shifted_lu_factor(ctx, M0, shifts, prec="fp32"):
+    """LU with partial pivoting of M0 + p I for every real p in `shifts`, one
+    launch.  M0: n x n on the GPU (cast to prec's type, column-major).
+    Returns (F, perm, info): F (nshifts, n, n) holding each factor column-major
+    (F[s].T is the n x n matrix of factors in row-major torch indexing), perm
+    (nshifts, n) int32 with (P M)[i] = M[perm[i]], and info, a list of 0 or
+    the 1-based first zero pivot."""
+    code = PREC[prec]
+    if code not in (L.CARE_FP32, L.CARE_FP64):
+        raise ValueError("prec must be fp32 or fp64")
+    dt = torch.float32 if code == L.CARE_FP32 else torch.float64
+    n = int(M0.shape[0])
+    Mc = colmajor(M0.to(dt))
+    if _ld(Mc) != n:
+        Mc = Mc.t().contiguous().t()
+    sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64).reshape(-1))
+    ns = int(sh.size)
+    F = torch.empty((max(ns, 1), n, n), device=M0.device, dtype=dt)
+    perm = torch.empty((max(ns, 1), n), device=M0.device, dtype=torch.int32)
+    info = (C.c_int32 * max(ns, 1))()
+    _check(_lib().care_shifted_lu_factor(ctx.h, code, n, _ptr(Mc), sh.ctypes.data_as(C.POINTER(C.c_double)), ns,
+                                         _ptr(F), _ptr(perm), info))
+    return F[:ns], perm[:ns], [int(info[i]) for i in range(ns)]
+
+
+def shifted_lu_solve(ctx, F, perm, Bm, prec="fp32"):
+    """X = M^{-1} B with one factor F (n x n storage as returned in
+    shifted_lu_factor's F[s]) and its perm; B: n x k on the GPU."""
+    code = PREC[prec]
+    dt = torch.float32 if code == L.CARE_FP32 else torch.float64
+    n = int(F.shape[-1])
+    Bc = colmajor(Bm.to(dt))
+    X = empty_colmajor(n, Bc.shape[1], Bm.device, dtype=dt)
+    _check(_lib().care_shifted_lu_solve(ctx.h, code, n, _ptr(F), _ptr(perm), Bc.shape[1], _ptr(Bc), _ld(Bc),
+                                        _ptr(X), _ld(X)))
+    return X

@@ -3,6 +3,7 @@
 #include <cstring>
 
 #include "care.hpp"
+#include "lu.hpp"
 
 using namespace mpcare;
 
@@ -223,6 +224,59 @@ care_status care_spmm_timing(care_ctx* cx, const care_csr* A, int32_t prec, care
     ctx->spmm_force_pg = 0;
     *us_per_product = 1e3 * (double)ms / ((double)reps * nsets);
     *bytes_per_product = ops[0].bytes(kr, 2);
+    ctx->sync();
+    return CARE_OK;
+  });
+}
+
+care_status care_shifted_lu_factor(care_ctx* cx, int32_t prec, int64_t n, const void* M0, const double* shifts,
+                                   int32_t nshifts, void* F, int32_t* perm, int32_t* info) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    if (prec != CARE_FP32 && prec != CARE_FP64) fail(CARE_ERR_ARG, "prec must be CARE_FP32 or CARE_FP64");
+    if (n < 1 || n > LU_NMAX) fail(CARE_ERR_ARG, "n must be in [1, " + std::to_string(LU_NMAX) + "]");
+    if (nshifts < 0) fail(CARE_ERR_ARG, "nshifts must be >= 0");
+    if (nshifts == 0) return CARE_OK;
+    if (!M0 || !shifts || !F || !perm || !info) fail(CARE_ERR_ARG, "NULL argument");
+    const size_t es = prec == CARE_FP32 ? 4 : 8;
+    const size_t mat = (size_t)n * n * es;
+    const char* f0 = (const char*)F;
+    const char* m0 = (const char*)M0;
+    if (f0 < m0 + mat && m0 < f0 + mat * nshifts) fail(CARE_ERR_ARG, "F overlaps M0");
+    std::vector<double> sh(shifts, shifts + nshifts);
+    for (double v : sh)
+      if (!std::isfinite(v)) fail(CARE_ERR_ARG, "shift not finite");
+    std::vector<int*> P(nshifts);
+    for (int s = 0; s < nshifts; ++s) P[s] = perm + (int64_t)s * n;
+    std::vector<int> inf;
+    if (prec == CARE_FP32) {
+      std::vector<float*> Fs(nshifts);
+      for (int s = 0; s < nshifts; ++s) Fs[s] = (float*)F + (int64_t)s * n * n;
+      lu_factor_shifted<float>(ctx, (int)n, (const float*)M0, sh, Fs, P, inf);
+    } else {
+      std::vector<double*> Fs(nshifts);
+      for (int s = 0; s < nshifts; ++s) Fs[s] = (double*)F + (int64_t)s * n * n;
+      lu_factor_shifted<double>(ctx, (int)n, (const double*)M0, sh, Fs, P, inf);
+    }
+    for (int s = 0; s < nshifts; ++s) info[s] = inf[s];
+    return CARE_OK;
+  });
+}
+
+care_status care_shifted_lu_solve(care_ctx* cx, int32_t prec, int64_t n, const void* F, const int32_t* perm,
+                                  int32_t k, const void* B, int64_t ldb, void* X, int64_t ldx) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    if (prec != CARE_FP32 && prec != CARE_FP64) fail(CARE_ERR_ARG, "prec must be CARE_FP32 or CARE_FP64");
+    if (n < 1 || n > LU_NMAX) fail(CARE_ERR_ARG, "n must be in [1, " + std::to_string(LU_NMAX) + "]");
+    if (k < 0) fail(CARE_ERR_ARG, "k must be >= 0");
+    if (k == 0) return CARE_OK;
+    if (!F || !perm || !B || !X || ldb < n || ldx < n) fail(CARE_ERR_ARG, "invalid F / perm / B / X");
+    if (B == X && ldb != ldx) fail(CARE_ERR_ARG, "in-place solve needs ldx == ldb");
+    if (prec == CARE_FP32)
+      lu_solve<float>(ctx, (int)n, (const float*)F, perm, k, (const float*)B, ldb, (float*)X, ldx);
+    else
+      lu_solve<double>(ctx, (int)n, (const double*)F, perm, k, (const double*)B, ldb, (double*)X, ldx);
     ctx->sync();
     return CARE_OK;
   });

@@ -265,6 +265,15 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
   // columns).  A projection without a stable Ritz value keeps the set.
   std::vector<Shift> cur = shifts;
   if (cur.empty()) cur = projection_shifts<T>(ctx, op, B, smw ? K : nullptr, m, W, ld, w, prm.proj_shifts);
+  // a dense operator factors A^T + p I for the whole set in one launch
+  auto prefactor = [&]() {
+    if (!op.dense) return;
+    std::vector<double> re;
+    for (const Shift& q : cur)
+      if (q.im == 0.0) re.push_back(q.re);
+    dense_prefactor(ctx, op, re);
+  };
+  prefactor();
   std::vector<int> step_col;   // first column of Z written by each step
 
   const int maxcols = smw ? w + m : w;
@@ -304,6 +313,7 @@ LradiOut lradi_run(Ctx* ctx, const SellOp& op, const T* B, const T* K, int m, T*
         cur = std::move(next);
         std::vector<ShiftCache> fresh(cur.size());
         cache.swap(fresh);
+        prefactor();
       } catch (const CareError& e) {
         if (e.status != CARE_ERR_UNSTABLE) throw;
       }

@@ -1,10 +1,12 @@
 // Dense operator for the dense CARE instances: A^T stored as an n x n
 // column-major matrix in the inner precision.  Products y = (A^T + p I) x
 // are rocBLAS GEMMs (MFMA) plus a shift; shifted solves factor A^T + p I
-// once per real shift with a partially pivoted LU (rocSOLVER getrf, FP32 for
-// the FP32 inner precision) and reuse the factors for every right-hand side
-// block of every Newton step, since with the SMW form the base matrix does
-// not change (Sec. 4).
+// once per real shift with a partially pivoted LU in the inner precision and
+// reuse the factors for every right-hand side block of every Newton step,
+// since with the SMW form the base matrix does not change (Sec. 4).  Up to
+// order LU_NMAX the factorisations of a whole shift set are one launch of the
+// hand-written batched LU (lu.hip) and the solves its triangular-solve
+// kernel; larger orders use rocSOLVER getrf / getrs per shift.
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
@@ -13,6 +15,7 @@
 
 #include "dense.hpp"
 #include "krylov.hpp"
+#include "lu.hpp"
 
 namespace mpcare {
 
@@ -123,20 +126,39 @@ static rocblas_status getrs(rocblas_handle h, int n, int k, float* a, const int*
   return rocsolver_sgetrs(h, rocblas_operation_none, n, k, a, n, ipiv, x, ldx);
 }
 
+// Factor A^T + p I for every listed real shift not factored yet: one launch
+// of the batched LU for all of them (orders up to LU_NMAX), else rocSOLVER
+// getrf per shift.
 template <typename T>
-KrylovResult dense_solve(Ctx* ctx, const SellOp& op, double pr, double pi, int ncols, const T* b, int64_t ldb, T* x,
-                         int64_t ldx) {
-  KrylovResult res;
-  if (ncols <= 0) return res;
-  if (pi != 0.0) fail(CARE_ERR_NOT_IMPLEMENTED, "complex shifts with a dense operator");
-  if ((op.prec == Prec::F64) != (sizeof(T) == 8)) fail(CARE_ERR_ARG, "dense solve precision mismatch");
+static void factor_shifts(Ctx* ctx, const SellOp& op, const std::vector<double>& want) {
   const int n = (int)op.n;
-  std::shared_ptr<SellOp::DenseLU> f;
-  auto it = op.lu.find(pr);
-  if (it != op.lu.end()) {
-    f = it->second;
-  } else {
-    f = std::make_shared<SellOp::DenseLU>();
+  std::vector<double> todo;
+  for (double p : want)
+    if (op.lu.find(p) == op.lu.end() && std::find(todo.begin(), todo.end(), p) == todo.end()) todo.push_back(p);
+  if (todo.empty()) return;
+  if (n <= LU_NMAX) {
+    std::vector<std::shared_ptr<SellOp::DenseLU>> fs;
+    std::vector<T*> F;
+    std::vector<int*> P;
+    for (size_t s = 0; s < todo.size(); ++s) {
+      auto f = std::make_shared<SellOp::DenseLU>();
+      f->a.resize(ctx, (size_t)n * n * sizeof(T));
+      f->perm.resize(ctx, n);
+      f->own = true;
+      F.push_back((T*)f->a.get());
+      P.push_back(f->perm.get());
+      fs.push_back(f);
+    }
+    std::vector<int> info;
+    lu_factor_shifted<T>(ctx, n, (const T*)op.dmat.get(), todo, F, P, info);
+    for (size_t s = 0; s < todo.size(); ++s) {
+      if (info[s] > 0) fail(CARE_ERR_BREAKDOWN, "A^T + p I is singular in the inner precision");
+      op.lu[todo[s]] = fs[s];
+    }
+    return;
+  }
+  for (double pr : todo) {
+    auto f = std::make_shared<SellOp::DenseLU>();
     f->a.resize(ctx, (size_t)n * n * sizeof(T));
     f->ipiv.resize(ctx, n);
     d2d(ctx, f->a.get(), op.dmat.get(), (size_t)n * n * sizeof(T));
@@ -151,8 +173,30 @@ KrylovResult dense_solve(Ctx* ctx, const SellOp& op, double pr, double pi, int n
     if (hinfo > 0) fail(CARE_ERR_BREAKDOWN, "A^T + p I is singular in the inner precision");
     op.lu[pr] = f;
   }
-  copy_cols<T, T>(ctx, n, ncols, b, ldb, x, ldx);
-  ROCBLAS_CHECK(getrs(ctx->blas, n, ncols, (T*)f->a.get(), f->ipiv.get(), x, (int)ldx));
+}
+
+void dense_prefactor(Ctx* ctx, const SellOp& op, const std::vector<double>& shifts) {
+  if (!op.dense) return;
+  if (op.prec == Prec::F64) factor_shifts<double>(ctx, op, shifts);
+  else factor_shifts<float>(ctx, op, shifts);
+}
+
+template <typename T>
+KrylovResult dense_solve(Ctx* ctx, const SellOp& op, double pr, double pi, int ncols, const T* b, int64_t ldb, T* x,
+                         int64_t ldx) {
+  KrylovResult res;
+  if (ncols <= 0) return res;
+  if (pi != 0.0) fail(CARE_ERR_NOT_IMPLEMENTED, "complex shifts with a dense operator");
+  if ((op.prec == Prec::F64) != (sizeof(T) == 8)) fail(CARE_ERR_ARG, "dense solve precision mismatch");
+  const int n = (int)op.n;
+  factor_shifts<T>(ctx, op, {pr});
+  const std::shared_ptr<SellOp::DenseLU>& f = op.lu.at(pr);
+  if (f->own) {
+    lu_solve<T>(ctx, n, (const T*)f->a.get(), f->perm.get(), ncols, b, ldb, x, ldx);
+  } else {
+    copy_cols<T, T>(ctx, n, ncols, b, ldb, x, ldx);
+    ROCBLAS_CHECK(getrs(ctx->blas, n, ncols, (T*)f->a.get(), f->ipiv.get(), x, (int)ldx));
+  }
   res.col_ok.assign(ncols, 1);
   res.col_relres.assign(ncols, 0.0);
   res.col_bnorm.assign(ncols, 0.0);

@@ -52,7 +52,9 @@ struct SellOp {
   DBuf<uint8_t> dmat;
   struct DenseLU {
     DBuf<uint8_t> a;               // LU factors, n x n
-    DBuf<int> ipiv;
+    DBuf<int> ipiv;                // rocSOLVER factors (n > LU_NMAX)
+    DBuf<int> perm;                // hand-written factors: (P M)[i] = M[perm[i]]
+    bool own = false;              // factors from lu_factor_shifted
   };
   mutable std::map<double, std::shared_ptr<DenseLU>> lu;
   // Red-black reduction of A^T + p I (rb.hip), present when A is two-colourable
@@ -103,6 +105,9 @@ void spmm_plain(Ctx* ctx, const SellOp& op, double pr, double pi, const void* X,
 // (device, leading dimension lda) in precision prec (FP64 or FP32), and
 // Y = (A^T + p I) X by GEMM (real p only).
 void build_dense(Ctx* ctx, const double* A, int64_t lda, int64_t n, Prec prec, SellOp& op);
+// Factor A^T + p I of a dense operator for every listed real shift not
+// factored yet (one launch of the batched LU for orders up to LU_NMAX).
+void dense_prefactor(Ctx* ctx, const SellOp& op, const std::vector<double>& shifts);
 void dense_apply(Ctx* ctx, const SellOp& op, double pr, double pi, const void* X, int64_t ldx, int k, void* Y,
                  int64_t ldy);
 
