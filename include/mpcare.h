@@ -345,7 +345,7 @@ care_status care_shifted_lu_factor(care_ctx* ctx, int32_t prec, int64_t n, const
  * then the unit lower and the upper triangular solves, in prec (CARE_FP32 or
  * CARE_FP64, the element type of F, B and X).  B, X: device, n x k column-
  * major (ldb, ldx >= n); X may be B (same leading dimension).  One workgroup
- * per 4 (FP32) or 2 (FP64) columns.  1 <= n <= 2048, k >= 0.  Errors:
+ * per 2 (FP32) or 1 (FP64) columns.  1 <= n <= 2048, k >= 0.  Errors:
  * CARE_ERR_ARG. */
 care_status care_shifted_lu_solve(care_ctx* ctx, int32_t prec, int64_t n, const void* F, const int32_t* perm,
                                   int32_t k, const void* B, int64_t ldb, void* X, int64_t ldx);

@@ -5,8 +5,9 @@
 // reuse the factors for every right-hand side block of every Newton step,
 // since with the SMW form the base matrix does not change (Sec. 4).  Up to
 // order LU_NMAX the factorisations of a whole shift set are one launch of the
-// hand-written batched LU (lu.hip) and the solves its triangular-solve
-// kernel; larger orders use rocSOLVER getrf / getrs per shift.
+// hand-written batched LU (lu.hip); its triangular-solve kernel serves orders
+// up to LU_OWN_SOLVE_MAX and rocSOLVER getrs (on the same factors) larger
+// ones; beyond LU_NMAX rocSOLVER getrf / getrs per shift.
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
@@ -140,17 +141,20 @@ static void factor_shifts(Ctx* ctx, const SellOp& op, const std::vector<double>&
     std::vector<std::shared_ptr<SellOp::DenseLU>> fs;
     std::vector<T*> F;
     std::vector<int*> P;
+    std::vector<int*> I;
     for (size_t s = 0; s < todo.size(); ++s) {
       auto f = std::make_shared<SellOp::DenseLU>();
       f->a.resize(ctx, (size_t)n * n * sizeof(T));
       f->perm.resize(ctx, n);
+      f->ipiv.resize(ctx, n);
       f->own = true;
       F.push_back((T*)f->a.get());
       P.push_back(f->perm.get());
+      I.push_back(f->ipiv.get());
       fs.push_back(f);
     }
     std::vector<int> info;
-    lu_factor_shifted<T>(ctx, n, (const T*)op.dmat.get(), todo, F, P, info);
+    lu_factor_shifted<T>(ctx, n, (const T*)op.dmat.get(), todo, F, P, info, I);
     for (size_t s = 0; s < todo.size(); ++s) {
       if (info[s] > 0) fail(CARE_ERR_BREAKDOWN, "A^T + p I is singular in the inner precision");
       op.lu[todo[s]] = fs[s];
@@ -191,7 +195,7 @@ KrylovResult dense_solve(Ctx* ctx, const SellOp& op, double pr, double pi, int n
   const int n = (int)op.n;
   factor_shifts<T>(ctx, op, {pr});
   const std::shared_ptr<SellOp::DenseLU>& f = op.lu.at(pr);
-  if (f->own) {
+  if (f->own && n <= LU_OWN_SOLVE_MAX) {
     lu_solve<T>(ctx, n, (const T*)f->a.get(), f->perm.get(), ncols, b, ldb, x, ldx);
   } else {
     copy_cols<T, T>(ctx, n, ncols, b, ldb, x, ldx);

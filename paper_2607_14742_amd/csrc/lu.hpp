@@ -16,10 +16,17 @@ constexpr int LU_NMAX = 2048;
 // matrix.  M0: device n x n column-major (ld n) in T; F[s]: device n x n (ld n,
 // not overlapping M0) receiving the LAPACK getrf layout; perm[s]: device n
 // ints with (P M_s)[i] = M_s[perm[s][i]]; info[s]: 0, or the 1-based index of
-// the first zero pivot.  The shift is rounded to T before it is added.
+// the first zero pivot; ipiv (optional, one device array of n ints per
+// shift): the row exchanges, 1-based as getrf's (for rocSOLVER getrs).  The
+// shift is rounded to T before it is added.
 template <typename T>
 void lu_factor_shifted(Ctx* ctx, int n, const T* M0, const std::vector<double>& shifts, const std::vector<T*>& F,
-                       const std::vector<int*>& perm, std::vector<int>& info);
+                       const std::vector<int*>& perm, std::vector<int>& info, const std::vector<int*>& ipiv = {});
+
+// Largest order at which the dense shifted solves use lu_solve; beyond it
+// rocSOLVER getrs on the same factors is faster (measured: FP32, k = 8..16,
+// 150 vs 180 us at n = 512, 354 vs 275 us at n = 1024).
+constexpr int LU_OWN_SOLVE_MAX = 512;
 
 // X = M^{-1} B for k columns with the factors of one matrix (B and X may be
 // the same storage with the same leading dimension).  Asynchronous on the

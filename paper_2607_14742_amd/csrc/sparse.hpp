@@ -52,7 +52,7 @@ struct SellOp {
   DBuf<uint8_t> dmat;
   struct DenseLU {
     DBuf<uint8_t> a;               // LU factors, n x n
-    DBuf<int> ipiv;                // rocSOLVER factors (n > LU_NMAX)
+    DBuf<int> ipiv;                // 1-based row exchanges (for getrs)
     DBuf<int> perm;                // hand-written factors: (P M)[i] = M[perm[i]]
     bool own = false;              // factors from lu_factor_shifted
   };

@@ -84,7 +84,7 @@ def test_lu_factor_backward_error_and_pivot_growth(pk, ctx, prec, n):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-@pytest.mark.parametrize("n,q", [(256, 2.0), (600, 3.0), (2048, 2.0)])
+@pytest.mark.parametrize("n,q", [(256, 2.0), (300, 2.0), (600, 3.0), (2048, 2.0)])
 def test_lu_solve_matches_oracle_shifted_solver(pk, ctx, prec, n, q):
     """(A^T + p I) X = W for the dense test family of Sec. 5.1
     (A = -Q diag(logspace(0, q, n)) Q^T), every shift of a logspaced set,
