@@ -156,8 +156,10 @@ typedef struct {
                              selects tau_L                                          */
   int32_t spmm_tune;      /* 1 (default): the first sparse product of each shape
                              (operator, precision, mode, column count rounded up to
-                             16) times 16- and 8-column panels and keeps the faster
-                             for the context's operator; 0: 16-column panels       */
+                             16) times 16- and 8-column panels, each with the
+                             default panel grouping or one panel per workgroup, and
+                             keeps the fastest for the context's operator; 0:
+                             16-column panels, default grouping                    */
   int32_t shift_update;   /* heuristic shifts only (nshifts = 0): 1 recomputes them
                              for every Lyapunov solve from its closed-loop operator
                              A - B K^T (Newton steps >= 1, corrections), the

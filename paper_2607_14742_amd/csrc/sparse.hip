@@ -366,9 +366,9 @@ static void launch_tv(const LaunchAt& at, int64_t n, int mode, bool cplx, SpmmAr
 }
 
 template <typename T>
-static void launch_prec(Ctx* ctx, const SellOp& op, int mode, bool cplx, const SpmmArgs<T>& a, int cp) {
+static void launch_prec(Ctx* ctx, const SellOp& op, int mode, bool cplx, const SpmmArgs<T>& a, int cp, int pg = 0) {
   const int wmax = op.max_width <= 4 ? 4 : (op.max_width <= 8 ? 8 : 0);
-  const int fpg = ctx->spmm_force_pg;
+  const int fpg = ctx->spmm_force_pg > 0 ? ctx->spmm_force_pg : pg;
   LaunchAt at;
   at.st = ctx->stream;
   at.e0 = ctx->spmm_ev0;
@@ -384,47 +384,77 @@ static void launch_prec(Ctx* ctx, const SellOp& op, int mode, bool cplx, const S
   KERNEL_CHECK();
 }
 
-// Panel-width autotuner.  A product of k > 8 columns runs in panels of 16 or
-// of 8 columns.  Wider panels read the matrix fewer times; narrower ones keep
-// fewer gathers in flight per thread and need fewer registers.  Which wins
+// Autotuner of the product's tile: panel width and panels per workgroup.  A
+// product of k > 8 columns runs in panels of 16 or of 8 columns, and a
+// workgroup runs one panel or a group of them over its row slice (the
+// matrix entries loaded once for the group).  Wider panels and larger groups
+// read the matrix fewer times; narrower panels keep fewer gathers in flight
+// per thread, and single panels give the grid more workgroups.  Which wins
 // depends on the matrix, the precision and k.  The first launch of a shape
-// (operator, precision, mode, real/complex, k rounded up to 16) runs both
-// widths twice with HIP events around each and keeps the faster for that
+// (operator, precision, mode, real/complex, k rounded up to 16) runs each
+// distinct candidate (16 or 8 columns; the default group or one panel per
+// workgroup) twice with HIP events around each and keeps the fastest for that
 // shape.  Only modes whose outputs every launch overwrites completely (plain
 // product, split BiCGStab products) are tuned: the extra launches then leave
-// the same results behind, since the panel width does not change any column's
+// the same results behind, since neither choice changes any column's
 // arithmetic.  Launches inside a stream capture use the stored choice or the
-// default.
+// default.  Returns the panel width; *pg receives the panels per workgroup
+// (0: the default rule).
 template <typename T>
-static int tuned_cp(Ctx* ctx, const SellOp& op, int mode, bool cplx, const SpmmArgs<T>& a) {
+static int tuned_cp(Ctx* ctx, const SellOp& op, int mode, bool cplx, const SpmmArgs<T>& a, int* pg) {
+  *pg = 0;
   const int k = a.ncols;
   const int cp0 = default_cp(k, cplx);
   if (cp0 == 16 && ctx->spmm_force_cp) return ctx->spmm_force_cp;
   if (!ctx->spmm_tune || cp0 != 16 || !(mode == MODE_PLAIN || mode == MODE_DOT1 || mode == MODE_DOT2)) return cp0;
   const int key = mode | (cplx ? 8 : 0) | (std::min((int)ceil_div(k, 16), 64) << 4) | (sizeof(T) == 8 ? 1 << 12 : 0);
   auto it = op.cp_choice.find(key);
-  if (it != op.cp_choice.end()) return it->second;
+  if (it != op.cp_choice.end()) {
+    *pg = it->second >> 8;
+    return it->second & 0xff;
+  }
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIP_CHECK(hipStreamIsCapturing(ctx->stream, &cs));
   if (cs != hipStreamCaptureStatusNone) return cp0;
-  hipEvent_t ev[5];
+  // distinct candidates (cp, pg); pg = 0 is the default rule
+  std::vector<std::pair<int, int>> cand;
+  for (int cp : {16, 8}) {
+    const int panels = ceil_div(k, cp);
+    const int dflt = panels_per_block(spmm_rowblocks(op.n), panels, mode, 0);
+    cand.push_back({cp, 0});
+    if (dflt > 1) cand.push_back({cp, 1});
+  }
+  const int nc = (int)cand.size();
+  std::vector<hipEvent_t> ev(2 * nc + 1);
   for (auto& e : ev) HIP_CHECK(hipEventCreate(&e));
-  const int cand[4] = {16, 8, 16, 8};
   HIP_CHECK(hipEventRecord(ev[0], ctx->stream));
-  for (int v = 0; v < 4; ++v) {
-    launch_prec<T>(ctx, op, mode, cplx, a, cand[v]);
+  for (int v = 0; v < 2 * nc; ++v) {
+    launch_prec<T>(ctx, op, mode, cplx, a, cand[v % nc].first, cand[v % nc].second);
     HIP_CHECK(hipEventRecord(ev[v + 1], ctx->stream));
   }
-  HIP_CHECK(hipEventSynchronize(ev[4]));
-  float t[4];
-  for (int v = 0; v < 4; ++v) HIP_CHECK(hipEventElapsedTime(&t[v], ev[v], ev[v + 1]));
+  HIP_CHECK(hipEventSynchronize(ev[2 * nc]));
+  std::vector<float> best(nc, INFINITY);
+  for (int v = 0; v < 2 * nc; ++v) {
+    float t = 0.0f;
+    HIP_CHECK(hipEventElapsedTime(&t, ev[v], ev[v + 1]));
+    best[v % nc] = std::min(best[v % nc], t);
+  }
   for (auto& e : ev) (void)hipEventDestroy(e);
-  const float t16 = std::min(t[0], t[2]), t8 = std::min(t[1], t[3]);
-  const int cp = t8 < 0.97f * t16 ? 8 : 16;
-  op.cp_choice[key] = cp;
-  if (std::getenv("MPCARE_TRACE"))
-    std::fprintf(stderr, "[spmm-tune] n %lld mode %d cplx %d k %d fp%d: 16 cols %.1f us, 8 cols %.1f us -> %d\n",
-                 (long long)op.n, mode, cplx ? 1 : 0, k, (int)(8 * sizeof(T)), 1e3f * t16, 1e3f * t8, cp);
+  // the default (16 columns, default groups) unless another is 3 % faster
+  int pick = 0;
+  for (int c = 1; c < nc; ++c)
+    if (best[c] < 0.97f * best[pick] && best[c] < best[0] * 0.97f) pick = c;
+  const int cp = cand[pick].first;
+  *pg = cand[pick].second;
+  op.cp_choice[key] = cp | (*pg << 8);
+  if (std::getenv("MPCARE_TRACE")) {
+    std::fprintf(stderr, "[spmm-tune] n %lld mode %d cplx %d k %d fp%d:", (long long)op.n, mode, cplx ? 1 : 0, k,
+                 (int)(8 * sizeof(T)));
+    for (int c = 0; c < nc; ++c)
+      std::fprintf(stderr, " %d cols/%s %.1f us", cand[c].first, cand[c].second ? "1 panel" : "default",
+                   1e3f * best[c]);
+    std::fprintf(stderr, " -> %d cols/%s\n", cp, *pg ? "1 panel" : "default");
+  }
   return cp;
 }
 
@@ -439,9 +469,10 @@ int launch_spmm(Ctx* ctx, const SellOp& op, int mode, bool cplx, SpmmArgs<T>& a)
   a.nrb = spmm_rowblocks(op.n);
   if (a.ncols <= 0) return a.nrb;
   if (cplx && (a.ncols % 2)) fail(CARE_ERR_ARG, "complex panel with an odd number of real columns");
-  const int cp = tuned_cp<T>(ctx, op, mode, cplx, a);
+  int pg = 0;
+  const int cp = tuned_cp<T>(ctx, op, mode, cplx, a, &pg);
   SpmmTimer timer(ctx, op, a.ncols, mode);
-  launch_prec<T>(ctx, op, mode, cplx, a, cp);
+  launch_prec<T>(ctx, op, mode, cplx, a, cp, pg);
   return a.nrb;
 }
 

@@ -119,8 +119,9 @@ def test_capacity_protocol(pk, ctx):
 
 
 def test_spmm_panel_autotuner_leaves_results_unchanged(pk, ctx):
-    # the tuner picks 16- or 8-column panels by timing; a column's arithmetic
-    # does not depend on the panel width, so a solve with and without it
+    # the tuner picks 16- or 8-column panels, and one or a group of panels per
+    # workgroup, by timing; a column's arithmetic depends on neither, so a
+    # solve with and without it
     # returns the same factor bit for bit (the solve is run-to-run
     # deterministic: fixed-order reductions, no atomics)
     P = wl.fdm2d_problem(60, 3, 4)
