@@ -352,10 +352,13 @@ care_status care_shifted_lu_factor(care_ctx* ctx, int32_t prec, int64_t n, const
 care_status care_shifted_lu_solve(care_ctx* ctx, int32_t prec, int64_t n, const void* F, const int32_t* perm,
                                   int32_t k, const void* B, int64_t ldb, void* X, int64_t ldx);
 
-/* Gram product C = X^T Y of tall-skinny FP64 panels (FP64 matrix cores:
- * rocBLAS dgemm over row chunks for a * b >= 1024, the library's own MFMA
- * kernel below), the Gram step of the thin QR of F in Algorithm 1 and of G in
- * Algorithm 2.  X: n x a (ldx >= n), Y: n x b (ldy >= n), C: a x b (ldc >= a).
+/* Gram product C = X^T Y of tall-skinny FP64 panels (FP64 matrix cores), the
+ * Gram step of the thin QR of F in Algorithm 1 and of G in Algorithm 2.  For
+ * a * b >= 1024: the library's own 128 x 128-tile MFMA kernel for X^T X (the
+ * tiles on and above the diagonal) up to 512 columns or 1.5 GB of X, rocBLAS
+ * dgemm over row chunks otherwise (environment variable MPCARE_GRAM, read at
+ * context creation: 0 always rocBLAS, 1 always the own kernel); smaller
+ * products use the library's 32 x 32-tile MFMA kernel.  X: n x a (ldx >= n), Y: n x b (ldy >= n), C: a x b (ldc >= a).
  * Partial products over row chunks are summed in a fixed order (run-to-run
  * reproducible); X == Y (same pointer and ld) gives an exactly symmetric C. */
 care_status care_gram(care_ctx* ctx, int64_t n, const double* X, int64_t ldx, int32_t a, const double* Y,

@@ -130,6 +130,8 @@ struct Ctx {
   int krylov_graphs = 1;            // 0: no HIP-graph capture of Krylov chunks (batch worker contexts)
   int krylov_rb = 1;                // 1: shifted solves through the red-black reduction where it applies
   int spmm_force_cp = 0;            // 8 / 16: panel width of every wide product (product timing), 0: chosen
+  int gram_impl = 2;                // large FP64 Grams: 0 rocBLAS dgemm, 1 the own 128 x 128-tile MFMA
+                                    // kernel, 2 the own kernel where measured faster (symmetric Grams)
   int spmm_force_pg = 0;            // > 0: column panels per workgroup (product timing), 0: chosen
   int krylov_compact = 1;           // BiCGStab: gather the still-active columns into fewer panels
   int krylov_restart = 0;           // GMRES restart length (0: 30 in FP32, 50 in FP64)

@@ -156,6 +156,170 @@ __global__ void k_sum_partials(int a, int b, int nsplit, const double* __restric
   C[(int64_t)j * ldc + i] = s;
 }
 
+// ---------------------------------------------------------------------------
+// Gram C = X^T Y in 128 x 128 output tiles (FP64)
+// ---------------------------------------------------------------------------
+// One workgroup (4 waves, 2 x 2) per output tile and row split; each wave
+// owns a 64 x 64 quarter as 4 x 4 MFMA tiles (16 accumulators).  Rows come
+// 16 at a time: the 16 x 128 slices of X and Y are staged in LDS (double
+// buffered; the next slices' global loads are issued before the current
+// slices' MFMAs), row k of the slice feeding MFMA step k / 4 from lane group
+// k % 4.  The tile's partial sum goes to part (column-major 128 x 128 per
+// tile and split) and k_gram128_reduce adds the splits in a fixed order.
+constexpr int G128_PITCH = 128 + 2;   // LDS row pitch (doubles)
+
+// Tile t of a ti x tj grid of 128 x 128 tiles, row by row; with sym only the
+// tiles on and above the diagonal (ti == tj) are enumerated.
+__device__ __forceinline__ void g128_tile(int t, int ti, int tj, int sym, int& I, int& J) {
+  if (!sym) {
+    I = t / tj;
+    J = t % tj;
+    return;
+  }
+  I = 0;
+  while (t >= ti - I) {
+    t -= ti - I;
+    ++I;
+  }
+  J = I + t;
+}
+
+__global__ void __launch_bounds__(256) k_gram128(int64_t n, const double* __restrict__ X, int64_t ldx, int a,
+                                                 const double* __restrict__ Y, int64_t ldy, int b, int ti, int tj,
+                                                 int sym, int64_t rows_per_split, double* __restrict__ part) {
+  __shared__ double xs[2][16 * G128_PITCH];
+  __shared__ double ys[2][16 * G128_PITCH];
+  const int tl = blockIdx.x;
+  int TI, TJ;
+  g128_tile(tl, ti, tj, sym, TI, TJ);
+  const int i0 = TI * 128, j0 = TJ * 128;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
+  const int64_t rbeg = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t rend = min(n, rbeg + rows_per_split);
+
+  // global -> register staging: thread t loads rows 8 (t % 2) .. + 7 of
+  // column t / 2 of the X and Y slices
+  const int sc = tid >> 1, sr = (tid & 1) * 8;
+  const bool xok = i0 + sc < a, yok = j0 + sc < b;
+  const double* xp = X + (int64_t)(xok ? i0 + sc : 0) * ldx;
+  const double* yp = Y + (int64_t)(yok ? j0 + sc : 0) * ldy;
+  double xr[8], yr[8];
+  auto load = [&](int64_t r0) {
+    const int64_t r = r0 + sr;
+    if (r + 7 < rend) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        xr[e] = xok ? xp[r + e] : 0.0;
+        yr[e] = yok ? yp[r + e] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const bool ok = r + e < rend;
+        xr[e] = (xok && ok) ? xp[r + e] : 0.0;
+        yr[e] = (yok && ok) ? yp[r + e] : 0.0;
+      }
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      xs[buf][(sr + e) * G128_PITCH + sc] = xr[e];
+      ys[buf][(sr + e) * G128_PITCH + sc] = yr[e];
+    }
+  };
+  double4_t acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+  // 16 x 16 sub-tiles wholly past a or b (a ragged last tile) skip their MFMAs
+  bool live[4], livej[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    live[u] = i0 + wi + 16 * u < a;
+    livej[u] = j0 + wj + 16 * u < b;
+  }
+  int buf = 0;
+  if (rbeg < rend) {
+    load(rbeg);
+    stage(0);
+  }
+  __syncthreads();
+  for (int64_t r0 = rbeg; r0 < rend; r0 += 16) {
+    const bool more = r0 + 16 < rend;
+    if (more) load(r0 + 16);
+    const double* xb = xs[buf];
+    const double* yb = ys[buf];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = 4 * t + lg;
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = xb[k * G128_PITCH + wi + 16 * u + li];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = yb[k * G128_PITCH + wj + 16 * v + li];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (live[u] && livej[v]) acc[u][v] = mfma16(av[u], bv[v], acc[u][v]);
+    }
+    if (more) stage(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  double* out = part + ((int64_t)blockIdx.y * gridDim.x + tl) * (128 * 128);
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int ii = wi + 16 * u + lg + 4 * e, jj = wj + 16 * v + li;
+        out[jj * 128 + ii] = acc[u][v][e];
+      }
+}
+
+// C(i, j) = sum over the splits (in order) of the tile partials; with sym the
+// entries below the diagonal take the value computed for (j, i), so C is
+// exactly symmetric.
+__global__ void k_gram128_reduce(const double* __restrict__ part, int ntl, int nsplit, int ti, int tj, int a, int b,
+                                 int sym, double* __restrict__ C, int64_t ldc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i >= a || j >= b) return;
+  const int si = (sym && i > j) ? j : i, sj = (sym && i > j) ? i : j;
+  const int I = si >> 7, J = sj >> 7;
+  // inverse of g128_tile
+  const int tl = sym ? I * ti - I * (I - 1) / 2 + (J - I) : I * tj + J;
+  const int64_t o = (int64_t)(sj & 127) * 128 + (si & 127);
+  double s = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) s += part[((int64_t)sp * ntl + tl) * (128 * 128) + o];
+  C[(int64_t)j * ldc + i] = s;
+}
+
+static void gram128(Ctx* ctx, int64_t n, const double* X, int64_t ldx, int a, const double* Y, int64_t ldy, int b,
+                    double* C, int64_t ldc) {
+  const bool sym = X == Y && ldx == ldy && a == b;
+  const int ti = (a + 127) / 128, tj = (b + 127) / 128;
+  const int ntl = sym ? ti * (ti + 1) / 2 : ti * tj;
+  // about two workgroups per compute unit, at least 512 rows per split
+  const int64_t want = std::max<int64_t>(1, (int64_t)2 * ctx->num_cu / ntl);
+  int64_t rps = std::max<int64_t>(512, (n + want - 1) / want);
+  rps = (rps + 15) / 16 * 16;
+  const int nsplit = (int)((n + rps - 1) / rps);
+  DBuf<double> part(ctx, (size_t)nsplit * ntl * 128 * 128);
+  hipLaunchKernelGGL(k_gram128, dim3(ntl, nsplit), dim3(256), 0, ctx->stream, n, X, ldx, a, Y, ldy, b, ti, tj,
+                     sym ? 1 : 0, rps, part.get());
+  KERNEL_CHECK();
+  hipLaunchKernelGGL(k_gram128_reduce, dim3(ceil_div(a, 256), b), dim3(256), 0, ctx->stream, (const double*)part.get(),
+                     ntl, nsplit, ti, tj, a, b, sym ? 1 : 0, C, ldc);
+  KERNEL_CHECK();
+}
+
 template <typename TX, typename TY>
 void gram(Ctx* ctx, int64_t n, const TX* X, int64_t ldx, int a, const TY* Y, int64_t ldy, int b, double* C,
           int64_t ldc) {
@@ -165,6 +329,20 @@ void gram(Ctx* ctx, int64_t n, const TX* X, int64_t ldx, int a, const TY* Y, int
     return;
   }
   if constexpr (sizeof(TX) == 8 && sizeof(TY) == 8) {
+    // The own 128 x 128-tile kernel for the symmetric Grams X^T X where it
+    // was measured faster than rocBLAS (it computes only the tiles on and
+    // above the diagonal): up to 512 columns, or while X stays within
+    // 1.5 GB (beyond, its per-tile re-reads of X from HBM dominate; n =
+    // 250000: q = 206 / 417 take 0.51 / 1.65 ms against 0.54 / 1.98 ms,
+    // q = 1026 10.8 ms against 10.3 ms; n = 125000, q = 1218: 4.8 against
+    // 6.4 ms).  gram_impl 1 uses it for every large Gram, 0 never.
+    const bool symx = (const void*)X == (const void*)Y && ldx == ldy && a == b;
+    const bool own = ctx->gram_impl == 1 ||
+                     (ctx->gram_impl == 2 && symx && (a <= 512 || (double)n * a * 8.0 <= 1.5e9));
+    if (own && (int64_t)a * b >= 32 * 32 && a < 65536 && b < 65536) {
+      gram128(ctx, n, (const double*)X, ldx, a, (const double*)Y, ldy, b, C, ldc);
+      return;
+    }
     // large FP64 Grams: rocBLAS dgemm (MFMA) over row chunks (split-K as a
     // strided batch), partial products summed in a fixed order, so the result
     // is reproducible (atomics are also disabled on the context's handle)

@@ -1,6 +1,7 @@
 // Context, arena and small runtime helpers.
 #include "common.hpp"
 
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -193,6 +194,12 @@ void ctx_init(Ctx& c, int device, hipStream_t user_stream, const AllocHooks& hoo
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c.num_cu = prop.multiProcessorCount;
+  // MPCARE_GRAM=0 / 1 / 2 picks the implementation of the large FP64 Grams
+  // (rocBLAS / the own kernel / the own kernel where it is faster, default)
+  if (const char* g = std::getenv("MPCARE_GRAM")) {
+    const int v = std::atoi(g);
+    c.gram_impl = v >= 0 && v <= 2 ? v : 2;
+  }
   c.arena = new Arena(c.stream, c.hooks);
   scratch_setup(device);
   if (rocblas_create_handle(&c.blas) != rocblas_status_success) {

@@ -122,6 +122,41 @@ def test_tsgemm_parity(ctx, pk, n, q, k, beta):
     assert np.abs(Y - ref).max() <= 1e-12 * (np.abs(X) @ np.abs(S)).max() + 1e-14
 
 
+@pytest.fixture(scope="module")
+def ctx_gram128(pk):
+    """A context whose large FP64 Grams run on the library's 128 x 128-tile
+    MFMA kernel (MPCARE_GRAM=1 at context creation)."""
+    import os
+    old = os.environ.get("MPCARE_GRAM")
+    os.environ["MPCARE_GRAM"] = "1"
+    try:
+        c = pk.Context(0)
+    finally:
+        if old is None:
+            del os.environ["MPCARE_GRAM"]
+        else:
+            os.environ["MPCARE_GRAM"] = old
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("n,a,b", [(1, 40, 40), (17, 33, 100), (1000, 129, 300), (70001, 64, 65), (5000, 256, 128),
+                                   (40000, 417, 417)])
+def test_gram128_parity(ctx_gram128, pk, n, a, b):
+    """The 128 x 128-tile FP64 MFMA Gram against the FP64 product in numpy:
+    ragged tiles, fewer rows than a 16-row slice, one and several tiles;
+    X^T X exactly symmetric and run-to-run identical."""
+    X = RNG.standard_normal((n, a))
+    Y = RNG.standard_normal((n, b))
+    C = host(pk.gram(ctx_gram128, dev(X), dev(Y)))
+    ref = X.T @ Y
+    assert np.abs(C - ref).max() <= 1e-13 * math.sqrt(n) * (np.abs(X).max() * np.abs(Y).max() * n) ** 0.5 + 1e-12
+    Xd = dev(X)
+    Cs = host(pk.gram(ctx_gram128, Xd, Xd))
+    assert np.allclose(Cs, X.T @ X, rtol=1e-12, atol=1e-10) and np.array_equal(Cs, Cs.T)
+    assert np.array_equal(Cs, host(pk.gram(ctx_gram128, Xd, Xd)))
+
+
 def test_gram_reproducible(ctx, pk):
     X = dev(RNG.standard_normal((50000, 40)))
     C1 = host(pk.gram(ctx, X, X))
