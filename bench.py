@@ -66,6 +66,10 @@ def parse():
     ap.add_argument("--no-xgate", action="store_true", help="skip the tol 1e-12 solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-shifts", type=int, default=12)
+    ap.add_argument("--dense-sweep", action="store_true",
+                    help="time the batched shifted LU (16 shifts, n = 256..2048, FP32 and FP64) with its solves, "
+                         "and the FP64 Grams of the refinement's shapes on both implementations, and print that "
+                         "table instead")
     ap.add_argument("--spmm-sweep", action="store_true",
                     help="time the shifted sparse product alone over k = 1..128 on the 500 x 500 2D and 64^3 3D "
                          "operators with rotated operand sets of more than 1 GiB, and print that table instead")
@@ -95,6 +99,66 @@ def spmm_sweep(pk, wl, torch):
                 print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
         del Ad
     ctx.close()
+    return rows
+
+
+def dense_sweep(pk, wl, torch, np):
+    """Host-timed sweep of the dense kernels (each call synchronises; kernel
+    durations come from a profiler run of this sweep):
+    * the batched LU of A^T + p_s I for 16 log-spaced shifts of the dense test
+      family (A = -Q diag(logspace(0, 2, n)) Q^T), n = 256, 512, 1024, 2048,
+      FP32 and FP64, then 10 solves with 16 right-hand sides;
+    * the FP64 Grams X^T X at the refinement's widths (n = 250000: 206, 417,
+      1026 columns; n = 125000: 1218) with the library's rule (own
+      128 x 128-tile kernel where faster) and with rocBLAS only."""
+    import os
+    rows = []
+    ctx = pk.Context(0)
+    for prec in ("fp32", "fp64"):
+        for n in (256, 512, 1024, 2048):
+            rng = np.random.default_rng(n)
+            Q = wl.haar_orthogonal(n, rng)
+            At = torch.as_tensor((-(Q * np.logspace(0.0, 2.0, n)) @ Q.T).T.copy(), device="cuda:0")
+            shifts = wl.logspaced_real_shifts(1.0, 100.0, 16).real
+            tf = []
+            for rep in range(3):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                F, perm, info = pk.shifted_lu_factor(ctx, At, shifts, prec=prec)
+                torch.cuda.synchronize()
+                tf.append(time.perf_counter() - t)
+            W = torch.as_tensor(rng.standard_normal((n, 16)), device="cuda:0")
+            pk.shifted_lu_solve(ctx, F[0], perm[0], W, prec=prec)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(10):
+                pk.shifted_lu_solve(ctx, F[0], perm[0], W, prec=prec)
+            torch.cuda.synchronize()
+            ts = (time.perf_counter() - t) / 10
+            fl = 16 * 2.0 / 3.0 * n ** 3
+            rows.append({"kernel": "lu", "prec": prec, "n": n, "shifts": 16, "factor_ms": round(1e3 * min(tf[1:]), 3),
+                         "factor_GFLOPs": round(fl / min(tf[1:]) * 1e-9, 1), "solve16_us": round(1e6 * ts, 1),
+                         "info": int(sum(info))})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    ctx.close()
+    for impl in ("2", "0"):
+        os.environ["MPCARE_GRAM"] = impl        # read at context creation
+        ctx = pk.Context(0)
+        for n, q in ((250000, 206), (250000, 417), (250000, 1026), (125000, 1218)):
+            X = torch.as_tensor(np.random.default_rng(q).standard_normal((n, q)), device="cuda:0")
+            pk.gram(ctx, X, X)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(5):
+                pk.gram(ctx, X, X)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / 5
+            rows.append({"kernel": "gram", "impl": "rule" if impl == "2" else "rocblas", "n": n, "q": q,
+                         "ms": round(1e3 * dt, 3), "TFLOPs_full_square": round(2.0 * n * q * q / dt * 1e-12, 1)})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            del X
+        ctx.close()
+    os.environ.pop("MPCARE_GRAM", None)
     return rows
 
 
@@ -261,6 +325,14 @@ def main():
         print(json.dumps({"metric": "SpMM HBM GB/s (standalone, rotated operands > 1 GiB)", "value": best["GB/s"],
                           "unit": "GB/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
                           "peak": HBM_PEAK_GBS, "rows": rows}))
+        return
+
+    if args.dense_sweep:
+        rows = dense_sweep(pk, wl, torch, np)
+        best = max(r["factor_GFLOPs"] for r in rows if r["kernel"] == "lu" and r["prec"] == "fp32")
+        print(json.dumps({"metric": "batched shifted LU GFLOP/s (16 shifts, FP32, best order)", "value": best,
+                          "unit": "GFLOP/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+                          "rows": rows}))
         return
 
     if args.workload == "fdm_batch":
