@@ -831,39 +831,10 @@ void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out
   // and the noise floor lies about 28 decades down, so three passes
   // normally suffice; the loop ends earlier when the remainder reaches the
   // noise level or F's rank is exhausted.
-  // After a pass that kept every new column the remainder E S lies in
-  // span(Rest) (below), so its scaled Gram is Rest H Rest^T with
-  // H = (E S Rest)^T (E S Rest), nrest x nrest: formed from the n x nrest
-  // product E (S Rest) instead of the q x q Gram of E, it is both the next
-  // pass's matrix and, through ||H||_F, the noise test.
-  DBuf<double> ER;
-  auto reduced_gram = [&]() {
-    d2d(ctx, Tmp.get(), Rest.get(), (size_t)q * nrest * sizeof(double));
-    dim3 gsr(ceil_div(q, 64), nrest);
-    hipLaunchKernelGGL(k_scale_rows, gsr, dim3(64), 0, ctx->stream, Tmp.get(), (int64_t)q, q, nrest, ds.get());
-    KERNEL_CHECK();
-    ER.resize(ctx, (size_t)ld * nrest);
-    tsgemm(ctx, n, Ecur, lde, q, Tmp.get(), q, nrest, 1.0, 0.0, ER.get(), ld);
-    gram(ctx, n, ER.get(), ld, nrest, ER.get(), ld, nrest, Hred.get(), nrest);
-    std::vector<double> h((size_t)nrest * nrest);
-    d2h(ctx, h.data(), Hred.get(), h.size() * sizeof(double));
-    double f2 = 0.0;
-    for (double v : h) f2 += v * v;
-    return std::sqrt(f2);
-  };
   const int max_passes = 6;
   bool complete = false;
   for (int pass = 0; pass < max_passes; ++pass) {
-    if (have_rest && nrest > 0) {
-      const double fro = reduced_gram();
-      if (fro <= noise) {
-        if (trace)
-          std::fprintf(stderr, "[rr_orth] n %lld q %d pass %d ||H||_F %.3e at noise (search %d): done\n",
-                       (long long)n, q, pass, fro, nrest);
-        complete = true;
-        break;
-      }
-    } else if (pass > 0 || k0 > 0) {
+    if (pass > 0 || k0 > 0) {
       // a remainder at the noise level ends the loop here, as the eigen-
       // decomposition below would (it selects nothing when lmax <= noise)
       const double fro = remainder_fro();
@@ -875,12 +846,10 @@ void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out
         break;
       }
     }
-    if (!have_rest) {
-      d2d(ctx, W.get(), G.get(), (size_t)q * q * sizeof(double));
-      dim3 gs(ceil_div(q, 64), q);
-      hipLaunchKernelGGL(k_scale_sym, gs, dim3(64), 0, ctx->stream, W.get(), (int64_t)q, q, ds.get());
-      KERNEL_CHECK();
-    }
+    d2d(ctx, W.get(), G.get(), (size_t)q * q * sizeof(double));
+    dim3 gs(ceil_div(q, 64), q);
+    hipLaunchKernelGGL(k_scale_sym, gs, dim3(64), 0, ctx->stream, W.get(), (int64_t)q, q, ds.get());
+    KERNEL_CHECK();
     // Search space of this pass, in the scaled coordinates of F's columns:
     // all of R^q, or, after a pass whose new columns were all kept, the
     // directions that pass left unselected (Rest, q x nrest, orthonormal).
@@ -894,7 +863,12 @@ void rr_orth(Ctx* ctx, int64_t n, const double* F, int64_t ldf, int q, Orth& out
       complete = true;
       break;
     }
-    double* Hm = reduced ? Hred.get() : W.get();   // Hred from reduced_gram() above
+    double* Hm = W.get();
+    if (reduced) {
+      dgemm(ctx, false, false, q, nb, q, 1.0, W.get(), q, Rest.get(), q, 0.0, Tmp.get(), q);
+      dgemm(ctx, true, false, nb, nb, q, 1.0, Rest.get(), q, Tmp.get(), q, 0.0, Hred.get(), nb);
+      Hm = Hred.get();
+    }
     dsyevd(ctx, nb, Hm, nb, lam);
     const double lmax = *std::max_element(lam.begin(), lam.end());
     const double thr = std::max(1e-11 * lmax, noise);
