@@ -15,5 +15,6 @@ Modules
   adi      - shifted solves with SMW (Sec. 4) and residual-based LR-ADI
   care     - NLR-ADI initial solve and Framework 1 (mixed-precision Newton IR)
   shifts   - Penzl-style heuristic shift selection from Ritz values
+  ilu      - multicolour ILU(0) of A^T + p I (the GMRES preconditioner of Sec. 5)
 """
-from . import riccati, lowrank, adi, care  # noqa: F401
+from . import riccati, lowrank, adi, care, ilu  # noqa: F401
