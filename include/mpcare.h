@@ -192,6 +192,13 @@ typedef struct {
                              x_r = (b_r - E x_b) / (d + p) (the red-black block
                              factorisation behind a multicolour ILU of the stencil,
                              with the black block's fill kept); 0: never        */
+  int32_t krylov_precond; /* 1: the restarted GMRES solves (krylov_method = 1) are right-
+                             preconditioned by ILU(0) of A^T + p I in a multicolour
+                             order (care_ilu0_factor), the inner solver of Sec. 5
+                             ("Performance Analysis on GPU"); with krylov_rb = 1 and
+                             a two-colourable A the reduced system still runs without
+                             it, so krylov_rb = 0 gives the paper's setting.  0
+                             (default): no preconditioner                          */
 } care_opts;
 
 /* Statistics written by the solvers (host struct). */
@@ -255,7 +262,8 @@ void care_ctx_destroy(care_ctx* ctx);
  *   - inner solver: column-batched BiCGStab on the red-black reduced
  *     operator where A is two-colourable with a constant diagonal
  *     (krylov_rb = 1), unpreconditioned BiCGStab otherwise (paper:
- *     ILU(0)-preconditioned restarted GMRES); Krylov tolerance 1e-7 for
+ *     ILU(0)-preconditioned restarted GMRES, available as krylov_method = 1,
+ *     krylov_precond = 1, krylov_rb = 0); Krylov tolerance 1e-7 for
  *     FP32 (paper 1e-5), max(1e-13, min(1e-10, tol / 10)) for FP64 (paper
  *     1e-10); iteration cap 4000 (paper 100 / 200 GMRES steps);
  *   - refinement forcing theta = 0.25 (refine_forcing; paper: fixed
@@ -324,6 +332,41 @@ care_status care_shifted_solve(care_ctx* ctx, const care_csr* A, const double* B
                                const double* K, int64_t ldk, int32_t m, care_shift p,
                                const double* W, int64_t ldw, int32_t w, int32_t prec,
                                double tol, int32_t maxit, double* V, int64_t ldv, int32_t* iters);
+
+/* care_shifted_solve with the Krylov method of `opts` (NULL: as
+ * care_shifted_solve): krylov_method, krylov_restart, krylov_compact,
+ * krylov_rb and krylov_precond are read, nothing else.  With krylov_method = 1,
+ * krylov_precond = 1 and krylov_rb = 0 the solve is the paper's restarted
+ * GMRES right-preconditioned by ILU(0) (Sec. 5, "Performance Analysis on
+ * GPU"); maxit then counts Arnoldi steps.  A zero ILU(0) pivot returns
+ * CARE_ERR_BREAKDOWN. */
+care_status care_shifted_solve_opts(care_ctx* ctx, const care_csr* A, const double* B, int64_t ldb,
+                                    const double* K, int64_t ldk, int32_t m, care_shift p, const double* W,
+                                    int64_t ldw, int32_t w, int32_t prec, double tol, int32_t maxit,
+                                    const care_opts* opts, double* V, int64_t ldv, int32_t* iters);
+
+/* ILU(0) of M = A^T + p I (real p) in precision prec, the preconditioner of
+ * the restarted-GMRES inner solves of Sec. 5 ("Performance Analysis on
+ * GPU"), in the multicolour order the library uses: rows are coloured
+ * first-fit in their natural order over the off-diagonal pattern of A (an
+ * edge for a_ij or a_ji nonzero), ordered colour by colour and by index
+ * inside a colour; L (unit lower) and U in that order keep the pattern of M
+ * and satisfy (L U)_ij = m_ij on it.  Inspection entry point, all outputs
+ * HOST: colours[n] the colour of each row; off[noff] the factor value at
+ * each off-diagonal nonzero (i, j) of A^T in row-major order (l_ij when j's
+ * colour is below i's, u_ij otherwise), noff = the number of off-diagonal
+ * nonzeros of A (CARE_ERR_CAPACITY otherwise); udiag[n] the pivots u_ii.
+ * CARE_ERR_BREAKDOWN on a zero pivot, CARE_ERR_NOT_IMPLEMENTED when the
+ * pattern needs more than 1024 colours. */
+care_status care_ilu0_factor(care_ctx* ctx, const care_csr* A, int32_t prec, double p, int32_t* colours,
+                             double* off, int64_t noff, double* udiag);
+
+/* Z = (L U)^{-1} X with the factors of care_ilu0_factor (the preconditioner
+ * solve: one forward and one backward sweep, each one parallel step per
+ * colour).  X, Z: device FP64, n x k column-major (ldx, ldz >= n), X rounded
+ * to prec, Z converted back; they may not overlap. */
+care_status care_ilu0_apply(care_ctx* ctx, const care_csr* A, int32_t prec, double p, const double* X,
+                            int64_t ldx, int32_t k, double* Z, int64_t ldz);
 
 /* Batched LU factorisation with partial pivoting of M_s = M0 + p_s I,
  * s < nshifts: the direct shifted solves of the dense problems (Sec. 5.1

@@ -40,7 +40,7 @@ class care_opts(C.Structure):
         ("spmm_split", C.c_int32), ("krylov_relax", C.c_int32), ("refine_forcing", C.c_double),
         ("tau_L0", C.c_double), ("spmm_tune", C.c_int32), ("shift_update", C.c_int32),
         ("krylov_method", C.c_int32), ("krylov_restart", C.c_int32), ("krylov_compact", C.c_int32),
-        ("adi_rotate", C.c_int32), ("krylov_rb", C.c_int32),
+        ("adi_rotate", C.c_int32), ("krylov_rb", C.c_int32), ("krylov_precond", C.c_int32),
     ]
 
 
@@ -92,6 +92,10 @@ SIGNATURES = {
     "care_spmm_timing": (I32, [P, C.POINTER(care_csr), I32, care_shift, I32, I32, I32, I32, I32, PDBL, PDBL]),
     "care_shifted_solve": (I32, [P, C.POINTER(care_csr), P, I64, P, I64, I32, care_shift, P, I64, I32, I32, DBL,
                                  I32, P, I64, PI32]),
+    "care_shifted_solve_opts": (I32, [P, C.POINTER(care_csr), P, I64, P, I64, I32, care_shift, P, I64, I32, I32,
+                                      DBL, I32, C.POINTER(care_opts), P, I64, PI32]),
+    "care_ilu0_factor": (I32, [P, C.POINTER(care_csr), I32, DBL, PI32, PDBL, I64, PDBL]),
+    "care_ilu0_apply": (I32, [P, C.POINTER(care_csr), I32, DBL, P, I64, I32, P, I64]),
     "care_gram": (I32, [P, I64, P, I64, I32, P, I64, I32, P, I64]),
     "care_gram_noalloc": (I32, [P, I64, P, I64, I32, P, I64, I32, P, I64]),
     "care_tsgemm": (I32, [P, I64, P, I64, I32, P, I64, I32, DBL, DBL, P, I64]),

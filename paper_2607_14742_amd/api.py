@@ -238,8 +238,10 @@ def tsgemm(ctx, X, S, alpha=1.0, beta=0.0, Y=None):
     return Y
 
 
-def shifted_solve(ctx, A, W, shift, B=None, K=None, prec="fp64", tol=0.0, maxit=0):
-    """V = (A_k^T + p I)^{-1} W with A_k = A - B K^T (SMW); complex p returns [Re | Im]."""
+def shifted_solve(ctx, A, W, shift, B=None, K=None, prec="fp64", tol=0.0, maxit=0, opts=None):
+    """V = (A_k^T + p I)^{-1} W with A_k = A - B K^T (SMW); complex p returns [Re | Im].
+    opts (care_opts, optional) selects the Krylov method (krylov_method,
+    krylov_restart, krylov_compact, krylov_rb, krylov_precond)."""
     W = colmajor(W)
     w = W.shape[1]
     m = 0 if K is None else K.shape[1]
@@ -248,10 +250,39 @@ def shifted_solve(ctx, A, W, shift, B=None, K=None, prec="fp64", tol=0.0, maxit=
     vc = 2 * w if complex(shift).imag != 0 else w
     V = empty_colmajor(A.n, vc, W.device)
     it = C.c_int32(0)
-    st = _check(_lib().care_shifted_solve(ctx.h, A.c, _ptr(B), _ld(B) if B is not None else A.n, _ptr(K),
-                                          _ld(K) if K is not None else A.n, m, _shift(shift), _ptr(W), _ld(W), w,
-                                          PREC[prec], tol, maxit, _ptr(V), _ld(V), C.byref(it)))
+    args = (ctx.h, A.c, _ptr(B), _ld(B) if B is not None else A.n, _ptr(K), _ld(K) if K is not None else A.n, m,
+            _shift(shift), _ptr(W), _ld(W), w, PREC[prec], tol, maxit)
+    if opts is None:
+        st = _check(_lib().care_shifted_solve(*args, _ptr(V), _ld(V), C.byref(it)))
+    else:
+        st = _check(_lib().care_shifted_solve_opts(*args, C.byref(opts), _ptr(V), _ld(V), C.byref(it)))
     return V, dict(status=st, iters=it.value)
+
+
+def ilu0_factor(ctx, A, shift, prec="fp64"):
+    """ILU(0) of A^T + p I in the library's multicolour order: returns
+    (colours, off, udiag) as numpy arrays (off at A^T's off-diagonal nonzeros
+    in row-major order)."""
+    rows = torch.repeat_interleave(torch.arange(A.n, device=A.row_ptr.device),
+                                   (A.row_ptr[1:] - A.row_ptr[:-1]).long())
+    noff = A.nnz - int((A.col_idx.long() == rows).sum().item())
+    colours = np.zeros(A.n, dtype=np.int32)
+    off = np.zeros(max(noff, 1), dtype=np.float64)
+    udiag = np.zeros(A.n, dtype=np.float64)
+    _check(_lib().care_ilu0_factor(ctx.h, A.c, PREC[prec], float(shift),
+                                   colours.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   off.ctypes.data_as(C.POINTER(C.c_double)), noff,
+                                   udiag.ctypes.data_as(C.POINTER(C.c_double))))
+    return colours, off[:noff], udiag
+
+
+def ilu0_apply(ctx, A, X, shift, prec="fp64"):
+    """Z = (L U)^{-1} X with the ILU(0) factors of A^T + p I."""
+    X = colmajor(X)
+    Z = empty_colmajor(A.n, X.shape[1], X.device)
+    _check(_lib().care_ilu0_apply(ctx.h, A.c, PREC[prec], float(shift), _ptr(X), _ld(X), X.shape[1], _ptr(Z),
+                                  _ld(Z)))
+    return Z
 
 
 def lyap_lradi(ctx, A, W, shifts, B=None, K=None, tol=0.0, opts=None, rmax=None):

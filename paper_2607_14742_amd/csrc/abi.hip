@@ -108,6 +108,7 @@ void care_opts_default(care_opts* o, int32_t inner_prec) {
   o->adi_deflate = 1;
   o->krylov_block_tol = -1;
   o->krylov_rb = 1;
+  o->krylov_precond = 0;
 }
 
 care_status care_ctx_create(care_ctx** out, int32_t device, void* stream, care_alloc_fn alloc,
@@ -282,17 +283,24 @@ care_status care_shifted_lu_solve(care_ctx* cx, int32_t prec, int64_t n, const v
   });
 }
 
-care_status care_shifted_solve(care_ctx* cx, const care_csr* A, const double* B, int64_t ldb, const double* K,
-                               int64_t ldk, int32_t m, care_shift p, const double* W, int64_t ldw, int32_t w,
-                               int32_t prec, double tol, int32_t maxit, double* V, int64_t ldv, int32_t* iters) {
+static care_status shifted_solve_entry(care_ctx* cx, const care_csr* A, const double* B, int64_t ldb,
+                                       const double* K, int64_t ldk, int32_t m, care_shift p, const double* W,
+                                       int64_t ldw, int32_t w, int32_t prec, double tol, int32_t maxit,
+                                       const care_opts* km, double* V, int64_t ldv, int32_t* iters) {
   return guarded([&]() -> care_status {
     Ctx* ctx = unwrap(cx);
     check_csr_shape(A);
     const Prec pr = prec_from_abi(prec);
     const int64_t n = A->n, ld = pad_ld(n);
     if (w < 0 || m < 0) fail(CARE_ERR_ARG, "w and m must be >= 0");
-    ctx->krylov_method = 0;   // this entry point documents BiCGStab
-    ctx->krylov_compact = 1;
+    // the Krylov method: BiCGStab with the red-black reduction unless km says otherwise
+    ctx->krylov_method = km ? km->krylov_method : 0;
+    ctx->krylov_restart = km ? km->krylov_restart : 0;
+    ctx->krylov_compact = km ? km->krylov_compact : 1;
+    ctx->krylov_rb = km ? km->krylov_rb : 1;
+    ctx->krylov_precond = km ? km->krylov_precond : 0;
+    if (ctx->krylov_method < 0 || ctx->krylov_method > 1) fail(CARE_ERR_ARG, "krylov_method must be 0 or 1");
+    if (ctx->krylov_precond < 0 || ctx->krylov_precond > 1) fail(CARE_ERR_ARG, "krylov_precond must be 0 or 1");
     if (w == 0) return CARE_OK;
     if (!W || !V || ldw < n || ldv < n) fail(CARE_ERR_ARG, "invalid W / V");
     const bool smw = K != nullptr && m > 0;
@@ -300,8 +308,8 @@ care_status care_shifted_solve(care_ctx* cx, const care_csr* A, const double* B,
     if (!(p.re < 0) || !std::isfinite(p.re) || !std::isfinite(p.im)) fail(CARE_ERR_ARG, "shift needs Re p < 0");
     SellOp op;
     build_sell(ctx, A, pr, op);
-    ctx->krylov_rb = 1;
-    rb_attach(ctx, rb_analyse(ctx, A), pr, op);
+    if (ctx->krylov_rb) rb_attach(ctx, rb_analyse(ctx, A), pr, op);
+    if (ctx->krylov_precond) ilu_attach(ctx, ilu_analyse(ctx, A), op);
     care_opts d;
     care_opts_default(&d, prec);
     d.krylov_tol = tol;
@@ -334,6 +342,94 @@ care_status care_shifted_solve(care_ctx* cx, const care_csr* A, const double* B,
     ctx->sync();
     if (iters) *iters = kr.max_iters;
     return kr.unconverged ? CARE_WARN_MAXIT : CARE_OK;
+  });
+}
+
+care_status care_shifted_solve(care_ctx* cx, const care_csr* A, const double* B, int64_t ldb, const double* K,
+                               int64_t ldk, int32_t m, care_shift p, const double* W, int64_t ldw, int32_t w,
+                               int32_t prec, double tol, int32_t maxit, double* V, int64_t ldv, int32_t* iters) {
+  return shifted_solve_entry(cx, A, B, ldb, K, ldk, m, p, W, ldw, w, prec, tol, maxit, nullptr, V, ldv, iters);
+}
+
+care_status care_shifted_solve_opts(care_ctx* cx, const care_csr* A, const double* B, int64_t ldb,
+                                    const double* K, int64_t ldk, int32_t m, care_shift p, const double* W,
+                                    int64_t ldw, int32_t w, int32_t prec, double tol, int32_t maxit,
+                                    const care_opts* opts, double* V, int64_t ldv, int32_t* iters) {
+  return shifted_solve_entry(cx, A, B, ldb, K, ldk, m, p, W, ldw, w, prec, tol, maxit, opts, V, ldv, iters);
+}
+
+care_status care_ilu0_factor(care_ctx* cx, const care_csr* A, int32_t prec, double p, int32_t* colours,
+                             double* off, int64_t noff, double* udiag) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    check_csr_shape(A);
+    const Prec pr = prec_from_abi(prec);
+    if (!std::isfinite(p)) fail(CARE_ERR_ARG, "shift must be finite");
+    if (!colours || !udiag || (noff > 0 && !off)) fail(CARE_ERR_ARG, "output pointer is NULL");
+    SellOp op;
+    build_sell(ctx, A, pr, op);
+    const std::shared_ptr<IluHost> h = ilu_analyse(ctx, A);
+    ilu_attach(ctx, h, op);
+    const std::shared_ptr<IluOp::Factors> f = ilu_factor(ctx, op, p);
+    const int64_t n = op.n;
+    const int nsl = op.nslices;
+    std::vector<int> sptr(nsl + 1), cols((size_t)op.width_total * 64), col(n);
+    d2h(ctx, sptr.data(), op.sptr.get(), (nsl + 1) * sizeof(int));
+    if (!cols.empty()) d2h(ctx, cols.data(), op.cols.get(), cols.size() * sizeof(int));
+    d2h(ctx, col.data(), op.ilu->colour.get(), n * sizeof(int));
+    const bool dbl = pr == Prec::F64;
+    const size_t vb = vec_bytes(pr);
+    std::vector<uint8_t> fo(cols.size() * vb), fd(n * vb);
+    if (!fo.empty()) d2h(ctx, fo.data(), f->off.get(), fo.size());
+    d2h(ctx, fd.data(), f->dinv.get(), fd.size());
+    auto val = [&](const std::vector<uint8_t>& v, size_t e) -> double {
+      return dbl ? reinterpret_cast<const double*>(v.data())[e] : (double)reinterpret_cast<const float*>(v.data())[e];
+    };
+    // the SELL rows hold A^T's off-diagonal entries in column order, padding last
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; ++i)
+      for (int q = sptr[i >> 6]; q < sptr[(i >> 6) + 1]; ++q) cnt += cols[(size_t)q * 64 + (i & 63)] != i;
+    if (cnt != noff) fail(CARE_ERR_CAPACITY, "off must hold the " + std::to_string(cnt) +
+                                                 " off-diagonal nonzeros of A");
+    int64_t t = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      colours[i] = col[i];
+      udiag[i] = 1.0 / val(fd, i);
+      for (int q = sptr[i >> 6]; q < sptr[(i >> 6) + 1]; ++q) {
+        const size_t e = (size_t)q * 64 + (i & 63);
+        if (cols[e] != i) off[t++] = val(fo, e);
+      }
+    }
+    return CARE_OK;
+  });
+}
+
+care_status care_ilu0_apply(care_ctx* cx, const care_csr* A, int32_t prec, double p, const double* X, int64_t ldx,
+                            int32_t k, double* Z, int64_t ldz) {
+  return guarded([&]() -> care_status {
+    Ctx* ctx = unwrap(cx);
+    check_csr_shape(A);
+    const Prec pr = prec_from_abi(prec);
+    const int64_t n = A->n, ld = pad_ld(n);
+    if (!std::isfinite(p)) fail(CARE_ERR_ARG, "shift must be finite");
+    if (k < 0) fail(CARE_ERR_ARG, "k must be >= 0");
+    if (k == 0) return CARE_OK;
+    if (!X || !Z || ldx < n || ldz < n) fail(CARE_ERR_ARG, "invalid X / Z");
+    SellOp op;
+    build_sell(ctx, A, pr, op);
+    ilu_attach(ctx, ilu_analyse(ctx, A), op);
+    const std::shared_ptr<IluOp::Factors> f = ilu_factor(ctx, op, p);
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      DBuf<T> Xs(ctx, (size_t)ld * k), Zs(ctx, (size_t)ld * k);
+      copy_cols<double, T>(ctx, n, k, X, ldx, Xs.get(), ld);
+      ilu_apply<T>(ctx, op, *f, k, Xs.get(), ld, Zs.get(), ld);
+      copy_cols<T, double>(ctx, n, k, Zs.get(), ld, Z, ldz);
+    };
+    if (pr == Prec::F64) run(double{});
+    else run(float{});
+    ctx->sync();
+    return CARE_OK;
   });
 }
 
@@ -423,10 +519,13 @@ care_status lyap_lradi(care_ctx* cx, const care_csr* A, const double* B, const d
     ctx->krylov_restart = o->krylov_restart;
     ctx->krylov_compact = o->krylov_compact;
     ctx->krylov_rb = o->krylov_rb;
+    ctx->krylov_precond = o->krylov_precond;
+    if (ctx->krylov_precond < 0 || ctx->krylov_precond > 1) fail(CARE_ERR_ARG, "krylov_precond must be 0 or 1");
     const double t0 = now_s();
     SellOp op;
     build_sell(ctx, A, r.prec, op);
     if (ctx->krylov_rb) rb_attach(ctx, rb_analyse(ctx, A), r.prec, op);
+    if (ctx->krylov_precond) ilu_attach(ctx, ilu_analyse(ctx, A), op);
     LradiOut lo;
     const int zcap = lradi_capacity(w, lp.jmax);
     auto run = [&](auto tag) {

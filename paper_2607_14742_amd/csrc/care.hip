@@ -374,7 +374,9 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   ctx->krylov_restart = opts ? opts->krylov_restart : 0;
   ctx->krylov_compact = opts ? opts->krylov_compact : 1;
   ctx->krylov_rb = opts ? opts->krylov_rb : 1;
+  ctx->krylov_precond = opts ? opts->krylov_precond : 0;
   if (ctx->krylov_method < 0 || ctx->krylov_method > 1) fail(CARE_ERR_ARG, "krylov_method must be 0 or 1");
+  if (ctx->krylov_precond < 0 || ctx->krylov_precond > 1) fail(CARE_ERR_ARG, "krylov_precond must be 0 or 1");
 
   SellOp A64, As;
   build_op(ctx, A, Prec::F64, A64);
@@ -382,6 +384,10 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   // by the operator build above), attached to each operator that solves
   const std::shared_ptr<RbHost> rbh = (ctx->krylov_rb && A.csr) ? rb_analyse(ctx, A.csr) : nullptr;
   rb_attach(ctx, rbh, Prec::F64, A64);
+  // multicolour ILU(0) of the shifted matrices for the preconditioned GMRES solves
+  const std::shared_ptr<IluHost> iluh =
+      (ctx->krylov_precond && ctx->krylov_method == 1 && A.csr) ? ilu_analyse(ctx, A.csr) : nullptr;
+  ilu_attach(ctx, iluh, A64);
   S.A64 = &A64;
   S.l0 = eff.penzl_l0;
   S.kp = eff.penzl_kp;
@@ -413,6 +419,7 @@ void care_solve_impl(Ctx* ctx, const OpSpec& A, const double* B, int m, const do
   } else {
     build_op(ctx, A, S.prm.prec, As);
     rb_attach(ctx, rbh, S.prm.prec, As);
+    ilu_attach(ctx, iluh, As);
     S.As = &As;
   }
   // B and C^T in internal layout (ld = pad_ld(n)); C is p x n row-major = C^T col-major with ld n

@@ -135,6 +135,7 @@ struct Ctx {
   int spmm_force_pg = 0;            // > 0: column panels per workgroup (product timing), 0: chosen
   int krylov_compact = 1;           // BiCGStab: gather the still-active columns into fewer panels
   int krylov_restart = 0;           // GMRES restart length (0: 30 in FP32, 50 in FP64)
+  int krylov_precond = 0;           // 1: GMRES right-preconditioned by ILU(0) where the operator has it
   // profile mode: the events the next k_spmm launch records at its own start
   // and end (set by SpmmTimer; null otherwise)
   hipEvent_t spmm_ev0 = nullptr, spmm_ev1 = nullptr;

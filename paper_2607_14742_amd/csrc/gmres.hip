@@ -1,5 +1,6 @@
-// Column-batched restarted GMRES(m) for real shifts, the inner solver family
-// of Sec. 5 (there with an ILU(0) preconditioner; here without one).
+// Column-batched restarted GMRES(m) for real shifts, the inner solver of
+// Sec. 5, optionally right-preconditioned by the multicolour ILU(0) of the
+// shifted matrix as there (ilu.hip).
 //
 // Every right-hand-side column runs its own Arnoldi process; the columns
 // share each launch.  One Arnoldi step is one sparse product of the whole
@@ -111,6 +112,10 @@ KrylovResult gmres(Ctx* ctx, const SellOp& op, double pr, int ncols, const T* b,
   DBuf<int> act(ctx, (size_t)k);
   std::vector<int> hact(k, 1);
   dim3 gcol(ceil_div(n, 256), k);
+  // right preconditioner (factored once per shift and kept on the operator)
+  std::shared_ptr<IluOp::Factors> pre;
+  if (ctx->krylov_precond == 1 && op.ilu) pre = ilu_factor(ctx, op, pr);
+  DBuf<T> zt(ctx, pre ? (size_t)bstride : 0);
 
   // per-column sums of squares of an n x k panel (ld = ldp)
   auto colsq = [&](const T* P, int64_t ldp, std::vector<double>& out) {
@@ -168,8 +173,13 @@ KrylovResult gmres(Ctx* ctx, const SellOp& op, double pr, int ncols, const T* b,
     for (int c = 0; c < k; ++c) g[(size_t)c * (m + 1)] = rnorm[c];
     int j = 0;
     for (; j < m && total < maxit; ++j) {
-      // w = M V_j
-      spmm_plain(ctx, op, pr, 0.0, V.get() + (int64_t)j * bstride, ld, k, w.get(), ld);
+      // w = M V_j, or M P^{-1} V_j
+      if (pre) {
+        ilu_apply<T>(ctx, op, *pre, k, V.get() + (int64_t)j * bstride, ld, zt.get(), ld);
+        spmm_plain(ctx, op, pr, 0.0, zt.get(), ld, k, w.get(), ld);
+      } else {
+        spmm_plain(ctx, op, pr, 0.0, V.get() + (int64_t)j * bstride, ld, k, w.get(), ld);
+      }
       // classical Gram-Schmidt against V_0..V_j, twice
       const int J = j + 1;
       std::vector<double> hsum((size_t)k * J, 0.0);
@@ -262,9 +272,19 @@ KrylovResult gmres(Ctx* ctx, const SellOp& op, double pr, int ncols, const T* b,
     }
     h2d(ctx, hdev.get(), Y.data(), Y.size() * sizeof(double));
     h2d(ctx, act.get(), upd.data(), k * sizeof(int));
-    hipLaunchKernelGGL(k_gm_multiaxpy<T>, gcol, dim3(256), 0, ctx->stream, n, J, V.get(), ld, bstride, hdev.get(),
-                       1.0, x, ldx, act.get());
-    KERNEL_CHECK();
+    if (pre) {
+      // x += P^{-1} (V y): columns without an update stay zero in zt
+      dzero(ctx, zt.get(), (size_t)bstride * sizeof(T));
+      hipLaunchKernelGGL(k_gm_multiaxpy<T>, gcol, dim3(256), 0, ctx->stream, n, J, V.get(), ld, bstride,
+                         hdev.get(), 1.0, zt.get(), ld, act.get());
+      KERNEL_CHECK();
+      ilu_apply<T>(ctx, op, *pre, k, zt.get(), ld, w.get(), ld);
+      axpby<T>(ctx, n, k, 1.0, w.get(), ld, 1.0, x, ldx);
+    } else {
+      hipLaunchKernelGGL(k_gm_multiaxpy<T>, gcol, dim3(256), 0, ctx->stream, n, J, V.get(), ld, bstride,
+                         hdev.get(), 1.0, x, ldx, act.get());
+      KERNEL_CHECK();
+    }
     // true residual for the next cycle (and the report)
     spmm_plain(ctx, op, pr, 0.0, x, ldx, k, w.get(), ld);
     axpby<T>(ctx, n, k, 1.0, b, ldb, -1.0, w.get(), ld);   // w = b - M x

@@ -26,6 +26,7 @@
 namespace mpcare {
 
 struct RbOp;
+struct IluOp;
 
 struct SellOp {
   int64_t n = 0, nnz = 0;          // of A
@@ -60,6 +61,9 @@ struct SellOp {
   // Red-black reduction of A^T + p I (rb.hip), present when A is two-colourable
   // with a constant diagonal and the context enables it
   std::shared_ptr<RbOp> rb;
+  // Multicolour ILU(0) of A^T + p I (ilu.hip): the colouring of A's pattern,
+  // present when the context asks for the preconditioned GMRES solves
+  std::shared_ptr<IluOp> ilu;
   // algorithmic bytes of one product with k real columns: the CSR formula
   // nnz (s_v + 4) + 4 (n + 1) plus `passes` n-vectors per column (2 for
   // y = M x; the fused BiCGStab modes move more, see spmm_vec_passes)
@@ -94,6 +98,32 @@ struct RbOp {
   DBuf<uint8_t> fval, eval;        // values in the operator's vector precision
   SellOp G;                        // G = F E over the black rows (SELL-64, diagonal kept apart)
 };
+
+// Multicolour ILU(0) of A^T + p I (ilu.hip).  ilu_analyse colours the
+// pattern of A first-fit in natural order (host, once per matrix; fails with
+// CARE_ERR_NOT_IMPLEMENTED past 1024 colours); ilu_attach uploads the colour
+// classes to an operator built from the same A.  ilu_factor returns the
+// factors of A^T + p I for a real shift, factored once per shift and kept on
+// the operator; a zero pivot fails with CARE_ERR_BREAKDOWN.  ilu_apply sets
+// Z = (L U)^{-1} X for k columns (X, Z distinct, vector precision of op).
+struct IluHost;
+std::shared_ptr<IluHost> ilu_analyse(Ctx* ctx, const care_csr* A);
+void ilu_attach(Ctx* ctx, const std::shared_ptr<IluHost>& h, SellOp& op);
+struct IluOp {
+  int ncol = 0;
+  std::vector<int> coff;           // colour c holds rows[coff[c] .. coff[c + 1]) (host)
+  DBuf<int> rows;                  // rows grouped by colour, increasing index inside a colour
+  DBuf<int> colour;                // colour of each row
+  struct Factors {
+    DBuf<uint8_t> off;             // l_ij / u_ij at the SELL positions of A^T
+    DBuf<uint8_t> dinv;            // 1 / u_ii
+  };
+  std::map<double, std::shared_ptr<Factors>> fac;
+};
+std::shared_ptr<IluOp::Factors> ilu_factor(Ctx* ctx, const SellOp& op, double p);
+template <typename T>
+void ilu_apply(Ctx* ctx, const SellOp& op, const IluOp::Factors& f, int k, const T* X, int64_t ldx, T* Z,
+               int64_t ldz);
 
 // Y = (A^T + p I) X for k real columns (complex shift: k complex columns in
 // interleaved [re, im] column pairs, i.e. 2k real columns).  X, Y in the

@@ -1,0 +1,176 @@
+"""Multicolour ILU(0) of A^T + p I and the ILU(0)-preconditioned restarted
+GMRES inner solves (Sec. 5, "Performance Analysis on GPU"), through the C
+ABI, against the oracle (oracle/ilu.py, oracle/adi.py).
+
+* colours: bit-exact against the oracle's first-fit colouring;
+* factor entries: within the rounding of the precision.  Each entry is the
+  result of at most w_i w_k multiply-adds (row widths of the stencil) on
+  values of the size of the matrix entries, taken in the same order as the
+  oracle's IKJ sweep; only the pivot division differs (a product with the
+  stored reciprocal), so the FP64 entries agree to 1e-12 and the FP32 ones to
+  1e-5 of the largest entry (50 roundings of 6e-8, three times over);
+* the preconditioner solve: against the oracle's triangular solves, normwise
+  1e-11 (FP64) / 1e-4 (FP32), on a bounded kappa(L U) (diagonally dominant
+  shifted matrices), k = 1, 3, 4, 9 columns (ragged column groups);
+* shifted solves (with and without SMW) with the preconditioned GMRES against
+  the oracle's sparse direct solve, and fewer Arnoldi steps than without the
+  preconditioner;
+* a CARE solved with the paper's inner solver against the Schur solution;
+* a zero pivot and bad arguments are reported as errors."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as wl
+from oracle import adi, ilu, lowrank, riccati
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+RNG = np.random.default_rng(41)
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2607_14742_amd as pk
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pk.load()
+    return pk
+
+
+@pytest.fixture(scope="module")
+def ctx(pk):
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), device="cuda")
+
+
+def random_stable(n, density, seed):
+    R = sp.random(n, n, density=density, random_state=np.random.RandomState(seed))
+    R = (R - 0.4 * R.T).tocsr()
+    d = np.asarray(abs(R).sum(axis=1)).ravel() + 1.0
+    A = (R - sp.diags(d)).tocsr()
+    A.sort_indices()
+    return A
+
+
+CASES = {
+    "fdm2d_30": lambda: (wl.fdm2d(30), -50.0),           # 2 colours (red-black)
+    "fdm3d_9": lambda: (wl.fdm3d(9, 100.0), -200.0),     # 2 colours, seven-point
+    "toeplitz_700": lambda: (wl.toeplitz5(700), -0.5),   # 4 colours
+    "random_600": lambda: (random_stable(600, 0.01, 9), -0.3),   # many colours, ragged rows
+}
+
+
+@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("case", list(CASES))
+def test_ilu0_factor_matches_oracle(pk, ctx, case, prec, rtol):
+    A, p = CASES[case]()
+    print(f"ILU(0) factor {case} {prec}", flush=True)
+    Ad = pk.DeviceCSR.from_scipy(A)
+    colours, off, udiag = pk.ilu0_factor(ctx, Ad, p, prec=prec)
+    f = ilu.ShiftedIlu0(A, p)
+    assert np.array_equal(colours, f.colours)
+    eo, ed = f.entries(A.T.tocsr())
+    scale = max(np.abs(eo).max(initial=0.0), np.abs(ed).max())
+    print(f"  {f.colours.max() + 1} colours; max entry error {np.abs(off - eo).max(initial=0.0) / scale:.2e}, "
+          f"pivots {np.abs(udiag - ed).max() / scale:.2e}", flush=True)
+    assert off.shape == eo.shape
+    assert np.abs(off - eo).max(initial=0.0) <= rtol * scale
+    assert np.abs(udiag - ed).max() <= rtol * scale
+
+
+@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-11), ("fp32", 1e-4)])
+@pytest.mark.parametrize("case", list(CASES))
+def test_ilu0_apply_matches_oracle(pk, ctx, case, prec, rtol):
+    A, p = CASES[case]()
+    n = A.shape[0]
+    print(f"ILU(0) apply {case} {prec}", flush=True)
+    Ad = pk.DeviceCSR.from_scipy(A)
+    f = ilu.ShiftedIlu0(A, p)
+    for k in (1, 3, 4, 9):
+        X = RNG.standard_normal((n, k))
+        Z = pk.ilu0_apply(ctx, Ad, dev(X), p, prec=prec).cpu().numpy()
+        Zo = f.apply(X)
+        err = np.linalg.norm(Z - Zo) / np.linalg.norm(Zo)
+        assert err <= rtol, (k, err)
+    print(f"  last relative error {err:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+@pytest.mark.parametrize("smw", [False, True])
+@pytest.mark.parametrize("p", [-300.0, -8.0])
+def test_ilu_gmres_shifted_solve_matches_oracle(pk, ctx, prec, tol, smw, p):
+    N = 24
+    A = wl.fdm2d(N)
+    n = N * N
+    m, w = 3, 5
+    B = RNG.standard_normal((n, m))
+    K = 5.0 * RNG.standard_normal((n, m)) if smw else None
+    W = RNG.standard_normal((n, w))
+    Ad = pk.DeviceCSR.from_scipy(A)
+    print(f"ILU-GMRES shifted solve {prec} smw={smw} p={p}", flush=True)
+    opts = pk.default_opts(prec, krylov_method=1, krylov_rb=0, krylov_precond=1)
+    V, info = pk.shifted_solve(ctx, Ad, dev(W), p, B=dev(B) if smw else None, K=dev(K) if smw else None,
+                               prec=prec, tol=tol, opts=opts)
+    V = V.cpu().numpy()
+    ref = adi.ShiftedSolver(A, B if smw else None, K).solve(p, W)
+    err = np.linalg.norm(V - ref) / np.linalg.norm(ref)
+    plain = pk.default_opts(prec, krylov_method=1, krylov_rb=0, krylov_precond=0)
+    _, info0 = pk.shifted_solve(ctx, Ad, dev(W), p, B=dev(B) if smw else None, K=dev(K) if smw else None,
+                                prec=prec, tol=tol, opts=plain)
+    print(f"  error {err:.2e}; Arnoldi steps {info['iters']} preconditioned, {info0['iters']} without", flush=True)
+    assert info["status"] == 0
+    assert err <= 30.0 * tol
+    assert 0 < info["iters"] < info0["iters"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_care_with_ilu_gmres_inner_solves_vs_schur(pk, ctx, prec):
+    """The 20 x 20 FDM CARE (n = 400) with the paper's inner solver
+    (GMRES(50/30) + ILU(0) on the full shifted system)."""
+    P = wl.config1()
+    print(f"CARE ILU-GMRES {prec}", flush=True)
+    A = pk.DeviceCSR.from_scipy(P.A)
+    Z, stats, st = pk.care_solve(ctx, A, dev(P.B), dev(P.C), tol=1e-12, shifts=P.shifts, prec=prec,
+                                 krylov_method=1, krylov_rb=0, krylov_precond=1)
+    assert st == 0, stats
+    Z = Z.cpu().numpy()
+    Xs = riccati.care_schur(P.A, P.B, P.C)
+    assert lowrank.residual_norm(P.A, P.B, P.C, Z) <= 1e-10 * np.linalg.norm(P.C @ P.C.T)
+    assert np.linalg.norm(Z @ Z.T - Xs) <= 1e-8 * np.linalg.norm(Xs)
+
+
+def test_ilu0_zero_pivot_and_bad_arguments(pk, ctx):
+    A = sp.csr_matrix((np.array([1.0, 1.0]), np.array([0, 2]), np.array([0, 1, 1, 2])), shape=(3, 3))
+    Ad = pk.DeviceCSR.from_scipy(A)
+    with pytest.raises(pk.CareError) as e:
+        pk.ilu0_factor(ctx, Ad, 0.0)       # row 1 of A^T + 0 I is empty: u_11 = 0
+    assert e.value.name == "CARE_ERR_BREAKDOWN"
+    colours, off, udiag = pk.ilu0_factor(ctx, Ad, -2.0)
+    assert list(colours) == [0, 0, 0] and off.size == 0 and np.array_equal(udiag, [-1.0, -2.0, -1.0])
+    B = wl.fdm2d(6)
+    Bd = pk.DeviceCSR.from_scipy(B)
+    lib = pk.load()
+    buf = np.zeros(B.nnz, dtype=np.float64)
+    ci = np.zeros(36, dtype=np.int32)
+    ud = np.zeros(36, dtype=np.float64)
+    st = lib.care_ilu0_factor(ctx.h, Bd.c, pk.CARE_FP64, -1.0, ci.ctypes.data_as(C.POINTER(C.c_int32)),
+                              buf.ctypes.data_as(C.POINTER(C.c_double)), B.nnz,
+                              ud.ctypes.data_as(C.POINTER(C.c_double)))
+    assert pk.STATUS_NAMES[st] == "CARE_ERR_CAPACITY"      # off holds nnz - n entries, not nnz
+    st = lib.care_ilu0_factor(ctx.h, Bd.c, pk.CARE_FP64, float("nan"), ci.ctypes.data_as(C.POINTER(C.c_int32)),
+                              buf.ctypes.data_as(C.POINTER(C.c_double)), B.nnz - 36,
+                              ud.ctypes.data_as(C.POINTER(C.c_double)))
+    assert pk.STATUS_NAMES[st] == "CARE_ERR_ARG"
+    with pytest.raises(pk.CareError):
+        pk.care_solve(ctx, Bd, dev(np.ones((36, 1))), dev(np.ones((1, 36))), tol=1e-10, shifts=[-1.0],
+                      krylov_method=1, krylov_precond=2)
