@@ -173,7 +173,7 @@ typedef struct {
                              1 restarted GMRES for real shifts (complex pairs stay
                              on BiCGStab); krylov_maxit then counts Arnoldi steps  */
   int32_t krylov_restart; /* GMRES restart length; <= 0 selects 30 (FP32) / 50 (FP64),
-                             the values of Sec. 5                                   */
+                             the values of Sec. 5; at most 1000                     */
   int32_t krylov_compact; /* BiCGStab: 1 (default) gathers the columns still
                              iterating into fewer 16-column panels whenever they
                              fit in fewer (same arithmetic per column, same
@@ -196,9 +196,10 @@ typedef struct {
                              preconditioned by ILU(0) of A^T + p I in a multicolour
                              order (care_ilu0_factor), the inner solver of Sec. 5
                              ("Performance Analysis on GPU"); with krylov_rb = 1 and
-                             a two-colourable A the reduced system still runs without
-                             it, so krylov_rb = 0 gives the paper's setting.  0
-                             (default): no preconditioner                          */
+                             a two-colourable A, GMRES runs on the reduced system
+                             G + p' I, preconditioned by ILU(0) of that matrix;
+                             krylov_rb = 0 gives the paper's setting.  0 (default):
+                             no preconditioner                                     */
 } care_opts;
 
 /* Statistics written by the solvers (host struct). */

@@ -26,15 +26,21 @@ namespace {
 constexpr int GM_ROWS = 8;                 // rows per thread in the dot kernel
 constexpr int GM_CHUNK = 256 * GM_ROWS;    // rows per block
 
-// part[(c J + i) nb + blk] = sum over the block's rows of V_i[row, c] w[row, c]
-// (V_i = V + i bstride); the block's rows of w stay in registers.
+// part[(c Jo + i) nb + blk] = sum over the block's rows of V_i[row, c] w[row, c]
+// for i < J (V_i = V + i bstride) and, with self = 1, i = J: the block's part
+// of w[:, c]^T w[:, c] (Jo = J + self).  The block's rows of w stay in
+// registers; each dot is reduced inside its wave by shuffles, and the four
+// wave sums meet once in LDS (fixed order), so the block synchronises once
+// for all J dots.
 template <typename T>
-__global__ void __launch_bounds__(256) k_gm_multidot(int64_t n, int J, const T* __restrict__ V, int64_t ld,
+__global__ void __launch_bounds__(256) k_gm_multidot(int64_t n, int J, int self, const T* __restrict__ V, int64_t ld,
                                                      int64_t bstride, const T* __restrict__ w, int64_t ldw,
                                                      const int* __restrict__ active, double* __restrict__ part,
                                                      int nb) {
   const int c = blockIdx.y, blk = blockIdx.x;
-  __shared__ double sh[256];
+  extern __shared__ double gm_sh[];          // (J + self) x 4 wave sums
+  const int Jo = J + self;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const bool on = active[c] != 0;
   double wv[GM_ROWS];
   int64_t rows[GM_ROWS];
@@ -43,44 +49,52 @@ __global__ void __launch_bounds__(256) k_gm_multidot(int64_t n, int J, const T* 
     rows[u] = (int64_t)blk * GM_CHUNK + u * 256 + threadIdx.x;
     wv[u] = (on && rows[u] < n) ? (double)w[(int64_t)c * ldw + rows[u]] : 0.0;
   }
-  for (int i = 0; i < J; ++i) {
+  for (int i = 0; i < Jo; ++i) {
     double s = 0.0;
     if (on) {
-      const T* vi = V + (int64_t)i * bstride + (int64_t)c * ld;
+      if (i < J) {
+        const T* vi = V + (int64_t)i * bstride + (int64_t)c * ld;
 #pragma unroll
-      for (int u = 0; u < GM_ROWS; ++u)
-        if (rows[u] < n) s += (double)vi[rows[u]] * wv[u];
+        for (int u = 0; u < GM_ROWS; ++u)
+          if (rows[u] < n) s += (double)vi[rows[u]] * wv[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < GM_ROWS; ++u) s += wv[u] * wv[u];
+      }
     }
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) part[((int64_t)c * J + i) * nb + blk] = sh[0];
-    __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) gm_sh[i * 4 + wave] = s;
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < Jo; i += 256)
+    part[((int64_t)c * Jo + i) * nb + blk] = (gm_sh[i * 4] + gm_sh[i * 4 + 1]) + (gm_sh[i * 4 + 2] + gm_sh[i * 4 + 3]);
 }
 
-// h[c J + i] = sum_blk part[(c J + i) nb + blk], fixed order
-__global__ void k_gm_reduce(int total, int nb, const double* __restrict__ part, double* __restrict__ h) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// h[t] = sum_blk part[t nb + blk] for t < total: one wave per output, the
+// lanes take strided blocks and a shuffle tree combines them (fixed order)
+__global__ void __launch_bounds__(256) k_gm_reduce(int total, int nb, const double* __restrict__ part,
+                                                   double* __restrict__ h) {
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (t >= total) return;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[(int64_t)t * nb + b];
-  h[t] = s;
+  for (int b = lane; b < nb; b += 64) s += part[(int64_t)t * nb + b];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) h[t] = s;
 }
 
-// y[:, c] += alpha sum_{i < J} coef[c J + i] V_i[:, c] for active columns
+// y[:, c] += alpha sum_{i < J} coef[c cstride + i] V_i[:, c] for active columns
 template <typename T>
 __global__ void __launch_bounds__(256) k_gm_multiaxpy(int64_t n, int J, const T* __restrict__ V, int64_t ld,
-                                                      int64_t bstride, const double* __restrict__ coef, double alpha,
-                                                      T* __restrict__ y, int64_t ldy, const int* __restrict__ active) {
+                                                      int64_t bstride, const double* __restrict__ coef, int cstride,
+                                                      double alpha, T* __restrict__ y, int64_t ldy,
+                                                      const int* __restrict__ active) {
   const int c = blockIdx.y;
   const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (row >= n || !active[c]) return;
   double acc = 0.0;
-  for (int i = 0; i < J; ++i) acc += coef[(int64_t)c * J + i] * (double)V[(int64_t)i * bstride + (int64_t)c * ld + row];
+#pragma unroll 4
+  for (int i = 0; i < J; ++i)
+    acc += coef[(int64_t)c * cstride + i] * (double)V[(int64_t)i * bstride + (int64_t)c * ld + row];
   T* yc = y + (int64_t)c * ldy + row;
   *yc = (T)((double)*yc + alpha * acc);
 }
@@ -104,7 +118,7 @@ KrylovResult gmres(Ctx* ctx, const SellOp& op, double pr, int ncols, const T* b,
   if (ncols <= 0) return res;
   const int64_t n = op.n, ld = pad_ld(n);
   const int k = ncols;
-  const int m = std::max(1, restart);
+  const int m = std::min(1000, std::max(1, restart));   // LDS of the dot kernel: (m + 1) x 4 doubles
   const int nb = (int)ceil_div(n, (int64_t)GM_CHUNK);
   const int64_t bstride = ld * k;
   DBuf<T> V(ctx, (size_t)bstride * (m + 1)), w(ctx, (size_t)bstride);
@@ -121,10 +135,10 @@ KrylovResult gmres(Ctx* ctx, const SellOp& op, double pr, int ncols, const T* b,
   auto colsq = [&](const T* P, int64_t ldp, std::vector<double>& out) {
     std::vector<int> all(k, 1);
     h2d(ctx, act.get(), all.data(), k * sizeof(int));
-    hipLaunchKernelGGL(k_gm_multidot<T>, dim3(nb, k), dim3(256), 0, ctx->stream, n, 1, P, ldp, (int64_t)0, P, ldp,
-                       act.get(), part.get(), nb);
+    hipLaunchKernelGGL(k_gm_multidot<T>, dim3(nb, k), dim3(256), 4 * sizeof(double), ctx->stream, n, 0, 1, P, ldp,
+                       (int64_t)0, P, ldp, act.get(), part.get(), nb);
     KERNEL_CHECK();
-    hipLaunchKernelGGL(k_gm_reduce, dim3(ceil_div(k, 256)), dim3(256), 0, ctx->stream, k, nb, part.get(),
+    hipLaunchKernelGGL(k_gm_reduce, dim3(ceil_div(k, 4)), dim3(256), 0, ctx->stream, k, nb, part.get(),
                        hdev.get());
     KERNEL_CHECK();
     out.resize(k);
@@ -180,30 +194,53 @@ KrylovResult gmres(Ctx* ctx, const SellOp& op, double pr, int ncols, const T* b,
       } else {
         spmm_plain(ctx, op, pr, 0.0, V.get() + (int64_t)j * bstride, ld, k, w.get(), ld);
       }
-      // classical Gram-Schmidt against V_0..V_j, twice
+      // classical Gram-Schmidt against V_0..V_j.  The first pass also returns
+      // ||w||^2; a column gets a second pass only when its norm after the
+      // first, estimated as ||w||^2 - sum_i h_i^2, fell below 1/sqrt(2) of
+      // it (the reorthogonalisation test of Daniel, Gragg, Kaufman and
+      // Stewart); the others are orthogonal to working accuracy already.
       const int J = j + 1;
       std::vector<double> hsum((size_t)k * J, 0.0);
+      std::vector<int> redo(k, 0);
       for (int rep = 0; rep < 2; ++rep) {
-        hipLaunchKernelGGL(k_gm_multidot<T>, dim3(nb, k), dim3(256), 0, ctx->stream, n, J, V.get(), ld, bstride,
-                           w.get(), ld, act.get(), part.get(), nb);
+        const int self = rep == 0 ? 1 : 0, Jo = J + self;
+        if (rep == 1) {
+          if (std::none_of(redo.begin(), redo.end(), [](int v) { return v != 0; })) break;
+          h2d(ctx, act.get(), redo.data(), k * sizeof(int));
+        }
+        hipLaunchKernelGGL(k_gm_multidot<T>, dim3(nb, k), dim3(256), (size_t)Jo * 4 * sizeof(double), ctx->stream,
+                           n, J, self, V.get(), ld, bstride, w.get(), ld, act.get(), part.get(), nb);
         KERNEL_CHECK();
-        hipLaunchKernelGGL(k_gm_reduce, dim3(ceil_div(k * J, 256)), dim3(256), 0, ctx->stream, k * J, nb,
+        hipLaunchKernelGGL(k_gm_reduce, dim3(ceil_div(k * Jo, 4)), dim3(256), 0, ctx->stream, k * Jo, nb,
                            part.get(), hdev.get());
         KERNEL_CHECK();
         hipLaunchKernelGGL(k_gm_multiaxpy<T>, gcol, dim3(256), 0, ctx->stream, n, J, V.get(), ld, bstride,
-                           hdev.get(), -1.0, w.get(), ld, act.get());
+                           hdev.get(), Jo, -1.0, w.get(), ld, act.get());
         KERNEL_CHECK();
-        hv.resize((size_t)k * J);
+        hv.resize((size_t)k * Jo);
         d2h(ctx, hv.data(), hdev.get(), hv.size() * sizeof(double));
-        for (size_t e = 0; e < hv.size(); ++e) hsum[e] += hv[e];
+        for (int c = 0; c < k; ++c) {
+          if (!(rep == 0 ? hact[c] : redo[c])) continue;
+          double h2 = 0.0;
+          for (int i = 0; i < J; ++i) {
+            const double h = hv[(size_t)c * Jo + i];
+            hsum[(size_t)c * J + i] += h;
+            h2 += h * h;
+          }
+          if (rep == 0) {
+            const double w2 = hv[(size_t)c * Jo + J];
+            redo[c] = (w2 - h2 < 0.5 * w2) ? 1 : 0;
+          }
+        }
+        if (rep == 1) h2d(ctx, act.get(), hact.data(), k * sizeof(int));
       }
       std::vector<double> wn2;
       {
         // ||w_c||^2 over the active columns
-        hipLaunchKernelGGL(k_gm_multidot<T>, dim3(nb, k), dim3(256), 0, ctx->stream, n, 1, w.get(), ld, (int64_t)0,
-                           w.get(), ld, act.get(), part.get(), nb);
+        hipLaunchKernelGGL(k_gm_multidot<T>, dim3(nb, k), dim3(256), 4 * sizeof(double), ctx->stream, n, 0, 1,
+                           w.get(), ld, (int64_t)0, w.get(), ld, act.get(), part.get(), nb);
         KERNEL_CHECK();
-        hipLaunchKernelGGL(k_gm_reduce, dim3(ceil_div(k, 256)), dim3(256), 0, ctx->stream, k, nb, part.get(),
+        hipLaunchKernelGGL(k_gm_reduce, dim3(ceil_div(k, 4)), dim3(256), 0, ctx->stream, k, nb, part.get(),
                            hdev.get());
         KERNEL_CHECK();
         wn2.resize(k);
@@ -276,13 +313,13 @@ KrylovResult gmres(Ctx* ctx, const SellOp& op, double pr, int ncols, const T* b,
       // x += P^{-1} (V y): columns without an update stay zero in zt
       dzero(ctx, zt.get(), (size_t)bstride * sizeof(T));
       hipLaunchKernelGGL(k_gm_multiaxpy<T>, gcol, dim3(256), 0, ctx->stream, n, J, V.get(), ld, bstride,
-                         hdev.get(), 1.0, zt.get(), ld, act.get());
+                         hdev.get(), J, 1.0, zt.get(), ld, act.get());
       KERNEL_CHECK();
       ilu_apply<T>(ctx, op, *pre, k, zt.get(), ld, w.get(), ld);
       axpby<T>(ctx, n, k, 1.0, w.get(), ld, 1.0, x, ldx);
     } else {
       hipLaunchKernelGGL(k_gm_multiaxpy<T>, gcol, dim3(256), 0, ctx->stream, n, J, V.get(), ld, bstride,
-                         hdev.get(), 1.0, x, ldx, act.get());
+                         hdev.get(), J, 1.0, x, ldx, act.get());
       KERNEL_CHECK();
     }
     // true residual for the next cycle (and the report)

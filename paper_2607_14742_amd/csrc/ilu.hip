@@ -47,7 +47,7 @@ namespace {
 
 constexpr int ILU_MAX_COLOURS = 1024;
 constexpr int ILU_NT = 256;
-constexpr int ILU_KC = 4;            // right-hand-side columns per thread in the solves
+constexpr int ILU_KC = 8;            // right-hand-side columns per thread in the solves
 constexpr size_t ILU_CACHE = 64;     // factorisations kept per operator
 
 // One colour of the factorisation: thread t factors row rows[t].

@@ -242,6 +242,8 @@ void rb_attach(Ctx* ctx, const std::shared_ptr<RbHost>& h, Prec prec, SellOp& op
   g.col_idx = gci.get();
   g.val = gv.get();
   build_sell(ctx, &g, prec, rb->G);
+  // the preconditioned GMRES solves run on the reduced system: ILU(0) of G + p' I
+  if (ctx->krylov_precond && ctx->krylov_method == 1) ilu_attach(ctx, ilu_analyse(ctx, &g), rb->G);
   ctx->sync();
   op.rb = rb;
 }
