@@ -17,6 +17,10 @@ of the Krylov chunks).  After them:
   * one extra FP32-inner solve in which every sparse-product launch records
     HIP events at its own start and end (hipExtLaunchKernelGGL, on the
     library's stream) gives the roofline object;
+  * both precisions are timed once more with the paper's inner solver,
+    restarted GMRES right-preconditioned by ILU(0) of A^T + p I
+    ("paper_inner_solver"; the production path runs BiCGStab on the exact
+    red-black reduction instead);
   * the CPU oracle is timed on a bounded sample of the same workload.
 
 `--workload toeplitz --n N` times the Toeplitz example of Sec. 5.2 instead
@@ -64,6 +68,9 @@ def parse():
     ap.add_argument("--n", type=int, default=131072, help="toeplitz matrix size")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison solves")
     ap.add_argument("--no-xgate", action="store_true", help="skip the tol 1e-12 solves")
+    ap.add_argument("--no-paper-solver", action="store_true",
+                    help="skip the two solves with the paper's inner solver (GMRES + ILU(0)); "
+                         "--no-fp64 skips them too")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-shifts", type=int, default=12)
     ap.add_argument("--dense-sweep", action="store_true",
@@ -370,11 +377,11 @@ def main():
     C = torch.as_tensor(P.C, device=dev)
     m, p = P.B.shape[1], P.C.shape[0]
 
-    def solve(prec, profile, tol=TOL):
+    def solve(prec, profile, tol=TOL, **kw):
         torch.cuda.synchronize()
         t = time.perf_counter()
         Z, stats, st = pk.care_solve(ctx, A, B, C, tol=tol, shifts=shifts, prec=prec, profile=profile,
-                                     rmax=2048)
+                                     rmax=2048, **kw)
         torch.cuda.synchronize()
         return time.perf_counter() - t, Z, stats, st
 
@@ -439,6 +446,20 @@ def main():
             del Zx64
         del Zx
         res["xgate"] = xg
+    if not args.no_paper_solver and not args.no_fp64:
+        # the inner solver of the paper's GPU runs: restarted GMRES (30 / 50)
+        # right-preconditioned by ILU(0) of A^T + p I (multicolour order, no
+        # red-black reduction); one solve per precision, factorisations included
+        ps = {"method": "GMRES(30 FP32 / 50 FP64) + ILU(0) of A^T + p I, full system"}
+        kw = dict(krylov_method=1, krylov_rb=0, krylov_precond=1)
+        for prec in ("fp32", "fp64"):
+            el, Zp, sp_, stp = solve(prec, 0, **kw)
+            ps["fp32_inner" if prec == "fp32" else "fp64"] = {
+                "status": stp, "solve_s": round(el, 4), "relres": sp_["res_rel"],
+                "iter": f"{sp_['iter_outer']}({sp_['iter_inner']})", "krylov_column_iters": sp_["krylov_iters"]}
+            del Zp
+        ps["speedup_fp32_inner_vs_fp64"] = round(ps["fp64"]["solve_s"] / ps["fp32_inner"]["solve_s"], 3)
+        res["paper_inner_solver"] = ps
 
     # roofline: one more FP32-inner solve in which every sparse-product launch
     # records HIP events at its own start and end on the library's stream
