@@ -175,3 +175,30 @@ def test_ilu0_zero_pivot_and_bad_arguments(pk, ctx):
     with pytest.raises(pk.CareError):
         pk.care_solve(ctx, Bd, dev(np.ones((36, 1))), dev(np.ones((1, 36))), tol=1e-10, shifts=[-1.0],
                       krylov_method=1, krylov_precond=2)
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16", 2e-2), ("fp16", 2e-3)])
+@pytest.mark.parametrize("case", ["fdm2d_30", "toeplitz_700"])
+def test_ilu0_with_16_bit_operator_values(pk, ctx, case, prec, tol):
+    """FP32 factors of the operator whose off-diagonal values are held in
+    bf16 or (scaled) fp16: against the oracle's FP64 ILU(0) of the unrounded
+    matrix, within the value format's rounding (bf16 2^-9, fp16 2^-12 per
+    value, through a few multiply-adds per entry; the bounds of the sparse
+    product's parity test)."""
+    A, p = CASES[case]()
+    n = A.shape[0]
+    print(f"ILU(0) {case} {prec}", flush=True)
+    Ad = pk.DeviceCSR.from_scipy(A)
+    colours, off, udiag = pk.ilu0_factor(ctx, Ad, p, prec=prec)
+    f = ilu.ShiftedIlu0(A, p)
+    assert np.array_equal(colours, f.colours)
+    eo, ed = f.entries(A.T.tocsr())
+    scale = max(np.abs(eo).max(initial=0.0), np.abs(ed).max())
+    assert np.abs(off - eo).max(initial=0.0) <= tol * scale
+    assert np.abs(udiag - ed).max() <= tol * scale
+    X = RNG.standard_normal((n, 5))
+    Z = pk.ilu0_apply(ctx, Ad, dev(X), p, prec=prec).cpu().numpy()
+    Zo = f.apply(X)
+    err = np.linalg.norm(Z - Zo) / np.linalg.norm(Zo)
+    print(f"  apply relative error {err:.2e}", flush=True)
+    assert err <= 5.0 * tol
