@@ -65,6 +65,7 @@ def parse():
                     help="fdm2d: the 2D FDM problem (default); toeplitz: the Toeplitz example of Sec. 5.2; "
                          "fdm_batch: the 32-instance uneven FDM batch")
     ap.add_argument("--N", type=int, default=500, help="fdm2d grid size (500 -> n = 250000)")
+    ap.add_argument("--batch-workers", type=int, default=4, help="fdm_batch: concurrent worker streams")
     ap.add_argument("--n", type=int, default=131072, help="toeplitz matrix size")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison solves")
     ap.add_argument("--no-xgate", action="store_true", help="skip the tol 1e-12 solves")
@@ -171,7 +172,8 @@ def dense_sweep(pk, wl, torch, np):
 
 def fdm_batch_bench(args, pk, wl, torch, np):
     """One JSON line for the 32-instance uneven FDM batch: wall time of one
-    batched care_solve_batch call (4 worker streams) per precision."""
+    batched care_solve_batch call (--batch-workers worker streams) per
+    precision."""
     count = 32
     probs = [wl.fdm_batch_problem(i, count) for i in range(count)]
     dev = "cuda:0"
@@ -184,7 +186,7 @@ def fdm_batch_bench(args, pk, wl, torch, np):
         for it in range(args.warmup + args.steps):
             torch.cuda.synchronize()
             t = time.perf_counter()
-            out = pk.care_solve_batch(ctx, items, tol=TOL, prec=prec, workers=4)
+            out = pk.care_solve_batch(ctx, items, tol=TOL, prec=prec, workers=args.batch_workers)
             torch.cuda.synchronize()
             if it >= args.warmup:
                 times.append(time.perf_counter() - t)
@@ -204,7 +206,7 @@ def fdm_batch_bench(args, pk, wl, torch, np):
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"uneven 2D FDM batch: {count} instances, n {probs[0].n}..{probs[-1].n}, "
                                   f"{sum(P.A.nnz for P in probs)} nonzeros in all, (m, p) in 1..8, "
-                                  "12 Wachspress shifts each, 4 worker streams, FP32 inner / FP64 refine, "
+                                  f"12 Wachspress shifts each, {args.batch_workers} worker streams, FP32 inner / FP64 refine, "
                                   f"tol {TOL:g}"},
            "fp32_inner": r32}
     if not args.no_fp64:
