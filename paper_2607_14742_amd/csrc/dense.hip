@@ -126,21 +126,27 @@ __global__ void __launch_bounds__(256) k_gram(int64_t n, const TX* __restrict__ 
   }
 }
 
-// C(i, j) = sum over splits (fixed order); symmetric: mirror the upper tiles
-__global__ void k_gram_reduce(const double* __restrict__ part, int ntl, int nsplit, const int* __restrict__ tile_list,
-                              int tiles_j, int a, int b, int sym, double* __restrict__ C, int64_t ldc) {
+// C(i, j) = sum over splits (fixed order); symmetric: mirror the upper tiles.
+// Grid (tiles, 4): one thread per element of a 32 x 32 tile; the split loop
+// is unrolled so that several partials are in flight while the sum keeps its
+// order.
+__global__ void __launch_bounds__(256) k_gram_reduce(const double* __restrict__ part, int ntl, int nsplit,
+                                                     const int* __restrict__ tile_list, int tiles_j, int a, int b,
+                                                     int sym, double* __restrict__ C, int64_t ldc) {
   const int tl = blockIdx.x;
   const int tcode = tile_list ? tile_list[tl] : tl;
   const int ti = tcode / tiles_j, tj = tcode % tiles_j;
-  for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
-    const int ii = e >> 5, jj = e & 31;
-    const int i = ti * 32 + ii, j = tj * 32 + jj;
-    if (i >= a || j >= b) continue;
-    double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) s += part[((int64_t)sp * ntl + tl) * 1024 + e];
-    C[(int64_t)j * ldc + i] = s;
-    if (sym && ti != tj) C[(int64_t)i * ldc + j] = s;
-  }
+  const int e = blockIdx.y * 256 + threadIdx.x;
+  const int ii = e >> 5, jj = e & 31;
+  const int i = ti * 32 + ii, j = tj * 32 + jj;
+  if (i >= a || j >= b) return;
+  const double* p = part + (int64_t)tl * 1024 + e;
+  const int64_t stride = (int64_t)ntl * 1024;
+  double s = 0.0;
+#pragma unroll 8
+  for (int sp = 0; sp < nsplit; ++sp) s += p[sp * stride];
+  C[(int64_t)j * ldc + i] = s;
+  if (sym && ti != tj) C[(int64_t)i * ldc + j] = s;
 }
 
 // C(i, j) = sum_s W_s(i, j), s = 0 .. nsplit-1 in order (W_s: a x b, ld a);
@@ -297,6 +303,7 @@ __global__ void k_gram128_reduce(const double* __restrict__ part, int ntl, int n
   const int tl = sym ? I * ti - I * (I - 1) / 2 + (J - I) : I * tj + J;
   const int64_t o = (int64_t)(sj & 127) * 128 + (si & 127);
   double s = 0.0;
+#pragma unroll 8
   for (int sp = 0; sp < nsplit; ++sp) s += part[((int64_t)sp * ntl + tl) * (128 * 128) + o];
   C[(int64_t)j * ldc + i] = s;
 }
@@ -396,8 +403,8 @@ void gram(Ctx* ctx, int64_t n, const TX* X, int64_t ldx, int a, const TY* Y, int
   hipLaunchKernelGGL((k_gram<TX, TY>), dim3(ntl, nsplit), dim3(256), 0, ctx->stream, n, X, ldx, a, Y, ldy, b, tiles_j,
                      rps, dtl.get(), part.get());
   KERNEL_CHECK();
-  hipLaunchKernelGGL(k_gram_reduce, dim3(ntl), dim3(256), 0, ctx->stream, part.get(), ntl, nsplit, dtl.get(), tiles_j,
-                     a, b, sym ? 1 : 0, C, ldc);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(ntl, 4), dim3(256), 0, ctx->stream, part.get(), ntl, nsplit, dtl.get(),
+                     tiles_j, a, b, sym ? 1 : 0, C, ldc);
   KERNEL_CHECK();
 }
 
@@ -424,7 +431,7 @@ bool gram_own_into(Ctx* ctx, int64_t n, const double* X, int64_t ldx, int a, con
   hipLaunchKernelGGL((k_gram<double, double>), dim3((unsigned)ntl, (unsigned)nsplit), dim3(256), 0, ctx->stream, n, X,
                      ldx, a, Y, ldy, b, tiles_j, rps, (const int*)nullptr, part);
   KERNEL_CHECK();
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)ntl), dim3(256), 0, ctx->stream, (const double*)part, (int)ntl,
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)ntl, 4), dim3(256), 0, ctx->stream, (const double*)part, (int)ntl,
                      (int)nsplit, (const int*)nullptr, tiles_j, a, b, 0, C, ldc);
   KERNEL_CHECK();
   return true;
