@@ -31,7 +31,9 @@ counter traffic.
 `--workload fdm_batch` times the uneven batch of 32 2D FDM CAREs (grids
 N = 100 ... 632, n = 1e4 ... 4e5, (m, p) from {1..8}) solved in one batched
 call on concurrent worker streams, FP32 inner vs FP64, and prints its own
-line (a step is one batched solve of all 32).
+line (a step is one batched solve of all 32).  `--workload dense_batch` does
+the same for the 64 dense CAREs (n = 256 ... 2048, kappa_2(A) = 1e2 ... 1e12,
+LU shifted solves), with the count of instances that met the tolerance.
 """
 from __future__ import annotations
 
@@ -61,9 +63,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("fdm2d", "toeplitz", "fdm_batch"), default="fdm2d",
+    ap.add_argument("--workload", choices=("fdm2d", "toeplitz", "fdm_batch", "dense_batch"), default="fdm2d",
                     help="fdm2d: the 2D FDM problem (default); toeplitz: the Toeplitz example of Sec. 5.2; "
-                         "fdm_batch: the 32-instance uneven FDM batch")
+                         "fdm_batch: the 32-instance uneven FDM batch; dense_batch: the 64-instance dense batch")
     ap.add_argument("--N", type=int, default=500, help="fdm2d grid size (500 -> n = 250000)")
     ap.add_argument("--batch-workers", type=int, default=4, help="fdm_batch: concurrent worker streams")
     ap.add_argument("--n", type=int, default=131072, help="toeplitz matrix size")
@@ -217,6 +219,66 @@ def fdm_batch_bench(args, pk, wl, torch, np):
     print(json.dumps(res))
 
 
+def dense_batch_bench(args, pk, wl, torch, np):
+    """One JSON line for the 64-instance uneven dense batch (n 256 ... 2048,
+    kappa_2(A) = 1e2 ... 1e12, m = p = 4, 16 log-spaced real shifts each):
+    wall time of one batched care_solve_batch call per precision, with the
+    count of instances that met the tolerance.  Beyond kappa ~ 1e6.5 no FP64
+    method reaches tol 1e-10 (the solver stops on stagnation at the oracle's
+    level), and from kappa ~ 1e8 the FP32 inner solves fail, as in Table 1."""
+    count = 64
+    dev = "cuda:0"
+    items, kappas = [], []
+    for i in range(count):
+        A, B, C, q = wl.dense_instance(i, count)
+        items.append((torch.as_tensor(A, device=dev), torch.as_tensor(B, device=dev),
+                      torch.as_tensor(C, device=dev), wl.logspaced_real_shifts(1.0, 10.0 ** q, 16)))
+        kappas.append(10.0 ** q)
+    ctx = pk.Context(0)
+
+    def run(prec):
+        times, last = [], None
+        for it in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = pk.care_solve_batch(ctx, items, tol=TOL, prec=prec, workers=args.batch_workers)
+            torch.cuda.synchronize()
+            if it >= args.warmup:
+                times.append(time.perf_counter() - t)
+            last = out
+        ok = [i for i, (_, s_, st, _) in enumerate(last) if st == 0 and s_["res_rel"] <= TOL]
+        stag = sum(1 for _, _, st, _ in last if st == 1)
+        worst_ok = max((last[i][1]["res_rel"] for i in ok), default=None)
+        print(f"[bench] dense_batch {prec}: {np.mean(times):.3f} s, {len(ok)} of {count} at tol",
+              file=sys.stderr, flush=True)
+        return {"mean_s": round(float(np.mean(times)), 4), "solve_s": [round(t, 4) for t in times],
+                "instances_at_tol": len(ok), "stagnated": stag, "other_status": count - len(ok) - stag,
+                "worst_relres_at_tol": worst_ok,
+                "largest_kappa_at_tol": max((kappas[i] for i in ok), default=None)}
+
+    r32 = run("fp32")
+    res = {"metric": "CARE batch solve time, 64 dense instances, at rel residual <=1e-10",
+           "value": r32["mean_s"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * r32["mean_s"], 2), "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"uneven dense batch: {count} instances, n in {sorted(set(wl.DENSE_SIZES))}, "
+                                  "A = -Q diag(logspace(0, q, n)) Q^T with kappa_2 = 10^q, q = 2 ... 12, "
+                                  "m = p = 4, 16 log-spaced real shifts each, LU shifted solves, "
+                                  f"{args.batch_workers} worker streams, FP32 inner / FP64 refine, tol {TOL:g}"},
+           "fp32_inner": r32}
+    if not args.no_fp64:
+        r64 = run("fp64")
+        res["fp64"] = r64
+        res["speedup_fp32_inner_vs_fp64"] = round(r64["mean_s"] / r32["mean_s"], 3)
+        # the a-priori choice of the inner precision per instance (FP32 where
+        # the estimate of kappa_F(L) u_32 allows it, FP64 elsewhere)
+        ra = run("auto")
+        res["auto"] = ra
+        res["speedup_auto_vs_fp64"] = round(r64["mean_s"] / ra["mean_s"], 3)
+    ctx.close()
+    print(json.dumps(res))
+
+
 def measured_traffic():
     """(bytes per launch, note) from the committed counter summary, or
     (None, reason) when it is missing or was taken on other kernel source."""
@@ -346,6 +408,9 @@ def main():
 
     if args.workload == "fdm_batch":
         fdm_batch_bench(args, pk, wl, torch, np)
+        return
+    if args.workload == "dense_batch":
+        dense_batch_bench(args, pk, wl, torch, np)
         return
 
     dev = "cuda:0"
