@@ -15,7 +15,10 @@ ABI, against the oracle (oracle/ilu.py, oracle/adi.py).
 * shifted solves (with and without SMW) with the preconditioned GMRES against
   the oracle's sparse direct solve, and fewer Arnoldi steps than without the
   preconditioner;
-* a CARE solved with the paper's inner solver against the Schur solution;
+* a CARE solved with the paper's inner solver against the Schur solution,
+  the same option through the batched entry point, and with a conjugate
+  shift pair (which keeps BiCGStab);
+* 16-bit operator values (bf16, scaled fp16) within their rounding;
 * a zero pivot and bad arguments are reported as errors."""
 import ctypes as C
 
@@ -202,3 +205,38 @@ def test_ilu0_with_16_bit_operator_values(pk, ctx, case, prec, tol):
     err = np.linalg.norm(Z - Zo) / np.linalg.norm(Zo)
     print(f"  apply relative error {err:.2e}", flush=True)
     assert err <= 5.0 * tol
+
+
+def test_ilu_gmres_in_a_batch_matches_single_solves(pk, ctx):
+    """The option travels through the batched entry point: three FDM CAREs
+    with the paper's inner solver on concurrent worker streams give the
+    factors of the same solves run one at a time (same arithmetic per
+    instance, so the same solution to the solve's tolerance)."""
+    probs = [wl.fdm2d_problem(N, 2, 2) for N in (16, 21, 27)]
+    kw = dict(krylov_method=1, krylov_rb=0, krylov_precond=1)
+    items = [(pk.DeviceCSR.from_scipy(P.A), dev(P.B), dev(P.C), P.shifts) for P in probs]
+    out = pk.care_solve_batch(ctx, items, tol=1e-11, prec="fp32", workers=3, **kw)
+    for P, it, (Zb, sb, stb, msg) in zip(probs, items, out):
+        print(f"batch n={P.n}: status {stb} relres {sb['res_rel']:.2e}", flush=True)
+        assert stb == 0, msg
+        Zs, ss, sts = pk.care_solve(ctx, it[0], it[1], it[2], tol=1e-11, shifts=P.shifts, prec="fp32", **kw)
+        assert sts == 0
+        Zb, Zs = Zb.cpu().numpy(), Zs.cpu().numpy()
+        assert lowrank.residual_norm(P.A, P.B, P.C, Zb) <= 1e-10 * np.linalg.norm(P.C @ P.C.T)
+        assert lowrank.factored_diff_norm(Zb, Zs) <= 1e-8 * lowrank.factored_norm(Zs)
+
+
+def test_ilu_gmres_with_complex_pairs_keeps_bicgstab_for_them(pk, ctx):
+    """Heuristic shifts of the rotating-field 3D problem include a conjugate
+    pair: with GMRES + ILU(0) requested, the real shifts take it and the
+    pair runs BiCGStab; the CARE still meets the gate."""
+    P = wl.fdm3d_problem(10, 1, 3)
+    A = pk.DeviceCSR.from_scipy(P.A)
+    sh = pk.penzl_shifts(ctx, A)
+    assert np.any(np.abs(sh.imag) > 0)
+    Z, stats, st = pk.care_solve(ctx, A, dev(P.B), dev(P.C), tol=1e-11, shifts=sh, prec="fp64", krylov_method=1,
+                                 krylov_rb=0, krylov_precond=1)
+    assert st == 0, stats
+    rel = lowrank.residual_norm(P.A, P.B, P.C, Z.cpu().numpy()) / np.linalg.norm(P.C @ P.C.T)
+    print(f"3D complex pair with ILU-GMRES: relres {rel:.2e}", flush=True)
+    assert rel <= 1e-11
