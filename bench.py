@@ -23,6 +23,11 @@ of the Krylov chunks).  After them:
     red-black reduction instead);
   * the CPU oracle is timed on a bounded sample of the same workload.
 
+`--workload fdm3d` times the 64^3 rotating-field problem (n = 262,144, m = 1,
+p = 10, the oracle golden's shift set with one conjugate pair), FP32 inner vs
+FP64, and adds one solve each with bf16 and scaled fp16 operator values, all
+against the oracle's samples of X.
+
 `--workload toeplitz --n N` times the Toeplitz example of Sec. 5.2 instead
 (B n x 10 with ||B||_F = 1, C 5 x n, one heuristic shift set shared by both
 precisions); its line carries no CPU baseline, no oracle X samples and no
@@ -53,6 +58,7 @@ METRIC = "CARE solve time & SpMM HBM GB/s: FP32-inner vs FP64, at rel residual <
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_spmm_fdm2d_500_fp32_hbm_counters.md")
 KERNEL_SOURCES = ("paper_2607_14742_amd/csrc/spmm_kernel.hpp", "paper_2607_14742_amd/csrc/sparse.hip")
 GOLDEN = os.path.join(ROOT, "tests", "golden", "config2_x_samples.json")
+GOLDEN3 = os.path.join(ROOT, "tests", "golden", "config3_x_samples.json")
 HBM_PEAK_GBS = 8000.0
 TOL = 1e-10
 TOL_XGATE = 1e-12
@@ -63,8 +69,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("fdm2d", "toeplitz", "fdm_batch", "dense_batch"), default="fdm2d",
-                    help="fdm2d: the 2D FDM problem (default); toeplitz: the Toeplitz example of Sec. 5.2; "
+    ap.add_argument("--workload", choices=("fdm2d", "fdm3d", "toeplitz", "fdm_batch", "dense_batch"), default="fdm2d",
+                    help="fdm2d: the 2D FDM problem (default); fdm3d: the 64^3 rotating-field problem "
+                         "(FP32 inner vs FP64, and bf16 / fp16 products); toeplitz: the Toeplitz example of Sec. 5.2; "
                          "fdm_batch: the 32-instance uneven FDM batch; dense_batch: the 64-instance dense batch")
     ap.add_argument("--N", type=int, default=500, help="fdm2d grid size (500 -> n = 250000)")
     ap.add_argument("--batch-workers", type=int, default=4, help="fdm_batch: concurrent worker streams")
@@ -432,6 +439,15 @@ def main():
                  f"{len(shifts)} Wachspress real shifts, FP32 inner / FP64 refine, tol {TOL:g}")
         if args.N == 500 and os.path.exists(GOLDEN):
             golden = json.load(open(GOLDEN))
+    elif args.workload == "fdm3d":
+        # the 64^3 rotating-field problem with the shift set the oracle's
+        # golden was computed with (heuristic shifts, one conjugate pair)
+        P = wl.config3()
+        A = pk.DeviceCSR.from_scipy(P.A, dev)
+        golden = json.load(open(GOLDEN3))
+        shifts = np.array(golden["shifts"]["re"]) + 1j * np.array(golden["shifts"]["im"])
+        wdesc = (f"3D convection-diffusion FDM 64^3 with a rotating field (n={P.n}, nnz={P.A.nnz}), m=1, p=10, "
+                 f"{len(shifts)} heuristic shifts (one conjugate pair), FP32 inner / FP64 refine, tol {TOL:g}")
     else:
         # the paper generates its shifts from Krylov subspaces: one heuristic
         # set (GPU Arnoldi, before the timed region) serves both precisions
@@ -527,6 +543,13 @@ def main():
             del Zp
         ps["speedup_fp32_inner_vs_fp64"] = round(ps["fp64"]["solve_s"] / ps["fp32_inner"]["solve_s"], 3)
         res["paper_inner_solver"] = ps
+    if args.workload == "fdm3d":
+        # FP32 inner solves whose products read A's values in bf16 or in
+        # scaled fp16 (one solve each, errors against the oracle's samples)
+        for prec in ("bf16", "fp16"):
+            el, Zh, sh_, sth = solve(prec, 0)
+            res[prec + "_products"] = summary([el], sth, sh_, Zh)
+            del Zh
 
     # roofline: one more FP32-inner solve in which every sparse-product launch
     # records HIP events at its own start and end on the library's stream
@@ -569,7 +592,7 @@ def main():
         # context only: the paper's V100 times for this example (n = 131072:
         # FP64 92.07 s, FP32 63.44 s; ILU(0)-GMRES, another machine)
         res["paper_context"] = "Sec. 5.2 Toeplitz table, one V100, n = 131072: FP64 92.07 s, FP32-inner 63.44 s"
-    elif not args.no_cpu_baseline and args.N == 500:
+    elif args.workload == "fdm2d" and not args.no_cpu_baseline and args.N == 500:
         res["cpu_baseline"] = cpu_baseline(P, args.cpu_sample_shifts)
     print(json.dumps(res))
 
