@@ -388,7 +388,7 @@ def cpu_baseline(P, nshift_sample):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; runs on several GPUs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
