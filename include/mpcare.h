@@ -362,6 +362,14 @@ care_status care_shifted_solve_opts(care_ctx* ctx, const care_csr* A, const doub
 care_status care_ilu0_factor(care_ctx* ctx, const care_csr* A, int32_t prec, double p, int32_t* colours,
                              double* off, int64_t noff, double* udiag);
 
+/* The colouring that orders care_ilu0_factor's unknowns, on its own: first-
+ * fit in natural row order over the undirected graph of the off-diagonal
+ * entries of A (a_ij or a_ji nonzero).  row_ptr, col_idx: HOST CSR pattern of
+ * A (n + 1 and nnz int32, checked here); colours: HOST, n entries; ncolours:
+ * HOST.  Needs no device.  CARE_ERR_NOT_IMPLEMENTED past 1024 colours. */
+care_status care_ilu0_colouring(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                                int32_t* colours, int32_t* ncolours);
+
 /* Z = (L U)^{-1} X with the factors of care_ilu0_factor (the preconditioner
  * solve: one forward and one backward sweep, each one parallel step per
  * colour).  X, Z: device FP64, n x k column-major (ldx, ldz >= n), X rounded

@@ -94,6 +94,7 @@ SIGNATURES = {
                                  I32, P, I64, PI32]),
     "care_shifted_solve_opts": (I32, [P, C.POINTER(care_csr), P, I64, P, I64, I32, care_shift, P, I64, I32, I32,
                                       DBL, I32, C.POINTER(care_opts), P, I64, PI32]),
+    "care_ilu0_colouring": (I32, [I64, I64, PI32, PI32, PI32, PI32]),
     "care_ilu0_factor": (I32, [P, C.POINTER(care_csr), I32, DBL, PI32, PDBL, I64, PDBL]),
     "care_ilu0_apply": (I32, [P, C.POINTER(care_csr), I32, DBL, P, I64, I32, P, I64]),
     "care_gram": (I32, [P, I64, P, I64, I32, P, I64, I32, P, I64]),

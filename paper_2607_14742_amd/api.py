@@ -276,6 +276,21 @@ def ilu0_factor(ctx, A, shift, prec="fp64"):
     return colours, off[:noff], udiag
 
 
+def ilu0_colouring(A):
+    """The library's first-fit colouring of a host sparse matrix's pattern
+    (host-only call, no device): returns (colours, number of colours)."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix(A)
+    rp = np.ascontiguousarray(A.indptr, dtype=np.int32)
+    ci = np.ascontiguousarray(A.indices, dtype=np.int32)
+    colours = np.zeros(A.shape[0], dtype=np.int32)
+    nc = C.c_int32(0)
+    p32 = C.POINTER(C.c_int32)
+    _check(_lib().care_ilu0_colouring(A.shape[0], A.nnz, rp.ctypes.data_as(p32), ci.ctypes.data_as(p32),
+                                      colours.ctypes.data_as(p32), C.byref(nc)))
+    return colours, nc.value
+
+
 def ilu0_apply(ctx, A, X, shift, prec="fp64"):
     """Z = (L U)^{-1} X with the ILU(0) factors of A^T + p I."""
     X = colmajor(X)

@@ -723,6 +723,18 @@ care_status care_solve_batch(care_ctx* cx, int32_t count, const care_instance* i
   });
 }
 
+care_status care_ilu0_colouring(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                                int32_t* colours, int32_t* ncolours) {
+  return guarded([&]() -> care_status {
+    if (!colours || !ncolours) fail(CARE_ERR_ARG, "output pointer is NULL");
+    std::vector<int> col;
+    const int nc = ilu_colour_host(n, nnz, row_ptr, col_idx, col);
+    for (int64_t i = 0; i < n; ++i) colours[i] = col[i];
+    *ncolours = nc;
+    return CARE_OK;
+  });
+}
+
 care_status care_ritz_values(const double* H, int32_t k, int64_t ldh, double* re, double* im) {
   return guarded([&]() -> care_status {
     if (k < 0 || (k > 0 && (!H || ldh < k || !re || !im))) fail(CARE_ERR_ARG, "invalid Hessenberg arguments");

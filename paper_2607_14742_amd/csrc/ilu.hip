@@ -200,12 +200,13 @@ void factor_launch(Ctx* ctx, const SellOp& op, const IluOp& il, double p, IluOp:
 
 }  // namespace
 
-std::shared_ptr<IluHost> ilu_analyse(Ctx* ctx, const care_csr* A) {
-  if (!A || A->n < 1) return nullptr;
-  const int64_t n = A->n, nnz = A->nnz;
-  std::vector<int> rp(n + 1), ci(std::max<int64_t>(nnz, 1));
-  d2h(ctx, rp.data(), A->row_ptr, (n + 1) * sizeof(int));
-  if (nnz) d2h(ctx, ci.data(), A->col_idx, nnz * sizeof(int));
+int ilu_colour_host(int64_t n, int64_t nnz, const int* rp, const int* ci, std::vector<int>& colour) {
+  if (n < 1 || nnz < 0 || !rp || (nnz > 0 && !ci)) fail(CARE_ERR_ARG, "invalid CSR pattern");
+  if (rp[0] != 0 || rp[n] != nnz) fail(CARE_ERR_ARG, "CSR row_ptr must start at 0 and end at nnz");
+  for (int64_t i = 0; i < n; ++i)
+    if (rp[i + 1] < rp[i]) fail(CARE_ERR_ARG, "CSR row_ptr is not monotone");
+  for (int64_t e = 0; e < nnz; ++e)
+    if (ci[e] < 0 || ci[e] >= n) fail(CARE_ERR_ARG, "CSR column index out of range");
   // rows of A^T (the other direction of each edge)
   std::vector<int> tp(n + 1, 0), tc(std::max<int64_t>(nnz, 1));
   for (int64_t e = 0; e < nnz; ++e) tp[ci[e] + 1] += 1;
@@ -215,14 +216,12 @@ std::shared_ptr<IluHost> ilu_analyse(Ctx* ctx, const care_csr* A) {
     for (int64_t i = 0; i < n; ++i)
       for (int e = rp[i]; e < rp[i + 1]; ++e) tc[fill[ci[e]]++] = (int)i;
   }
-  auto h = std::make_shared<IluHost>();
-  h->n = n;
-  h->colour.assign(n, -1);
+  colour.assign(n, -1);
   std::vector<int64_t> stamp(ILU_MAX_COLOURS + 1, -1);
   int ncol = 0;
   for (int64_t i = 0; i < n; ++i) {
     auto mark = [&](int j) {
-      if (j != i && h->colour[j] >= 0) stamp[h->colour[j]] = i;
+      if (j != i && colour[j] >= 0) stamp[colour[j]] = i;
     };
     for (int e = rp[i]; e < rp[i + 1]; ++e) mark(ci[e]);
     for (int e = tp[i]; e < tp[i + 1]; ++e) mark(tc[e]);
@@ -230,9 +229,21 @@ std::shared_ptr<IluHost> ilu_analyse(Ctx* ctx, const care_csr* A) {
     while (stamp[c] == i) ++c;
     if (c >= ILU_MAX_COLOURS)
       fail(CARE_ERR_NOT_IMPLEMENTED, "ILU(0): the pattern needs more than 1024 colours");
-    h->colour[i] = c;
+    colour[i] = c;
     ncol = std::max(ncol, c + 1);
   }
+  return ncol;
+}
+
+std::shared_ptr<IluHost> ilu_analyse(Ctx* ctx, const care_csr* A) {
+  if (!A || A->n < 1) return nullptr;
+  const int64_t n = A->n, nnz = A->nnz;
+  std::vector<int> rp(n + 1), ci(std::max<int64_t>(nnz, 1));
+  d2h(ctx, rp.data(), A->row_ptr, (n + 1) * sizeof(int));
+  if (nnz) d2h(ctx, ci.data(), A->col_idx, nnz * sizeof(int));
+  auto h = std::make_shared<IluHost>();
+  h->n = n;
+  const int ncol = ilu_colour_host(n, nnz, rp.data(), ci.data(), h->colour);
   h->ncol = ncol;
   h->coff.assign(ncol + 1, 0);
   for (int64_t i = 0; i < n; ++i) h->coff[h->colour[i] + 1] += 1;

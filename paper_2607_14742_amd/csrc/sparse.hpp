@@ -108,6 +108,9 @@ struct RbOp {
 // Z = (L U)^{-1} X for k columns (X, Z distinct, vector precision of op).
 struct IluHost;
 std::shared_ptr<IluHost> ilu_analyse(Ctx* ctx, const care_csr* A);
+// The colouring alone, on a host CSR pattern (validated here): colour[i] for
+// every row, returns the number of colours.
+int ilu_colour_host(int64_t n, int64_t nnz, const int* rp, const int* ci, std::vector<int>& colour);
 void ilu_attach(Ctx* ctx, const std::shared_ptr<IluHost>& h, SellOp& op);
 struct IluOp {
   int ncol = 0;
