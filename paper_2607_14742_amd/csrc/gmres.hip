@@ -23,8 +23,12 @@ namespace mpcare {
 
 namespace {
 
-constexpr int GM_ROWS = 8;                 // rows per thread in the dot kernel
-constexpr int GM_CHUNK = 256 * GM_ROWS;    // rows per block
+// rows per thread in the dot kernel (measured on the 500 x 500 problem's
+// paper-setting solves: 8 is fastest in FP32, 4 in FP64) and rows per block
+template <typename T>
+constexpr int gm_rows() { return sizeof(T) == 8 ? 4 : 8; }
+template <typename T>
+constexpr int gm_chunk() { return 256 * gm_rows<T>(); }
 
 // part[(c Jo + i) nb + blk] = sum over the block's rows of V_i[row, c] w[row, c]
 // for i < J (V_i = V + i bstride) and, with self = 1, i = J: the block's part
@@ -42,11 +46,12 @@ __global__ void __launch_bounds__(256) k_gm_multidot(int64_t n, int J, int self,
   const int Jo = J + self;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const bool on = active[c] != 0;
+  constexpr int GM_ROWS = gm_rows<T>();
   double wv[GM_ROWS];
   int64_t rows[GM_ROWS];
 #pragma unroll
   for (int u = 0; u < GM_ROWS; ++u) {
-    rows[u] = (int64_t)blk * GM_CHUNK + u * 256 + threadIdx.x;
+    rows[u] = (int64_t)blk * gm_chunk<T>() + u * 256 + threadIdx.x;
     wv[u] = (on && rows[u] < n) ? (double)w[(int64_t)c * ldw + rows[u]] : 0.0;
   }
   for (int i = 0; i < Jo; ++i) {
@@ -119,7 +124,7 @@ KrylovResult gmres(Ctx* ctx, const SellOp& op, double pr, int ncols, const T* b,
   const int64_t n = op.n, ld = pad_ld(n);
   const int k = ncols;
   const int m = std::min(1000, std::max(1, restart));   // LDS of the dot kernel: (m + 1) x 4 doubles
-  const int nb = (int)ceil_div(n, (int64_t)GM_CHUNK);
+  const int nb = (int)ceil_div(n, (int64_t)gm_chunk<T>());
   const int64_t bstride = ld * k;
   DBuf<T> V(ctx, (size_t)bstride * (m + 1)), w(ctx, (size_t)bstride);
   DBuf<double> part(ctx, (size_t)nb * k * (m + 1)), hdev(ctx, (size_t)k * (m + 1)), sdev(ctx, (size_t)k);
