@@ -1,5 +1,6 @@
 """Restarted GMRES as the inner solver (option krylov_method = 1; the solver
-family of Sec. 5, without the paper's ILU(0) preconditioner): CARE solves
+family of Sec. 5, here without the ILU(0) preconditioner, which
+tests/test_gpu_ilu.py covers): CARE solves
 against dense Schur solutions and against the BiCGStab path, and the
 fallback to BiCGStab for complex shift pairs."""
 import numpy as np
