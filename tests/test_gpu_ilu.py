@@ -240,3 +240,29 @@ def test_ilu_gmres_with_complex_pairs_keeps_bicgstab_for_them(pk, ctx):
     rel = lowrank.residual_norm(P.A, P.B, P.C, Z.cpu().numpy()) / np.linalg.norm(P.C @ P.C.T)
     print(f"3D complex pair with ILU-GMRES: relres {rel:.2e}", flush=True)
     assert rel <= 1e-11
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+@pytest.mark.parametrize("rb", [0, 1])
+def test_ilu_gmres_shifted_solve_at_full_size(pk, ctx, prec, tol, rb):
+    """The paper's inner solver at the benchmark's size (the 500 x 500 FDM
+    operator, n = 250,000, with the SMW feedback, m = 5) against the oracle's
+    sparse direct solve of the same shifted system, for a middle shift of the
+    benchmark's Wachspress set."""
+    P = wl.config2()
+    A = P.A
+    n = A.shape[0]
+    p = float(np.real(P.shifts[len(P.shifts) // 2]))
+    rng = np.random.default_rng(77)
+    B = rng.standard_normal((n, 5))
+    K = 1e-3 * rng.standard_normal((n, 5))
+    W = rng.standard_normal((n, 4))
+    print(f"full-size ILU-GMRES shifted solve {prec} rb={rb} p={p:.3e}", flush=True)
+    opts = pk.default_opts(prec, krylov_method=1, krylov_rb=rb, krylov_precond=1)
+    V, info = pk.shifted_solve(ctx, pk.DeviceCSR.from_scipy(A), dev(W), p, B=dev(B), K=dev(K), prec=prec, tol=tol,
+                               opts=opts)
+    ref = adi.ShiftedSolver(A, B, K).solve(p, W)
+    err = np.linalg.norm(V.cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"  error {err:.2e}, Arnoldi steps {info['iters']}", flush=True)
+    assert info["status"] == 0
+    assert err <= 30.0 * tol
