@@ -266,3 +266,38 @@ def test_ilu_gmres_shifted_solve_at_full_size(pk, ctx, prec, tol, rb):
     print(f"  error {err:.2e}, Arnoldi steps {info['iters']}", flush=True)
     assert info["status"] == 0
     assert err <= 30.0 * tol
+
+
+def test_shifted_solve_opts_null_equals_the_plain_entry_point(pk, ctx):
+    """care_shifted_solve_opts with opts = NULL is care_shifted_solve (same
+    BiCGStab arithmetic, same result bit for bit)."""
+    A = wl.fdm2d(20)
+    n = A.shape[0]
+    rng = np.random.default_rng(5)
+    W = pk.api.colmajor(dev(rng.standard_normal((n, 3))))      # the ABI's column-major layout
+    Ad = pk.DeviceCSR.from_scipy(A)
+    V0, _ = pk.shifted_solve(ctx, Ad, W, -40.0, prec="fp64", tol=1e-10)
+    V1 = pk.api.empty_colmajor(n, 3, W.device)
+    assert pk.api._ld(W) == n and pk.api._ld(V1) == n and pk.api._ld(V0) == n
+    it = C.c_int32(0)
+    lib = pk.load()
+    st = lib.care_shifted_solve_opts(ctx.h, Ad.c, None, n, None, n, 0, pk.api._shift(-40.0), C.c_void_p(W.data_ptr()),
+                                     n, 3, pk.CARE_FP64, 1e-10, 0, None, C.c_void_p(V1.data_ptr()), n,
+                                     C.byref(it))
+    assert st == 0
+    torch.cuda.synchronize()
+    assert torch.equal(V0, V1)
+
+
+def test_gmres_restart_beyond_the_cap_is_clamped(pk, ctx):
+    """A restart length above 1000 runs as 1000 (the dot kernel's LDS bound)
+    and still solves to the tolerance."""
+    A = wl.fdm2d(24)
+    n = A.shape[0]
+    rng = np.random.default_rng(6)
+    W = rng.standard_normal((n, 2))
+    opts = pk.default_opts("fp64", krylov_method=1, krylov_rb=0, krylov_precond=1, krylov_restart=5000)
+    V, info = pk.shifted_solve(ctx, pk.DeviceCSR.from_scipy(A), dev(W), -60.0, prec="fp64", tol=1e-10, opts=opts)
+    ref = adi.ShiftedSolver(A).solve(-60.0, W)
+    assert info["status"] == 0
+    assert np.linalg.norm(V.cpu().numpy() - ref) / np.linalg.norm(ref) <= 3e-9
